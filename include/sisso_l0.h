@@ -1,0 +1,173 @@
+/*
+ * sisso_l0.h -- C ABI of an MI355X (gfx950) library for the l0 step of SISSO.
+ *
+ * The operation (paper, section "l0-regularization"): given the m features
+ * that sure-independence screening selected and a target property, score
+ * every D-tuple of features by a least-squares fit of the target and keep the
+ * best.  The paper scores by the mean squared deviation; here tuples are
+ * ranked by the sum of squared errors (SSE), which orders them identically
+ * for a fixed problem (MSD = SSE / n_total).  Each task of a multi-task
+ * problem (section "Test Cases": one descriptor, coefficients per task) has
+ * its own intercept and coefficients, and a tuple's SSE is the sum over tasks.
+ *
+ * Call sequence:  sisso_l0_workspace_bytes -> sisso_l0_create -> sisso_gram
+ *                 -> sisso_l0_search (any number of times, any D <= D_max)
+ *                 -> sisso_l0_topk -> sisso_l0_destroy.
+ *
+ * Conventions
+ *  - Every function returns SISSO_OK (0) or a negative SISSO_E* code; no
+ *    exception crosses the ABI.  sisso_l0_last_error(h) gives a message.
+ *  - Device pointers are HIP device memory owned by the caller.  The library
+ *    never allocates device memory: it carves everything it needs out of the
+ *    caller's workspace, which must stay alive until sisso_l0_destroy.
+ *  - All device work is enqueued on desc.stream (a hipStream_t; NULL = the
+ *    default stream) and is asynchronous, except sisso_l0_topk, which
+ *    synchronises that stream.  Calls on one handle must not overlap in time
+ *    from several host threads.
+ *  - Results are deterministic: they do not depend on launch configuration,
+ *    scheduling or the order in which the GPU visits tuples.
+ */
+#ifndef SISSO_L0_H
+#define SISSO_L0_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sisso_l0 sisso_l0; /* opaque handle, owned by the library */
+
+enum {
+    SISSO_OK = 0,
+    SISSO_EINVAL = -1,  /* bad argument (null pointer, size, index, non-finite input) */
+    SISSO_ESTATE = -2,  /* call out of order (search before gram, topk before search) */
+    SISSO_ENOMEM = -3,  /* caller's workspace smaller than sisso_l0_workspace_bytes */
+    SISSO_EDEVICE = -4, /* a HIP runtime call failed; see sisso_l0_last_error */
+    SISSO_ENOTSUP = -5  /* supported but not in this build (e.g. D > SISSO_MAX_D) */
+};
+
+enum {
+    SISSO_PREC_FP64 = 0 /* Gram, fits and scores in FP64 */
+};
+
+#define SISSO_MAX_D 4      /* largest descriptor dimension compiled in */
+#define SISSO_MAX_T 64     /* largest number of tasks */
+#define SISSO_MAX_K 496    /* largest top-k */
+
+typedef struct {
+    /* F: device, n_total x S, column-major ("feature-major"): sample i of
+     * feature j is F[j * n_total + i].  Must be finite. */
+    const double *F;
+    /* y: device, n_total target values, rows in the same order as F. */
+    const double *y;
+    /* task_offsets: HOST array of T+1 nondecreasing row offsets with
+     * task_offsets[0] = 0 and task_offsets[T] = n_total; task t owns rows
+     * [task_offsets[t], task_offsets[t+1]).  Copied at create. */
+    const int64_t *task_offsets;
+    int64_t n_total;  /* rows (samples) */
+    int64_t S;        /* features (columns) */
+    int32_t T;        /* tasks, 1..SISSO_MAX_T */
+    int32_t D_max;    /* largest D that will be searched, 1..SISSO_MAX_D */
+    int32_t k_max;    /* largest k that will be requested, 1..SISSO_MAX_K */
+    int32_t precision;/* SISSO_PREC_* */
+    void *workspace;  /* device, >= sisso_l0_workspace_bytes(desc) bytes, 256-B aligned */
+    size_t workspace_bytes;
+    void *stream;     /* hipStream_t on which all work is enqueued */
+} sisso_l0_desc;
+
+/* Device bytes the caller must provide in desc->workspace for this problem
+ * shape (pure function of n_total, S, T, D_max, k_max; reads no pointer).
+ * Returns 0 if the shape is invalid. */
+size_t sisso_l0_workspace_bytes(const sisso_l0_desc *desc);
+
+/* Validate the descriptor and create a handle in *out.  Errors: EINVAL for
+ * null pointers, S < 1, T outside 1..SISSO_MAX_T, offsets not covering
+ * [0, n_total) in order, D_max/k_max out of range; ENOMEM if the workspace is
+ * too small; ENOTSUP for an unknown precision; EDEVICE if the device cannot
+ * be queried.  *out is set only on success. */
+int32_t sisso_l0_create(const sisso_l0_desc *desc, sisso_l0 **out);
+
+/* Enqueue the per-task statistics and the Gram precompute: column means,
+ * centred cross-products F_t^T F_t (as a correlation matrix), F_t^T y_t and
+ * |y_t - mean|^2 for every task.  This replaces the per-tuple assembly of the
+ * descriptor matrix: every least-squares system of the search is a
+ * sub-matrix of these products.  Non-finite entries of F or y are detected
+ * here and reported (EINVAL) by the next sisso_l0_topk. */
+int32_t sisso_gram(sisso_l0 *h);
+
+/* Enqueue an exhaustive search over all C(S, D) tuples and keep the k best by
+ * (SSE ascending, lexicographic rank ascending).  Rank-deficient tuples (a
+ * feature whose 1 - R^2 on the intercept and the earlier features of the
+ * tuple is <= 1e-10 in some task) are never returned.  Errors: ESTATE before
+ * sisso_gram; ENOTSUP for D > D_max or D > SISSO_MAX_D; EINVAL for D < 1,
+ * S < D, k < 1, k > k_max, k > C(S, D), or a task with fewer than D + 2 rows. */
+int32_t sisso_l0_search(sisso_l0 *h, int32_t D, int32_t k);
+
+/* As sisso_l0_search, restricted to tuples whose lexicographic rank r
+ * (0-based, among all C(S, D) tuples of sorted indices) satisfies
+ * r0 <= r < r1.  Disjoint ranges merged by (SSE, rank) give the full search,
+ * which makes the search resumable and splittable.  EINVAL if r0 >= r1 or
+ * r1 > C(S, D). */
+int32_t sisso_l0_search_range(sisso_l0 *h, int32_t D, int32_t k, uint64_t r0, uint64_t r1);
+
+/* Synchronise the stream and copy the result of the last search to HOST
+ * buffers: idx (k*D int32, row-major, ascending indices within a row), sse
+ * (k doubles, SSE summed over tasks) and, unless NULL, coef (k*T*(D+1)
+ * doubles: for result r and task t, coef[(r*T + t)*(D+1)] is the intercept
+ * and the next D entries the coefficients of the tuple's features, in the
+ * units of F and y).  Rows beyond the number of full-rank tuples are filled
+ * with idx -1, sse +inf, coef NaN.  Errors: ESTATE before a search or for k
+ * above the searched k; EINVAL for null idx/sse or non-finite input data. */
+int32_t sisso_l0_topk(sisso_l0 *h, int32_t k, int32_t *idx, double *sse, double *coef);
+
+/* Synchronise the stream and copy task t's precomputed statistics to HOST
+ * buffers (any may be NULL): G (S*S doubles, row-major) the correlation
+ * matrix of the task's centred columns, G[i][j] = x_ic.x_jc / (|x_ic||x_jc|)
+ * with a unit diagonal (0 on the diagonal of a constant column); b (S
+ * doubles) b_j = x_jc.y_c / |x_jc|; c (1 double) |y_c|^2, where x_c, y_c are
+ * the task's columns minus their means.  ESTATE before sisso_gram, EINVAL for
+ * t out of range. */
+int32_t sisso_gram_read(sisso_l0 *h, int32_t t, double *G, double *b, double *c);
+
+/* Number of tuples the last search scored (C(S, D), or r1 - r0 for a range
+ * search), for throughput accounting.  Host-only. */
+uint64_t sisso_l0_scored(const sisso_l0 *h);
+
+/* Per-phase timing with HIP events recorded on the handle's stream.
+ * sisso_l0_profile(h, 1) turns it on (0 off; off by default).  After a
+ * sisso_gram / sisso_l0_search, sisso_l0_phase_ms fills ms[SISSO_NPHASE]
+ * (milliseconds of the last run of each phase; 0 if it has not run) and
+ * synchronises the stream.  Phases: statistics, Gram, threshold pre-pass,
+ * search kernel, merge, exact re-score, final ordering. */
+#define SISSO_NPHASE 7
+enum {
+    SISSO_PHASE_STATS = 0,
+    SISSO_PHASE_GRAM = 1,
+    SISSO_PHASE_PREPASS = 2,
+    SISSO_PHASE_SEARCH = 3,
+    SISSO_PHASE_MERGE = 4,
+    SISSO_PHASE_RESCORE = 5,
+    SISSO_PHASE_FINAL = 6
+};
+int32_t sisso_l0_profile(sisso_l0 *h, int32_t enable);
+int32_t sisso_l0_phase_ms(sisso_l0 *h, double *ms);
+
+/* Release the handle (NULL-safe).  Does not free caller memory. */
+void sisso_l0_destroy(sisso_l0 *h);
+
+/* Message for the last error on h ("" if none); valid until the next call on
+ * h.  With h == NULL, the message of the last failed sisso_l0_create. */
+const char *sisso_l0_last_error(const sisso_l0 *h);
+
+/* Lexicographic rank <-> tuple (combinatorial number system), host side.
+ * rank_of returns UINT64_MAX for an invalid tuple; unrank returns EINVAL for
+ * r >= C(S, D). */
+uint64_t sisso_l0_rank_of(int64_t S, int32_t D, const int32_t *tuple);
+int32_t sisso_l0_unrank(int64_t S, int32_t D, uint64_t r, int32_t *tuple);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SISSO_L0_H */

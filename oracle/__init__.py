@@ -124,3 +124,10 @@ def all_sse(F, y, D: int, offsets=None) -> np.ndarray:
 
 def max_d() -> int:
     return int(_load().oracle_max_d())
+
+
+def threads() -> int:
+    """OpenMP threads the oracle uses by default."""
+    lib = _load()
+    lib.oracle_threads.restype = ctypes.c_int
+    return int(lib.oracle_threads())

@@ -370,3 +370,13 @@ int64_t oracle_all_sse(const double *F, const double *y, const int64_t *off, int
 }
 
 int oracle_max_d(void) { return ORACLE_MAX_D; }
+
+/* Threads an OpenMP region of the oracle uses by default. */
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

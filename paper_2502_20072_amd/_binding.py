@@ -1,0 +1,212 @@
+"""ctypes binding of libsisso_l0.so -- argument marshalling only.
+
+Each function mirrors the C entry point of the same name in
+``include/sisso_l0.h``.  Device memory (inputs and the workspace) comes from
+torch; every step of the computation runs in the library's HIP kernels.  If
+the shared library is missing the import of a function fails loudly: there
+is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsisso_l0.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "sisso_l0.h")
+
+SISSO_OK, SISSO_EINVAL, SISSO_ESTATE, SISSO_ENOMEM, SISSO_EDEVICE, SISSO_ENOTSUP = 0, -1, -2, -3, -4, -5
+SISSO_PREC_FP64 = 0
+
+
+def _header_int(name: str) -> int:
+    with open(HEADER) as f:
+        m = re.search(r"#define\s+%s\s+(\d+)" % name, f.read())
+    return int(m.group(1))
+
+
+SISSO_MAX_D = _header_int("SISSO_MAX_D")
+SISSO_MAX_T = _header_int("SISSO_MAX_T")
+SISSO_MAX_K = _header_int("SISSO_MAX_K")
+
+
+class SissoError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class sisso_l0_desc(ctypes.Structure):
+    _fields_ = [
+        ("F", ctypes.c_void_p),
+        ("y", ctypes.c_void_p),
+        ("task_offsets", ctypes.POINTER(ctypes.c_int64)),
+        ("n_total", ctypes.c_int64),
+        ("S", ctypes.c_int64),
+        ("T", ctypes.c_int32),
+        ("D_max", ctypes.c_int32),
+        ("k_max", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("workspace", ctypes.c_void_p),
+        ("workspace_bytes", ctypes.c_size_t),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def load():
+    """Load the in-tree shared library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                           "(the GPU path has no fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    h = ctypes.c_void_p
+    lib.sisso_l0_workspace_bytes.argtypes = [P(sisso_l0_desc)]
+    lib.sisso_l0_workspace_bytes.restype = ctypes.c_size_t
+    lib.sisso_l0_create.argtypes = [P(sisso_l0_desc), P(h)]
+    lib.sisso_l0_create.restype = ctypes.c_int32
+    lib.sisso_gram.argtypes = [h]
+    lib.sisso_gram.restype = ctypes.c_int32
+    lib.sisso_l0_search.argtypes = [h, ctypes.c_int32, ctypes.c_int32]
+    lib.sisso_l0_search.restype = ctypes.c_int32
+    lib.sisso_l0_search_range.argtypes = [h, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint64]
+    lib.sisso_l0_search_range.restype = ctypes.c_int32
+    lib.sisso_l0_topk.argtypes = [h, ctypes.c_int32, P(ctypes.c_int32), P(ctypes.c_double), P(ctypes.c_double)]
+    lib.sisso_l0_topk.restype = ctypes.c_int32
+    lib.sisso_gram_read.argtypes = [h, ctypes.c_int32, P(ctypes.c_double), P(ctypes.c_double),
+                                    P(ctypes.c_double)]
+    lib.sisso_gram_read.restype = ctypes.c_int32
+    lib.sisso_l0_scored.argtypes = [h]
+    lib.sisso_l0_scored.restype = ctypes.c_uint64
+    lib.sisso_l0_destroy.argtypes = [h]
+    lib.sisso_l0_destroy.restype = None
+    lib.sisso_l0_last_error.argtypes = [h]
+    lib.sisso_l0_last_error.restype = ctypes.c_char_p
+    lib.sisso_l0_rank_of.argtypes = [ctypes.c_int64, ctypes.c_int32, P(ctypes.c_int32)]
+    lib.sisso_l0_rank_of.restype = ctypes.c_uint64
+    lib.sisso_l0_unrank.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64, P(ctypes.c_int32)]
+    lib.sisso_l0_unrank.restype = ctypes.c_int32
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, handle=None):
+    if rc != SISSO_OK:
+        msg = load().sisso_l0_last_error(handle)
+        raise SissoError(rc, (msg or b"").decode())
+
+
+# ------------------------------------------------------------ thin wrappers
+def make_desc(F_ptr: int, y_ptr: int, offsets: np.ndarray, n_total: int, S: int, D_max: int,
+              k_max: int, workspace_ptr: int = 0, workspace_bytes: int = 0, stream: int = 0,
+              precision: int = SISSO_PREC_FP64) -> sisso_l0_desc:
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    d = sisso_l0_desc()
+    d.F = F_ptr
+    d.y = y_ptr
+    d._offsets_keepalive = offsets
+    d.task_offsets = offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    d.n_total = n_total
+    d.S = S
+    d.T = len(offsets) - 1
+    d.D_max = D_max
+    d.k_max = k_max
+    d.precision = precision
+    d.workspace = workspace_ptr
+    d.workspace_bytes = workspace_bytes
+    d.stream = stream
+    return d
+
+
+def sisso_l0_workspace_bytes(desc: sisso_l0_desc) -> int:
+    return int(load().sisso_l0_workspace_bytes(ctypes.byref(desc)))
+
+
+def sisso_l0_create(desc: sisso_l0_desc) -> int:
+    out = ctypes.c_void_p()
+    _check(load().sisso_l0_create(ctypes.byref(desc), ctypes.byref(out)), None)
+    return out.value
+
+
+def sisso_gram(h: int) -> None:
+    _check(load().sisso_gram(h), h)
+
+
+def sisso_l0_search(h: int, D: int, k: int) -> None:
+    _check(load().sisso_l0_search(h, D, k), h)
+
+
+def sisso_l0_search_range(h: int, D: int, k: int, r0: int, r1: int) -> None:
+    _check(load().sisso_l0_search_range(h, D, k, r0, r1), h)
+
+
+def sisso_l0_topk(h: int, k: int, D: int, T: int, with_coef: bool = True):
+    idx = np.full((k, D), -1, dtype=np.int32)
+    sse = np.full(k, np.inf)
+    coef = np.full((k, T, D + 1), np.nan) if with_coef else None
+    P = ctypes.POINTER
+    _check(load().sisso_l0_topk(h, k, idx.ctypes.data_as(P(ctypes.c_int32)),
+                                sse.ctypes.data_as(P(ctypes.c_double)),
+                                coef.ctypes.data_as(P(ctypes.c_double)) if with_coef else None), h)
+    return idx, sse, coef
+
+
+def sisso_gram_read(h: int, t: int, S: int):
+    G = np.empty((S, S))
+    b = np.empty(S)
+    c = np.empty(1)
+    P = ctypes.POINTER(ctypes.c_double)
+    _check(load().sisso_gram_read(h, t, G.ctypes.data_as(P), b.ctypes.data_as(P), c.ctypes.data_as(P)), h)
+    return G, b, float(c[0])
+
+
+def sisso_l0_scored(h: int) -> int:
+    return int(load().sisso_l0_scored(h))
+
+
+def sisso_l0_destroy(h: Optional[int]) -> None:
+    load().sisso_l0_destroy(h)
+
+
+def sisso_l0_last_error(h: Optional[int]) -> str:
+    return (load().sisso_l0_last_error(h) or b"").decode()
+
+
+def sisso_l0_rank_of(S: int, tup: Sequence[int]) -> int:
+    t = np.ascontiguousarray(tup, dtype=np.int32)
+    return int(load().sisso_l0_rank_of(S, len(t), t.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+
+
+def sisso_l0_unrank(S: int, D: int, r: int):
+    t = np.zeros(D, dtype=np.int32)
+    _check(load().sisso_l0_unrank(S, D, r, t.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+    return tuple(int(v) for v in t)
+
+
+PHASES = ("stats", "gram", "prepass", "search", "merge", "rescore", "final")
+
+
+def sisso_l0_profile(h: int, enable: bool) -> None:
+    lib = load()
+    lib.sisso_l0_profile.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+    lib.sisso_l0_profile.restype = ctypes.c_int32
+    _check(lib.sisso_l0_profile(h, 1 if enable else 0), h)
+
+
+def sisso_l0_phase_ms(h: int) -> dict:
+    lib = load()
+    lib.sisso_l0_phase_ms.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]
+    lib.sisso_l0_phase_ms.restype = ctypes.c_int32
+    ms = np.zeros(len(PHASES))
+    _check(lib.sisso_l0_phase_ms(h, ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), h)
+    return dict(zip(PHASES, ms.tolist()))

@@ -1,0 +1,330 @@
+// C ABI of the gfx950 l0 library: argument checks, workspace carving and the
+// order of launches.  All arithmetic happens in the kernels.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "kernels.h"
+
+using namespace sl0;
+
+struct sisso_l0 {
+    sisso_l0_desc desc;
+    std::vector<int64_t> offsets;
+    Layout lay;
+    Ctx ctx;
+    hipStream_t stream;
+    bool gram_done = false;
+    bool search_done = false;
+    int last_D = 0, last_k = 0;
+    uint64_t scored = 0;
+    std::string err;
+    hipEvent_t ev[2 * SISSO_NPHASE] = {};
+    bool ran[SISSO_NPHASE] = {};
+    bool prof = false;
+    ~sisso_l0() {
+        for (auto &e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+
+static thread_local std::string g_create_err;
+
+static int32_t fail(sisso_l0 *h, int32_t code, const char *msg) {
+    if (h) h->err = msg;
+    else g_create_err = msg;
+    return code;
+}
+
+static Layout compute_layout(int64_t n_total, int64_t S, int T, int D_max, int k_max) {
+    Layout L{};
+    L.TP = next_pow2(T);
+    const int64_t ntile = (S + GRAM_TILE - 1) / GRAM_TILE;
+    const int64_t blocks = ntile * (ntile + 1) / 2 * T;
+    // split the rows so the Gram launch has >= ~512 workgroups, keeping at
+    // least 256 rows per split
+    const int64_t maxrows = n_total;
+    int64_t ns = (512 + blocks - 1) / blocks;
+    const int64_t byrows = maxrows / 256 > 1 ? maxrows / 256 : 1;
+    if (ns > byrows) ns = byrows;
+    if (ns > 16) ns = 16;
+    if (ns < 1) ns = 1;
+    L.nsplit = (int)ns;
+    L.KP = next_pow2(k_max + 16);
+    if (L.KP < 64) L.KP = 64;
+    L.search_wgs = 1024;
+    L.nwaves = L.search_wgs * SEARCH_WAVES;
+    const int64_t nlists = L.nwaves;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align256(o + bytes);
+        return at;
+    };
+    const size_t d = sizeof(double);
+    L.off_dev = take((T + 1) * sizeof(int64_t));
+    L.ybar = take(T * d);
+    L.cyy = take(T * d);
+    L.mu = take((size_t)T * S * d);
+    L.inv_s = take((size_t)T * S * d);
+    L.bhat = take((size_t)S * L.TP * d);
+    L.G = take((size_t)S * S * L.TP * d);
+    L.part = take((size_t)L.nsplit * T * S * S * d);
+    L.flags = take(64 * sizeof(uint32_t));
+    // pre-pass + counters: theta, work counter, cand counter, cum table, prefixes, scores
+    L.pre = take(64 + (size_t)(S / 4 + 8) * sizeof(uint64_t) + PRE_Q * SISSO_MAX_D * sizeof(int32_t) +
+                 64 + (size_t)PRE_Q * S * d + PRE_Q * d + 1024 +
+                 (size_t)(SISSO_MAX_D + 1) * (S + 1) * sizeof(uint64_t) + 256);
+    L.lists = take((size_t)nlists * L.KP * 2 * d + (size_t)nlists * (sizeof(int32_t) + sizeof(int64_t)) +
+                   (size_t)nlists * L.KP * 2 * d);
+    L.merged = take((size_t)L.KP * 2 * d);
+    L.rescored = take((size_t)L.KP * d);
+    L.coef = take((size_t)L.KP * T * (D_max + 1) * d);
+    L.res_idx = take((size_t)k_max * D_max * sizeof(int32_t));
+    L.res_sse = take((size_t)k_max * d);
+    L.res_coef = take((size_t)k_max * T * (D_max + 1) * d);
+    L.total = o;
+    return L;
+}
+
+static bool shape_ok(const sisso_l0_desc *d) {
+    return d && d->n_total >= 1 && d->S >= 1 && d->T >= 1 && d->T <= SISSO_MAX_T && d->D_max >= 1 &&
+           d->D_max <= SISSO_MAX_D && d->k_max >= 1 && d->k_max <= SISSO_MAX_K && d->S < (1 << 30);
+}
+
+extern "C" size_t sisso_l0_workspace_bytes(const sisso_l0_desc *d) {
+    if (!shape_ok(d)) return 0;
+    return compute_layout(d->n_total, d->S, d->T, d->D_max, d->k_max).total + 256;
+}
+
+static void carve(sisso_l0 *h) {
+    const Layout &L = h->lay;
+    char *base = (char *)h->desc.workspace;
+    Ctx &c = h->ctx;
+    c = Ctx{};
+    c.F = h->desc.F;
+    c.y = h->desc.y;
+    c.n_total = h->desc.n_total;
+    c.S = h->desc.S;
+    c.T = h->desc.T;
+    c.TP = L.TP;
+    c.off_dev = (int64_t *)(base + L.off_dev);
+    c.ybar = (double *)(base + L.ybar);
+    c.cyy = (double *)(base + L.cyy);
+    c.mu = (double *)(base + L.mu);
+    c.inv_s = (double *)(base + L.inv_s);
+    c.bhat = (double *)(base + L.bhat);
+    c.G = (double *)(base + L.G);
+    c.part = (double *)(base + L.part);
+    c.flags = (uint32_t *)(base + L.flags);
+    char *p = base + L.pre;
+    c.theta_bits = (unsigned long long *)p;
+    c.work_counter = (unsigned int *)(p + 8);
+    c.cand_counter = (unsigned int *)(p + 12);
+    c.pre_count = (int32_t *)(p + 16);
+    p += 64;
+    c.cum = (uint64_t *)p;
+    p += (size_t)(c.S / 4 + 8) * sizeof(uint64_t);
+    c.pre_prefix = (int32_t *)p;
+    p += align256(PRE_Q * SISSO_MAX_D * sizeof(int32_t));
+    c.pre_bound = (double *)p;
+    p += align256(PRE_Q * sizeof(double));
+    c.pre_sse = (double *)p;
+    p += align256((size_t)PRE_Q * c.S * sizeof(double));
+    c.btab = (uint64_t *)p;
+    const int64_t nl = L.nwaves;
+    char *q = base + L.lists;
+    c.list_sse = (double *)q;
+    q += (size_t)nl * L.KP * sizeof(double);
+    c.list_rank = (uint64_t *)q;
+    q += (size_t)nl * L.KP * sizeof(uint64_t);
+    c.list_count = (int32_t *)q;
+    q += (size_t)nl * sizeof(int32_t);
+    q = (char *)(((uintptr_t)q + 255) & ~(uintptr_t)255);
+    c.list_offset = (int64_t *)q;
+    q += (size_t)nl * sizeof(int64_t);
+    q = (char *)(((uintptr_t)q + 255) & ~(uintptr_t)255);
+    c.cand_sse = (double *)q;
+    q += (size_t)nl * L.KP * sizeof(double);
+    c.cand_rank = (uint64_t *)q;
+    c.merged_sse = (double *)(base + L.merged);
+    c.merged_rank = (uint64_t *)(base + L.merged + (size_t)L.KP * sizeof(double));
+    c.resc_sse = (double *)(base + L.rescored);
+    c.resc_coef = (double *)(base + L.coef);
+    c.res_idx = (int32_t *)(base + L.res_idx);
+    c.res_sse = (double *)(base + L.res_sse);
+    c.res_coef = (double *)(base + L.res_coef);
+    c.nsplit = L.nsplit;
+    c.KP = L.KP;
+    c.nwaves = L.nwaves;
+    c.search_wgs = L.search_wgs;
+    c.D_max = h->desc.D_max;
+    c.k_max = h->desc.k_max;
+    c.ev = h->prof ? h->ev : nullptr;
+}
+
+extern "C" int32_t sisso_l0_create(const sisso_l0_desc *d, sisso_l0 **out) {
+    if (!d || !out) return fail(nullptr, SISSO_EINVAL, "null descriptor or output pointer");
+    if (!d->F || !d->y || !d->task_offsets || !d->workspace)
+        return fail(nullptr, SISSO_EINVAL, "null F, y, task_offsets or workspace");
+    if (!shape_ok(d)) return fail(nullptr, SISSO_EINVAL, "shape out of range (n_total, S, T, D_max, k_max)");
+    if (d->precision != SISSO_PREC_FP64) return fail(nullptr, SISSO_ENOTSUP, "unknown precision mode");
+    const int64_t *o = d->task_offsets;
+    if (o[0] != 0 || o[d->T] != d->n_total) return fail(nullptr, SISSO_EINVAL, "task offsets must span [0, n_total)");
+    for (int t = 0; t < d->T; ++t)
+        if (o[t + 1] <= o[t]) return fail(nullptr, SISSO_EINVAL, "every task needs at least one row");
+    if (((uintptr_t)d->workspace & 255) != 0) return fail(nullptr, SISSO_EINVAL, "workspace must be 256-byte aligned");
+    const size_t need = sisso_l0_workspace_bytes(d);
+    if (d->workspace_bytes < need) return fail(nullptr, SISSO_ENOMEM, "workspace smaller than sisso_l0_workspace_bytes");
+    sisso_l0 *h = new (std::nothrow) sisso_l0();
+    if (!h) return fail(nullptr, SISSO_ENOMEM, "host allocation failed");
+    h->desc = *d;
+    h->offsets.assign(o, o + d->T + 1);
+    h->desc.task_offsets = h->offsets.data();
+    h->lay = compute_layout(d->n_total, d->S, d->T, d->D_max, d->k_max);
+    h->stream = (hipStream_t)d->stream;
+    carve(h);
+    if (hipMemcpyAsync(h->ctx.off_dev, h->offsets.data(), (d->T + 1) * sizeof(int64_t), hipMemcpyHostToDevice,
+                       h->stream) != hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess) {
+        delete h;
+        return fail(nullptr, SISSO_EDEVICE, "could not initialise the workspace on the device");
+    }
+    *out = h;
+    return SISSO_OK;
+}
+
+extern "C" int32_t sisso_gram(sisso_l0 *h) {
+    if (!h) return SISSO_EINVAL;
+    h->err.clear();
+    if (launch_stats(h->ctx, h->stream) || launch_gram(h->ctx, h->stream))
+        return fail(h, SISSO_EDEVICE, hipGetErrorString(hipGetLastError()));
+    h->ran[SISSO_PHASE_STATS] = h->ran[SISSO_PHASE_GRAM] = h->prof;
+    h->gram_done = true;
+    h->search_done = false;
+    return SISSO_OK;
+}
+
+static int32_t do_search(sisso_l0 *h, int32_t D, int32_t k, bool ranged, uint64_t r0, uint64_t r1) {
+    if (!h) return SISSO_EINVAL;
+    h->err.clear();
+    if (!h->gram_done) return fail(h, SISSO_ESTATE, "sisso_gram must run before a search");
+    if (D > h->desc.D_max || D > SISSO_MAX_D) return fail(h, SISSO_ENOTSUP, "D exceeds D_max");
+    if (D < 1 || D > h->desc.S) return fail(h, SISSO_EINVAL, "need 1 <= D <= S");
+    if (k < 1 || k > h->desc.k_max) return fail(h, SISSO_EINVAL, "need 1 <= k <= k_max");
+    const uint64_t total = binom(h->desc.S, D);
+    if (total >= (1ull << 63)) return fail(h, SISSO_ENOTSUP, "C(S, D) does not fit the 63-bit rank space");
+    if (ranged) {
+        if (r0 >= r1 || r1 > total) return fail(h, SISSO_EINVAL, "need r0 < r1 <= C(S, D)");
+        if ((uint64_t)k > r1 - r0) return fail(h, SISSO_EINVAL, "k exceeds the number of tuples in the range");
+    } else if ((uint64_t)k > total) {
+        return fail(h, SISSO_EINVAL, "k exceeds C(S, D)");
+    }
+    for (int t = 0; t < h->desc.T; ++t)
+        if (h->offsets[t + 1] - h->offsets[t] < D + 2) return fail(h, SISSO_EINVAL, "a task has fewer than D + 2 rows");
+    SearchCall sc{D, k, ranged ? 1 : 0, ranged ? r0 : 0, ranged ? r1 : total};
+    if (launch_search(h->ctx, sc, h->stream)) return fail(h, SISSO_EDEVICE, hipGetErrorString(hipGetLastError()));
+    for (int ph = SISSO_PHASE_PREPASS; ph <= SISSO_PHASE_FINAL; ++ph) h->ran[ph] = h->prof;
+    h->search_done = true;
+    h->last_D = D;
+    h->last_k = k;
+    h->scored = ranged ? r1 - r0 : total;
+    return SISSO_OK;
+}
+
+extern "C" int32_t sisso_l0_search(sisso_l0 *h, int32_t D, int32_t k) { return do_search(h, D, k, false, 0, 0); }
+
+extern "C" int32_t sisso_l0_search_range(sisso_l0 *h, int32_t D, int32_t k, uint64_t r0, uint64_t r1) {
+    return do_search(h, D, k, true, r0, r1);
+}
+
+extern "C" int32_t sisso_l0_topk(sisso_l0 *h, int32_t k, int32_t *idx, double *sse, double *coef) {
+    if (!h) return SISSO_EINVAL;
+    h->err.clear();
+    if (!h->search_done) return fail(h, SISSO_ESTATE, "no search has run");
+    if (k < 1 || k > h->last_k) return fail(h, SISSO_ESTATE, "k exceeds the searched k");
+    if (!idx || !sse) return fail(h, SISSO_EINVAL, "null idx or sse");
+    const int D = h->last_D, T = h->desc.T;
+    uint32_t flags[4] = {0, 0, 0, 0};
+    hipError_t e = hipMemcpyAsync(idx, h->ctx.res_idx, (size_t)k * D * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(sse, h->ctx.res_sse, (size_t)k * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess && coef)
+        e = hipMemcpyAsync(coef, h->ctx.res_coef, (size_t)k * T * (D + 1) * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(flags, h->ctx.flags, sizeof(flags), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return fail(h, SISSO_EDEVICE, hipGetErrorString(e));
+    if (flags[FLAG_NONFINITE]) return fail(h, SISSO_EINVAL, "F or y holds a non-finite value");
+    return SISSO_OK;
+}
+
+extern "C" int32_t sisso_gram_read(sisso_l0 *h, int32_t t, double *G, double *b, double *c) {
+    if (!h) return SISSO_EINVAL;
+    h->err.clear();
+    if (!h->gram_done) return fail(h, SISSO_ESTATE, "sisso_gram has not run");
+    if (t < 0 || t >= h->desc.T) return fail(h, SISSO_EINVAL, "task index out of range");
+    const size_t S = (size_t)h->desc.S, TP = (size_t)h->ctx.TP, d = sizeof(double);
+    hipError_t e = hipSuccess;
+    // device layouts are task-fastest: a strided copy picks task t
+    if (G) e = hipMemcpy2DAsync(G, d, h->ctx.G + t, TP * d, d, S * S, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess && b) e = hipMemcpy2DAsync(b, d, h->ctx.bhat + t, TP * d, d, S, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess && c) e = hipMemcpyAsync(c, h->ctx.cyy + t, d, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return fail(h, SISSO_EDEVICE, hipGetErrorString(e));
+    return SISSO_OK;
+}
+
+extern "C" uint64_t sisso_l0_scored(const sisso_l0 *h) { return h ? h->scored : 0; }
+
+extern "C" int32_t sisso_l0_profile(sisso_l0 *h, int32_t enable) {
+    if (!h) return SISSO_EINVAL;
+    h->err.clear();
+    if (enable && !h->ev[0]) {
+        for (auto &e : h->ev)
+            if (hipEventCreate(&e) != hipSuccess) return fail(h, SISSO_EDEVICE, "hipEventCreate failed");
+    }
+    h->prof = enable != 0;
+    h->ctx.ev = h->prof ? h->ev : nullptr;
+    for (auto &r : h->ran) r = false;
+    return SISSO_OK;
+}
+
+extern "C" int32_t sisso_l0_phase_ms(sisso_l0 *h, double *ms) {
+    if (!h || !ms) return SISSO_EINVAL;
+    h->err.clear();
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return fail(h, SISSO_EDEVICE, "stream synchronisation failed");
+    for (int ph = 0; ph < SISSO_NPHASE; ++ph) {
+        ms[ph] = 0.0;
+        if (!h->ran[ph]) continue;
+        float f = 0.f;
+        if (hipEventElapsedTime(&f, h->ev[2 * ph], h->ev[2 * ph + 1]) != hipSuccess)
+            return fail(h, SISSO_EDEVICE, "hipEventElapsedTime failed");
+        ms[ph] = f;
+    }
+    return SISSO_OK;
+}
+
+extern "C" void sisso_l0_destroy(sisso_l0 *h) { delete h; }
+
+extern "C" const char *sisso_l0_last_error(const sisso_l0 *h) {
+    return h ? h->err.c_str() : g_create_err.c_str();
+}
+
+extern "C" uint64_t sisso_l0_rank_of(int64_t S, int32_t D, const int32_t *t) {
+    if (!t || D < 1 || D > 8 || S < D) return UINT64_MAX;
+    for (int m = 0; m < D; ++m) {
+        if (t[m] < 0 || t[m] >= S) return UINT64_MAX;
+        if (m > 0 && t[m] <= t[m - 1]) return UINT64_MAX;
+    }
+    return lex_rank(BinomCalc{}, S, D, t);
+}
+
+extern "C" int32_t sisso_l0_unrank(int64_t S, int32_t D, uint64_t r, int32_t *t) {
+    if (!t || D < 1 || D > 8 || S < D || r >= binom(S, D)) return SISSO_EINVAL;
+    lex_unrank(BinomCalc{}, S, D, r, t);
+    return SISSO_OK;
+}

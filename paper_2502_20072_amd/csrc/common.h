@@ -1,0 +1,163 @@
+// Shared definitions of the gfx950 l0 library: workspace layout, launch
+// parameters, and host/device helpers for the combinatorial number system.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/sisso_l0.h"
+
+namespace sl0 {
+
+constexpr int WAVE = 64;               // CDNA wavefront width
+constexpr double RANK_EPS = 1e-10;     // pivot ratio at or below which a tuple is rank-deficient
+constexpr int GRAM_TILE = 128;         // Gram output tile (rows = cols)
+constexpr int GRAM_KC = 16;            // samples per LDS stage of the Gram
+constexpr int SEARCH_WG = 256;         // threads per search workgroup (4 waves)
+constexpr int SEARCH_WAVES = SEARCH_WG / WAVE;
+constexpr int JBLK = 64;               // (D-1)-th indices per search work item (one per lane)
+constexpr int SUBP = 4;                // sub-prefixes sharing one Gram load (single task)
+constexpr int PRE_M = 16;              // features the threshold pre-pass starts from
+constexpr int PRE_Q = 8;               // best prefixes the pre-pass extends by every feature
+constexpr int KP_MAX = 512;            // longest per-wave candidate list
+
+// ---------------------------------------------------------------- binomials
+// C(n, r) exactly in 64-bit arithmetic, saturating at UINT64_MAX (never
+// reached for accepted sizes, which keep C(S, D) < 2^63).  Multiplicative
+// formula c <- c (n - r + i) / i with the division done first: with
+// g = gcd(c, i), i/g divides n - r + i, so no intermediate exceeds the result.
+__host__ __device__ inline uint64_t gcd_u64(uint64_t a, uint64_t b) {
+    while (b) {
+        const uint64_t t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+__host__ __device__ inline uint64_t binom(int64_t n, int r) {
+    if (r < 0 || n < r) return 0;
+    if (r == 0) return 1;
+    if (r > n - r) r = (int)(n - r);
+    uint64_t c = 1;
+    for (int i = 1; i <= r; ++i) {
+        const uint64_t g = gcd_u64(c, (uint64_t)i);
+        const uint64_t m = (uint64_t)(n - r + i) / ((uint64_t)i / g);
+        c /= g;
+        if (c > UINT64_MAX / m) return UINT64_MAX;
+        c *= m;
+    }
+    return c;
+}
+
+// Binomials from a table tab[r * (S + 1) + n], r <= SISSO_MAX_D, n <= S,
+// filled on the device once per search (lookups replace the arithmetic in
+// kernels); the host uses binom() directly.
+struct BinomTab {
+    const uint64_t *tab;
+    int64_t S;
+    __host__ __device__ uint64_t operator()(int64_t n, int r) const {
+        return (r < 0 || n < r) ? 0 : tab[(int64_t)r * (S + 1) + n];
+    }
+};
+struct BinomCalc {
+    __host__ __device__ uint64_t operator()(int64_t n, int r) const { return binom(n, r); }
+};
+
+// Lexicographic rank of a sorted tuple (i_1 < ... < i_D) of {0..S-1}:
+// tuples with a smaller first index come first, then by the second, etc.
+// rank = sum_m [C(S - i_{m-1} - 1, D - m + 1) - C(S - i_m, D - m + 1)], i_0 = -1
+// (the hockey-stick sum of the tuples skipped at position m).
+template <class BF>
+__host__ __device__ inline uint64_t lex_rank(const BF &bf, int64_t S, int D, const int32_t *t) {
+    uint64_t r = 0;
+    int64_t prev = -1;
+    for (int m = 1; m <= D; ++m) {
+        int64_t im = t[m - 1];
+        r += bf(S - prev - 1, D - m + 1) - bf(S - im, D - m + 1);
+        prev = im;
+    }
+    return r;
+}
+
+// Inverse of lex_rank: position by position, the m-th index is the largest
+// x with count(x) <= r, where count(x) = C(S - prev - 1, k) - C(S - x, k)
+// (k = D - m + 1) counts the tuples whose m-th index lies in (prev, x);
+// found by bisection on that monotone count.
+template <class BF>
+__host__ __device__ inline void lex_unrank(const BF &bf, int64_t S, int D, uint64_t r, int32_t *t) {
+    int64_t prev = -1;
+    for (int m = 1; m <= D; ++m) {
+        const int k = D - m + 1;
+        const uint64_t base = bf(S - prev - 1, k);
+        int64_t lo = prev + 1, hi = S - k;  // answer in [lo, hi]
+        while (lo < hi) {
+            int64_t mid = (lo + hi + 1) / 2;
+            uint64_t before = base - bf(S - mid, k);
+            if (before <= r) lo = mid; else hi = mid - 1;
+        }
+        r -= base - bf(S - lo, k);
+        t[m - 1] = (int32_t)lo;
+        prev = lo;
+    }
+}
+
+// Colexicographic unranking of a q-combination of {0..N-1}: the q-th element
+// is the largest c with C(c, q) <= r, then recurse on r - C(c, q).  Used to
+// hand out groups of sub-prefixes: colex ranks below C(N, q) are exactly the
+// combinations inside {0..N-1}.
+template <class BF>
+__host__ __device__ inline void colex_unrank(const BF &bf, uint64_t r, int q, int64_t N, int32_t *t) {
+    int64_t hi = N - 1;
+    for (int m = q; m >= 1; --m) {
+        int64_t lo = m - 1, h = hi;  // largest c in [m-1, hi] with C(c, m) <= r
+        while (lo < h) {
+            int64_t mid = (lo + h + 1) / 2;
+            if (bf(mid, m) <= r) lo = mid; else h = mid - 1;
+        }
+        t[m - 1] = (int32_t)lo;
+        r -= bf(lo, m);
+        hi = lo - 1;
+    }
+}
+
+// -------------------------------------------------------- workspace layout
+// Every region is 256-byte aligned; offsets in bytes from the workspace base.
+struct Layout {
+    size_t off_dev;    // int64 [T+1]
+    size_t ybar;       // double [T]
+    size_t cyy;        // double [T]   |y_t - ybar_t|^2
+    size_t mu;         // double [T][S] column means per task
+    size_t inv_s;      // double [T][S] 1/|x - mean| (0 for a constant column)
+    size_t bhat;       // double [S][TP] normalised F_t^T y_t
+    size_t G;          // double [S][S][TP] correlation matrices, task fastest
+    size_t part;       // double [nsplit][T][S][S] raw centred Gram partial sums
+    size_t flags;      // uint32 [64] device status words
+    size_t pre;        // pre-pass scratch
+    size_t lists;      // per-wave top lists: (double sse, uint64 rank) [nwaves][KP]
+    size_t merged;     // merged candidates [KP] (sse, rank)
+    size_t rescored;   // rescored candidates [KP] (sse, rank)
+    size_t coef;       // double [KP][T][D_max+1]
+    size_t res_idx;    // int32 [k_max][D_max]
+    size_t res_sse;    // double [k_max]
+    size_t res_coef;   // double [k_max][T][D_max+1]
+    size_t total;
+    int TP;            // tasks padded to a power of two
+    int nsplit;        // split-K factor of the Gram
+    int KP;            // list length per wave (power of two >= k_max + margin)
+    int nwaves;        // persistent search waves
+    int search_wgs;    // persistent search workgroups
+};
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+inline int next_pow2(int x) {
+    int p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+// device status flag indices
+enum { FLAG_NONFINITE = 0, FLAG_WORK = 1, FLAG_CAND = 2, FLAG_THETA = 4 /* uint64 at 4..5 */ };
+
+}  // namespace sl0

@@ -1,0 +1,274 @@
+// Per-task column statistics and the centred Gram precompute (FP64 MFMA).
+//
+// Every least-squares system the l0 step solves is the normal-equation
+// system of [1, x_i1, ..., x_iD] against y on the rows of one task.
+// Eliminating the intercept first leaves the centred cross-products, so all
+// systems are sub-matrices of G_t = X_tc^T X_tc, b_t = X_tc^T y_tc and
+// c_t = |y_tc|^2 (X_tc: columns of task t minus their means).  These are
+// computed once here; the search never touches F again.  G_t is stored as a
+// correlation matrix (scaled by 1/|x_i - mean| on both sides, unit diagonal),
+// which leaves every SSE unchanged and makes pivot ratios plain pivots.
+#include "common.h"
+#include "kernels.h"
+
+namespace sl0 {
+
+// ---------------------------------------------------------------- a0: stats
+// One wavefront per (feature j or the target, task t).  Sums run over the
+// task's rows with a fixed lane-strided order and a fixed butterfly, so the
+// result does not depend on scheduling.
+__device__ inline double wave_sum(double v) {
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__global__ __launch_bounds__(256) void stats_y_kernel(const double *__restrict__ y,
+                                                      const int64_t *__restrict__ off, int T,
+                                                      double *__restrict__ ybar,
+                                                      double *__restrict__ cyy,
+                                                      uint32_t *__restrict__ flags) {
+    const int lane = threadIdx.x & 63;
+    const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (t >= T) return;
+    const int64_t r0 = off[t], r1 = off[t + 1];
+    double s = 0.0;
+    bool bad = false;
+    for (int64_t i = r0 + lane; i < r1; i += 64) {
+        double v = y[i];
+        bad |= !isfinite(v);
+        s += v;
+    }
+    s = wave_sum(s);
+    const double m = s / (double)(r1 - r0);
+    double ss = 0.0;
+    for (int64_t i = r0 + lane; i < r1; i += 64) {
+        double d = y[i] - m;
+        ss += d * d;
+    }
+    ss = wave_sum(ss);
+    if (__any(bad) && lane == 0) atomicOr(&flags[FLAG_NONFINITE], 1u);
+    if (lane == 0) {
+        ybar[t] = m;
+        cyy[t] = ss;
+    }
+}
+
+__global__ __launch_bounds__(256) void stats_x_kernel(const double *__restrict__ F,
+                                                      const double *__restrict__ y,
+                                                      const int64_t *__restrict__ off,
+                                                      int64_t n_total, int64_t S, int T, int TP,
+                                                      const double *__restrict__ ybar,
+                                                      double *__restrict__ mu,
+                                                      double *__restrict__ inv_s,
+                                                      double *__restrict__ bhat,
+                                                      uint32_t *__restrict__ flags) {
+    const int lane = threadIdx.x & 63;
+    const int64_t job = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (job >= S * T) return;
+    const int64_t j = job / T;
+    const int t = (int)(job % T);
+    const int64_t r0 = off[t], r1 = off[t + 1];
+    const double *col = F + j * n_total;
+    double s = 0.0;
+    bool bad = false;
+    for (int64_t i = r0 + lane; i < r1; i += 64) {
+        double v = col[i];
+        bad |= !isfinite(v);
+        s += v;
+    }
+    s = wave_sum(s);
+    const double m = s / (double)(r1 - r0);
+    const double ym = ybar[t];
+    double ss = 0.0, sy = 0.0;
+    for (int64_t i = r0 + lane; i < r1; i += 64) {
+        double d = col[i] - m;
+        ss += d * d;
+        sy += d * (y[i] - ym);
+    }
+    ss = wave_sum(ss);
+    sy = wave_sum(sy);
+    if (__any(bad) && lane == 0) atomicOr(&flags[FLAG_NONFINITE], 1u);
+    if (lane == 0) {
+        const double is = (ss > 0.0 && isfinite(ss)) ? 1.0 / sqrt(ss) : 0.0;
+        mu[(int64_t)t * S + j] = m;
+        inv_s[(int64_t)t * S + j] = is;
+        bhat[j * TP + t] = sy * is;
+    }
+}
+
+// ------------------------------------------------------- a1: Gram on MFMA
+// One workgroup (4 waves) computes a GRAM_TILE x GRAM_TILE block (bi <= bj)
+// of the centred Gram of one task over one split of its rows; each wave owns
+// a 64x64 quarter as 4x4 MFMA 16x16 accumulators.  Samples are staged through
+// LDS in chunks of GRAM_KC, centred on load (x - mean).
+//
+// v_mfma_f64_16x16x4f64 operand layout: A[i][k] in lane i + 16k, B[k][j] in
+// lane j + 16k, result D[i][j] in lane j + 16*(i%4), register i/4.
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+constexpr int LDS_STRIDE = GRAM_TILE + 16;  // 144 doubles: rows k, k+1 land on opposite bank halves
+
+__global__ __launch_bounds__(256) void gram_kernel(const double *__restrict__ F, int64_t n_total,
+                                                   int64_t S, const int64_t *__restrict__ off,
+                                                   int T, const double *__restrict__ mu,
+                                                   int ntile, int nsplit,
+                                                   double *__restrict__ part) {
+    __shared__ double As[GRAM_KC][LDS_STRIDE];
+    __shared__ double Bs[GRAM_KC][LDS_STRIDE];
+
+    // blockIdx.x -> (split, task, tile pair) ; tile pairs enumerate bi <= bj row by row
+    int64_t b = blockIdx.x;
+    const int npair = ntile * (ntile + 1) / 2;
+    const int split = (int)(b / ((int64_t)T * npair));
+    b -= (int64_t)split * T * npair;
+    const int t = (int)(b / npair);
+    int pr = (int)(b - (int64_t)t * npair);
+    int bi = 0;
+    while (pr >= ntile - bi) {
+        pr -= ntile - bi;
+        ++bi;
+    }
+    const int bj = bi + pr;
+
+    const int64_t r0 = off[t], r1 = off[t + 1];
+    const int64_t nchunk = (r1 - r0 + GRAM_KC - 1) / GRAM_KC;
+    const int64_t per = (nchunk + nsplit - 1) / nsplit;
+    const int64_t c0 = (int64_t)split * per;
+    const int64_t c1 = c0 + per < nchunk ? c0 + per : nchunk;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wr = (wave >> 1) * 64;  // wave's row offset inside the tile
+    const int wc = (wave & 1) * 64;   // wave's column offset
+    const double *mut = mu + (int64_t)t * S;
+
+    double4_t acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] = (double4_t){0.0, 0.0, 0.0, 0.0};
+
+    // loader mapping: kk = tid % KC (consecutive samples), feature = tid / KC + 16 r
+    const int kk = tid % GRAM_KC;
+    const int f0 = tid / GRAM_KC;
+    double muA[GRAM_TILE / 16], muB[GRAM_TILE / 16];
+#pragma unroll
+    for (int r = 0; r < GRAM_TILE / 16; ++r) {
+        const int64_t ga = (int64_t)bi * GRAM_TILE + f0 + 16 * r;
+        const int64_t gb = (int64_t)bj * GRAM_TILE + f0 + 16 * r;
+        muA[r] = ga < S ? mut[ga] : 0.0;
+        muB[r] = gb < S ? mut[gb] : 0.0;
+    }
+
+    for (int64_t c = c0; c < c1; ++c) {
+        const int64_t row = r0 + c * GRAM_KC + kk;
+        const bool rin = row < r1;
+#pragma unroll
+        for (int r = 0; r < GRAM_TILE / 16; ++r) {
+            const int f = f0 + 16 * r;
+            const int64_t ga = (int64_t)bi * GRAM_TILE + f;
+            const int64_t gb = (int64_t)bj * GRAM_TILE + f;
+            As[kk][f] = (rin && ga < S) ? F[ga * n_total + row] - muA[r] : 0.0;
+            Bs[kk][f] = (rin && gb < S) ? F[gb * n_total + row] - muB[r] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < GRAM_KC / 4; ++ks) {
+            const int krow = ks * 4 + (lane >> 4);
+            double a[4], bv[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) a[m] = As[krow][wr + m * 16 + (lane & 15)];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) bv[m] = Bs[krow][wc + m * 16 + (lane & 15)];
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int n = 0; n < 4; ++n)
+                    acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], bv[n], acc[m][n], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+
+    // store the raw block into part[split][t][i][j]
+    double *P = part + ((int64_t)split * T + t) * S * S;
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int n = 0; n < 4; ++n)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t gi = (int64_t)bi * GRAM_TILE + wr + m * 16 + (lane >> 4) + 4 * r;
+                const int64_t gj = (int64_t)bj * GRAM_TILE + wc + n * 16 + (lane & 15);
+                if (gi < S && gj < S) P[gi * S + gj] = acc[m][n][r];
+            }
+}
+
+// Sum the split partials of the upper triangle, scale to a correlation
+// matrix and write both triangles into G[i][k][t] (task fastest).  The
+// diagonal is exactly 1 for a non-constant column and 0 for a constant one.
+__global__ __launch_bounds__(256) void gram_finish_kernel(const double *__restrict__ part,
+                                                          int64_t S, int T, int TP, int nsplit,
+                                                          const double *__restrict__ inv_s,
+                                                          double *__restrict__ G) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= S * S * TP) return;
+    const int t = (int)(e % TP);
+    const int64_t ik = e / TP;
+    const int64_t i = ik / S, k = ik % S;
+    double v = 0.0;
+    if (t < T) {
+        const double si = inv_s[(int64_t)t * S + i], sk = inv_s[(int64_t)t * S + k];
+        if (i == k) {
+            v = si > 0.0 ? 1.0 : 0.0;
+        } else {
+            // canonical element: the tile pair (bi <= bj) that holds it, upper
+            // triangle of a diagonal tile
+            const int64_t bi = i / GRAM_TILE, bk = k / GRAM_TILE;
+            int64_t a = i, c = k;
+            if (bi > bk || (bi == bk && i > k)) {
+                a = k;
+                c = i;
+            }
+            double s = 0.0;
+            for (int sp = 0; sp < nsplit; ++sp) s += part[(((int64_t)sp * T + t) * S + a) * S + c];
+            // scale in canonical (a, c) order so G[i][k] and G[k][i] are bitwise equal
+            v = s * (inv_s[(int64_t)t * S + a] * inv_s[(int64_t)t * S + c]);
+            (void)si;
+            (void)sk;
+        }
+    }
+    G[e] = v;
+}
+
+// ------------------------------------------------------------- launchers
+__global__ void clear_flags_kernel(uint32_t *flags) {
+    if (threadIdx.x < 64) flags[threadIdx.x] = 0u;
+}
+
+int launch_stats(const Ctx &c, hipStream_t st) {
+    phase_begin(c, SISSO_PHASE_STATS, st);
+    hipLaunchKernelGGL(clear_flags_kernel, dim3(1), dim3(64), 0, st, c.flags);
+    hipLaunchKernelGGL(stats_y_kernel, dim3((c.T + 3) / 4), dim3(256), 0, st, c.y, c.off_dev, c.T,
+                       c.ybar, c.cyy, c.flags);
+    const int64_t jobs = c.S * c.T;
+    hipLaunchKernelGGL(stats_x_kernel, dim3((unsigned)((jobs + 3) / 4)), dim3(256), 0, st, c.F, c.y,
+                       c.off_dev, c.n_total, c.S, c.T, c.TP, c.ybar, c.mu, c.inv_s, c.bhat, c.flags);
+    phase_end(c, SISSO_PHASE_STATS, st);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_gram(const Ctx &c, hipStream_t st) {
+    const int ntile = (int)((c.S + GRAM_TILE - 1) / GRAM_TILE);
+    const int64_t blocks = (int64_t)c.nsplit * c.T * ntile * (ntile + 1) / 2;
+    phase_begin(c, SISSO_PHASE_GRAM, st);
+    hipLaunchKernelGGL(gram_kernel, dim3((unsigned)blocks), dim3(256), 0, st, c.F, c.n_total, c.S,
+                       c.off_dev, c.T, c.mu, ntile, c.nsplit, c.part);
+    const int64_t elems = c.S * c.S * c.TP;
+    hipLaunchKernelGGL(gram_finish_kernel, dim3((unsigned)((elems + 255) / 256)), dim3(256), 0, st,
+                       c.part, c.S, c.T, c.TP, c.nsplit, c.inv_s, c.G);
+    phase_end(c, SISSO_PHASE_GRAM, st);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace sl0

@@ -1,0 +1,63 @@
+// Device-pointer view of a handle's workspace and the kernel launchers.
+#pragma once
+
+#include "common.h"
+
+namespace sl0 {
+
+struct Ctx {
+    // problem (caller memory)
+    const double *F;
+    const double *y;
+    int64_t n_total, S;
+    int T, TP;
+    // carved from the workspace
+    int64_t *off_dev;
+    double *ybar, *cyy, *mu, *inv_s, *bhat, *G, *part;
+    uint32_t *flags;
+    unsigned long long *theta_bits;  // shared SSE bound (bit pattern of a non-negative double)
+    unsigned int *work_counter;      // next search work item
+    unsigned int *cand_counter;      // slow-path candidates seen (diagnostics)
+    uint64_t *cum;                   // cumulative work items per j-block [S/JBLK + 2]
+    uint64_t *btab;                  // binomials C(n, r), r <= SISSO_MAX_D, n <= S
+    int32_t *pre_prefix;             // pre-pass: chosen prefixes [PRE_Q][SISSO_MAX_D]
+    int32_t *pre_count;              // pre-pass: number of chosen prefixes
+    double *pre_sse;                 // pre-pass: extension scores [PRE_Q][S]
+    double *pre_bound;               // pre-pass: per-prefix L-th best [PRE_Q]
+    double *list_sse;                // per-wave lists [nwaves][KP]
+    uint64_t *list_rank;
+    int32_t *list_count;             // merge: entries <= bound per list [nwaves]
+    int64_t *list_offset;            // merge: exclusive scan of list_count [nwaves + 1]
+    double *cand_sse;                // merge: compacted candidates [nwaves * KP]
+    uint64_t *cand_rank;
+    double *merged_sse;              // [KP]
+    uint64_t *merged_rank;
+    double *resc_sse;                // rescored [KP]
+    double *resc_coef;               // [KP][T][D_max+1]
+    int32_t *res_idx;                // final [k_max][D_max]
+    double *res_sse;                 // [k_max]
+    double *res_coef;                // [k_max][T][D_max+1]
+    int nsplit, KP, nwaves, search_wgs, D_max, k_max;
+    // host-side: start/stop events per phase when profiling is on (else null)
+    hipEvent_t *ev;
+};
+
+inline void phase_begin(const Ctx &c, int ph, hipStream_t st) {
+    if (c.ev) (void)hipEventRecord(c.ev[2 * ph], st);
+}
+inline void phase_end(const Ctx &c, int ph, hipStream_t st) {
+    if (c.ev) (void)hipEventRecord(c.ev[2 * ph + 1], st);
+}
+
+// search parameters of one call
+struct SearchCall {
+    int D, k;
+    int ranged;
+    uint64_t r0, r1;
+};
+
+int launch_stats(const Ctx &c, hipStream_t st);
+int launch_gram(const Ctx &c, hipStream_t st);
+int launch_search(const Ctx &c, const SearchCall &sc, hipStream_t st);
+
+}  // namespace sl0

@@ -1,0 +1,1126 @@
+// Exhaustive l0 search on gfx950: every D-tuple of the S features is scored
+// by the SSE of its least-squares fit (intercept per task), and the k best
+// by (SSE, lexicographic rank) are kept.
+//
+// The paper factorises each tuple's n x (D+1) descriptor matrix with
+// Householder QR, one GPU thread per tuple.  Here the fits come from the
+// correlation matrices G_t, b_t, c_t that the Gram step precomputed: for a
+// tuple T = (P, k) with prefix P,
+//     w = R_P^{-1} G[P,k],  d = 1 - |w|^2,  zeta = b_k - w.z_P,
+//     SSE_t(T) = p_P - zeta^2 / d       (p_P = c_t - |z_P|^2 = SSE_t(P)),
+// with R_P the Cholesky factor of G[P,P] and z_P = R_P^{-1} b_P.  d is the
+// pivot of k (1 - R^2 of x_k on the intercept and P), which is also the
+// rank test.  For a single task the comparison SSE <= theta needs no
+// division: zeta^2 >= (p_P - theta) d.
+//
+// Work decomposition.  A tuple is (P', j, k): a sub-prefix P' of D-2
+// indices, the (D-1)-th index j and the last index k.  A work item is a
+// block of 64 consecutive j values together with a group of sub-prefixes
+// (SUBP of them for one task, one when lanes are split over tasks).  The
+// workgroup builds the Cholesky row of every (P', j) pair of the item in
+// parallel (one thread each) into LDS; then each wave sweeps chunks of 64
+// consecutive k (one per lane), keeps the k-dependent part of the
+// sub-prefix solve in registers, and for every j loads one G[j][k] that
+// serves all sub-prefixes of the item.  Items are handed out through an
+// atomic counter in order of increasing j, i.e. largest first; sub-prefix
+// groups are addressed by colexicographic rank (combinatorial number
+// system), so item -> (j-block, sub-prefixes) is a bisection, not a table.
+//
+// Top-k.  Each wave keeps a sorted list of the KP best (SSE, rank) pairs in
+// LDS; insertions happen only for tuples that pass the current bound, which
+// is the minimum of a pre-pass bound theta0 (see pre_*), the wave's own
+// KP-th entry and a device-wide bound that full lists publish with an
+// atomic min.  Any list's KP-th entry bounds the global KP-th best, so the
+// filter never drops a tuple of the global top-KP.  A merge kernel gathers
+// the entries under the final bound, and every survivor is re-scored from F
+// itself (explicit residuals in FP64), which fixes the reported SSE to the
+// accuracy of a direct least-squares fit, before the final ordering.
+#include <math.h>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace sl0 {
+
+constexpr int MAXD = SISSO_MAX_D;
+constexpr double INF = __builtin_huge_val();
+constexpr double THETA_SLACK = 1e-9;  // relative slack of the filter bound
+
+__device__ inline bool key_less(double s1, uint64_t r1, double s2, uint64_t r2) {
+    return s1 < s2 || (s1 == s2 && r1 < r2);
+}
+
+__device__ inline double theta_load(const unsigned long long *p) {
+    unsigned long long b = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __longlong_as_double((long long)b);
+}
+
+__device__ inline void theta_publish(unsigned long long *p, double v) {
+    // non-negative doubles order like their bit patterns
+    if (v >= 0.0 && v < INF) atomicMin(p, (unsigned long long)__double_as_longlong(v));
+}
+
+__device__ inline double Gat(const Ctx &c, int64_t i, int64_t k, int t) {
+    return c.G[(i * c.S + k) * c.TP + t];
+}
+
+// ----------------------------------------------------------------- helpers
+// Normal-equation SSE of one sorted tuple summed over tasks, from the
+// correlation matrices (Cholesky in increasing index order).  +inf when a
+// pivot is <= RANK_EPS in some task.  Used by the threshold pre-pass.
+__device__ double ne_sse(const Ctx &c, int D, const int32_t *tup) {
+    double total = 0.0;
+    for (int t = 0; t < c.T; ++t) {
+        double L[MAXD][MAXD], z[MAXD];
+        double p = c.cyy[t];
+        for (int m = 0; m < D; ++m) {
+            for (int j = 0; j < m; ++j) {
+                double s = Gat(c, tup[m], tup[j], t);
+                for (int l = 0; l < j; ++l) s -= L[m][l] * L[j][l];
+                L[m][j] = s / L[j][j];
+            }
+            double d = Gat(c, tup[m], tup[m], t);
+            for (int l = 0; l < m; ++l) d -= L[m][l] * L[m][l];
+            if (!(d > RANK_EPS)) return INF;
+            L[m][m] = sqrt(d);
+            double zm = c.bhat[(int64_t)tup[m] * c.TP + t];
+            for (int l = 0; l < m; ++l) zm -= L[m][l] * z[l];
+            z[m] = zm / L[m][m];
+            p -= z[m] * z[m];
+        }
+        total += p;
+    }
+    return total;
+}
+
+// Sorted per-wave list in LDS: entries e = lane + 64 m, m < KP/64.
+__device__ void list_insert(double *Ls, uint64_t *Lr, int KP, double s, uint64_t r) {
+    const int lane = threadIdx.x & 63;
+    const int nper = KP >> 6;
+    int pos = 0;
+    for (int m = 0; m < nper; ++m) {
+        const int e = lane + 64 * m;
+        pos += __popcll(__ballot(key_less(Ls[e], Lr[e], s, r)));
+    }
+    if (pos >= KP) return;
+    double vs[KP_MAX / 64];
+    uint64_t vr[KP_MAX / 64];
+#pragma unroll
+    for (int m = 0; m < KP_MAX / 64; ++m) {
+        const int e = lane + 64 * m;
+        if (m < nper && e > pos) {
+            vs[m] = Ls[e - 1];
+            vr[m] = Lr[e - 1];
+        }
+    }
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int m = 0; m < KP_MAX / 64; ++m) {
+        const int e = lane + 64 * m;
+        if (m < nper && e > pos) {
+            Ls[e] = vs[m];
+            Lr[e] = vr[m];
+        }
+    }
+    if (lane == 0) {
+        Ls[pos] = s;
+        Lr[pos] = r;
+    }
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_wave_barrier();
+}
+
+// ------------------------------------------------------------ init kernel
+// Resets the per-search device state and tabulates the cumulative number
+// of work items per j-block: block jb covers j in [JB*jb, N_jb) with
+// N_jb = min(JB*(jb+1), S-1); its sub-prefixes are the q-combinations of
+// {0..N_jb-2}, grouped R at a time.
+__global__ void search_init_kernel(Ctx c, int D, int R, int JB) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < (int64_t)(SISSO_MAX_D + 1) * (c.S + 1)) {
+        const int r = (int)(e / (c.S + 1));
+        const int64_t n = e % (c.S + 1);
+        c.btab[e] = binom(n, r);
+    }
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        *c.work_counter = 0;
+        *c.cand_counter = 0;
+        *c.theta_bits = (unsigned long long)__double_as_longlong(INF);
+        *c.pre_count = 0;
+        const int q = D - 2;
+        const int64_t nblk = (c.S - 1 + JB - 1) / JB;
+        uint64_t acc = 0;
+        c.cum[0] = 0;
+        for (int64_t b = 0; b < nblk; ++b) {
+            int64_t N = JB * (b + 1);
+            if (N > c.S - 1) N = c.S - 1;
+            const uint64_t nsub = q >= 0 ? binom(N - 1, q) : 0;
+            acc += (nsub + R - 1) / R;
+            c.cum[b + 1] = acc;
+        }
+    }
+}
+
+// ----------------------------------------------------- threshold pre-pass
+// pre_select: the PRE_M features with the largest sum over tasks of b_t^2
+// (their D=1 explained sums of squares), every (D-1)-subset of them scored,
+// and the PRE_Q best subsets kept as prefixes.
+__global__ __launch_bounds__(256) void pre_select_kernel(Ctx c, int D) {
+    __shared__ double rel[256];
+    __shared__ int32_t ridx[256];
+    __shared__ int32_t sel[PRE_M];
+    __shared__ double psse[1024];
+    __shared__ int32_t pidx[1024];
+    __shared__ int nsel;
+    const int tid = threadIdx.x;
+    const int q = D - 1;
+    if (tid == 0) nsel = 0;
+    __syncthreads();
+    // top-PRE_M by relevance (ties: smaller index), repeated block argmax
+    for (int it = 0; it < PRE_M; ++it) {
+        double best = -1.0;
+        int bidx = -1;
+        for (int64_t j = tid; j < c.S; j += 256) {
+            bool taken = false;
+            for (int s = 0; s < it; ++s) taken |= (sel[s] == j);
+            if (taken) continue;
+            double r = 0.0;
+            bool ok = true;
+            for (int t = 0; t < c.T; ++t) {
+                ok &= Gat(c, j, j, t) == 1.0;
+                const double b = c.bhat[j * c.TP + t];
+                r += b * b;
+            }
+            if (!ok) continue;
+            if (r > best) {
+                best = r;
+                bidx = (int)j;
+            }
+        }
+        rel[tid] = best;
+        ridx[tid] = bidx;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if (tid < o) {
+                const double a = rel[tid], b = rel[tid + o];
+                const int ia = ridx[tid], ib = ridx[tid + o];
+                if (b > a || (b == a && ib >= 0 && (ia < 0 || ib < ia))) {
+                    rel[tid] = b;
+                    ridx[tid] = ib;
+                }
+            }
+            __syncthreads();
+        }
+        if (tid == 0) {
+            if (ridx[0] >= 0) sel[nsel++] = ridx[0];
+        }
+        __syncthreads();
+        if (nsel <= it) break;
+        __syncthreads();
+    }
+    const int M = nsel;
+    if (M < q) return;
+    // sort the selected features by index (tiny insertion sort by one thread)
+    if (tid == 0) {
+        for (int a = 1; a < M; ++a) {
+            int v = sel[a], b = a - 1;
+            while (b >= 0 && sel[b] > v) {
+                sel[b + 1] = sel[b];
+                --b;
+            }
+            sel[b + 1] = v;
+        }
+    }
+    __syncthreads();
+    // score every q-subset of the selection
+    const uint64_t nsub = binom(M, q);
+    for (uint64_t s = tid; s < 1024; s += 256) {
+        psse[s] = INF;
+        pidx[s] = -1;
+    }
+    __syncthreads();
+    for (uint64_t s = tid; s < nsub && s < 1024; s += 256) {
+        int32_t loc[MAXD], tup[MAXD];
+        colex_unrank(BinomTab{c.btab, c.S}, s, q, M, loc);
+        for (int m = 0; m < q; ++m) tup[m] = sel[loc[m]];
+        psse[s] = ne_sse(c, q, tup);
+        pidx[s] = (int)s;
+    }
+    __syncthreads();
+    // keep the PRE_Q best (SSE, then subset rank), repeated block argmin
+    for (int it = 0; it < PRE_Q; ++it) {
+        double best = INF;
+        int bi = -1;
+        for (int s = tid; s < 1024; s += 256) {
+            if (pidx[s] >= 0 && (psse[s] < best || (psse[s] == best && bi >= 0 && pidx[s] < bi))) {
+                best = psse[s];
+                bi = pidx[s];
+            }
+        }
+        rel[tid] = best;
+        ridx[tid] = bi;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if (tid < o) {
+                const double a = rel[tid], b = rel[tid + o];
+                const int ia = ridx[tid], ib = ridx[tid + o];
+                if (ib >= 0 && (ia < 0 || b < a || (b == a && ib < ia))) {
+                    rel[tid] = b;
+                    ridx[tid] = ib;
+                }
+            }
+            __syncthreads();
+        }
+        const int win = ridx[0];
+        const double wsse = rel[0];
+        __syncthreads();
+        if (win < 0 || !(wsse < INF)) break;
+        if (tid == 0) {
+            int32_t loc[MAXD];
+            colex_unrank(BinomTab{c.btab, c.S}, (uint64_t)win, q, M, loc);
+            for (int m = 0; m < q; ++m) c.pre_prefix[it * MAXD + m] = sel[loc[m]];
+            *c.pre_count = it + 1;
+            pidx[win] = -1;
+        }
+        __syncthreads();
+    }
+}
+
+// pre_extend: block qq scores every tuple prefix_qq + {k} that does not
+// contain an earlier chosen prefix (so the tuples of different blocks are
+// distinct) and lies in the searched rank range, and records the L-th
+// smallest SSE.  Q*L >= KP distinct tuples at or below max_q bound_q make
+// that maximum an upper bound of the KP-th best SSE of the search.
+__global__ __launch_bounds__(256) void pre_extend_kernel(Ctx c, int D, int ranged, uint64_t r0,
+                                                         uint64_t r1, int L) {
+    __shared__ double red[256];
+    __shared__ int64_t redi[256];
+    const int qq = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int Q = *c.pre_count;
+    if (qq >= Q) {
+        if (tid == 0) c.pre_bound[qq] = INF;
+        return;
+    }
+    const int q = D - 1;
+    int32_t P[MAXD];
+    for (int m = 0; m < q; ++m) P[m] = c.pre_prefix[qq * MAXD + m];
+    double *row = c.pre_sse + (int64_t)qq * c.S;
+    for (int64_t k = tid; k < c.S; k += 256) {
+        double s = INF;
+        int32_t tup[MAXD];
+        bool inP = false;
+        int n = 0;
+        for (int m = 0; m < q; ++m) {
+            if (P[m] == k) inP = true;
+        }
+        if (!inP) {
+            bool placed = false;
+            for (int m = 0; m < q; ++m) {
+                if (!placed && k < P[m]) {
+                    tup[n++] = (int32_t)k;
+                    placed = true;
+                }
+                tup[n++] = P[m];
+            }
+            if (!placed) tup[n++] = (int32_t)k;
+            bool dup = false;
+            for (int o = 0; o < qq && !dup; ++o) {
+                int hit = 0;
+                for (int m = 0; m < q; ++m) {
+                    const int32_t v = c.pre_prefix[o * MAXD + m];
+                    for (int u = 0; u < D; ++u) hit += (tup[u] == v);
+                }
+                dup = (hit == q);
+            }
+            if (!dup) {
+                bool in = true;
+                if (ranged) {
+                    const uint64_t rk = lex_rank(BinomTab{c.btab, c.S}, c.S, D, tup);
+                    in = rk >= r0 && rk < r1;
+                }
+                if (in) s = ne_sse(c, D, tup);
+            }
+        }
+        row[k] = s;
+    }
+    __syncthreads();
+    // L rounds of block argmin extraction; the last value is the L-th smallest
+    double last = INF;
+    for (int it = 0; it < L; ++it) {
+        double best = INF;
+        int64_t bk = -1;
+        for (int64_t k = tid; k < c.S; k += 256) {
+            const double v = row[k];
+            if (v < best) {
+                best = v;
+                bk = k;
+            }
+        }
+        red[tid] = best;
+        redi[tid] = bk;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if (tid < o) {
+                if (red[tid + o] < red[tid] ||
+                    (red[tid + o] == red[tid] && redi[tid + o] >= 0 &&
+                     (redi[tid] < 0 || redi[tid + o] < redi[tid]))) {
+                    red[tid] = red[tid + o];
+                    redi[tid] = redi[tid + o];
+                }
+            }
+            __syncthreads();
+        }
+        last = red[0];
+        const int64_t win = redi[0];
+        __syncthreads();
+        if (win < 0) {
+            last = INF;
+            break;
+        }
+        if (tid == 0) row[win] = INF;
+        __syncthreads();
+    }
+    if (tid == 0) c.pre_bound[qq] = last;
+}
+
+__device__ double theta0_from_prepass(const Ctx &c, int L, int KP) {
+    const int Q = *c.pre_count;
+    if ((int64_t)Q * L < KP) return INF;
+    double th = 0.0;
+    for (int q = 0; q < Q; ++q) th = fmax(th, c.pre_bound[q]);
+    return th;
+}
+
+// --------------------------------------------------------- search kernel
+struct SearchArgs {
+    int D, TL, JB, R, KP, L, ranged;
+    uint64_t r0, r1;
+};
+
+// LDS record of the Cholesky row of prefix (P', j) for one task:
+//   v[0..q-1] = R_{P'}^{-1} G[P', j],  alpha = 1/d_j,  zs = z_j / s_j,
+//   pi = p - theta_f (single task) ,  p = SSE of the prefix (P', j)
+// z_j = (b_j - v.z') / s_j, s_j = sqrt(d_j), d_j = 1 - |v|^2.
+// An invalid record has p = pi = NaN, which fails every comparison.
+
+template <int D, bool MT>
+__global__ __launch_bounds__(256) void search_kernel(Ctx c, SearchArgs a) {
+    constexpr int q = D - 2;
+    constexpr int QA = q > 0 ? q : 1;               // array extent
+    constexpr int RECW = q + 4;                      // doubles per record
+    constexpr int SUBW = QA * QA + QA + 2;           // Linv (QA x QA), z', p', valid
+    constexpr int NR = MT ? 1 : SUBP;                // sub-prefixes per item
+
+    extern __shared__ double smem[];
+    const int KP = a.KP;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+
+    // LDS carve: per-wave lists, records [256][RECW], sub-prefix factors
+    double *Ls = smem + (size_t)wave * KP * 2;
+    uint64_t *Lr = reinterpret_cast<uint64_t *>(Ls + KP);
+    double *recs = smem + (size_t)SEARCH_WAVES * KP * 2;
+    double *subf = recs + 256 * RECW;                  // [64][SUBW] (per r, or per task)
+    __shared__ int32_t s_sub[SUBP][QA];                // sub-prefix indices per r
+    __shared__ int s_iq[SUBP];                         // last sub-prefix index (or -1)
+    __shared__ unsigned long long s_mask[SUBP > 64 ? SUBP : 64];  // record validity per r (ST) / per jj (MT)
+    __shared__ uint64_t s_item;
+    __shared__ double s_theta;
+
+    for (int m = lane; m < KP; m += 64) {
+        Ls[m] = INF;
+        Lr[m] = ~0ull;
+    }
+    double theta_pub = INF;  // last value this wave published
+    const double theta0 = theta0_from_prepass(c, a.L, KP);
+
+    const int TL = MT ? a.TL : 1;         // lanes per last index
+    const int KL = 64 / TL;               // last indices per wave chunk
+    const int JB = a.JB;                  // j values per item
+
+    const uint64_t nitems = c.cum[(c.S - 1 + JB - 1) / JB];
+    for (;;) {
+        if (tid == 0) {
+            s_item = atomicAdd(c.work_counter, 1u);
+            const double ts = theta_load(c.theta_bits);
+            s_theta = fmin(ts, theta0);
+        }
+        __syncthreads();
+        const uint64_t item = s_item;
+        if (item >= nitems) break;
+        const double theta_item = s_theta;
+        const double theta_f = theta_item < INF ? theta_item * (1.0 + THETA_SLACK) : INF;
+
+        // item -> (j-block, sub-prefix group) by bisection on the cumulative table
+        int64_t lo = 0, hi = (c.S - 1 + JB - 1) / JB - 1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) / 2;
+            if (c.cum[mid] <= item) lo = mid; else hi = mid - 1;
+        }
+        const int64_t jb = lo;
+        const uint64_t grp = item - c.cum[jb];
+        int64_t Nj = JB * (jb + 1);
+        if (Nj > c.S - 1) Nj = c.S - 1;
+        const int64_t j0 = JB * jb;
+        const uint64_t nsub = q > 0 ? binom(Nj - 1, q) : 1;
+
+        // ---- records: thread -> (r, jj) for one task, (jj, t) for many
+        {
+            int r, jj, t;
+            if (MT) {
+                r = 0;
+                jj = tid / TL;
+                t = tid % TL;
+            } else {
+                r = tid >> 6;
+                jj = tid & 63;
+                t = 0;
+            }
+            const uint64_t sr = grp * NR + r;
+            const bool rvalid = (r < NR) && (sr < nsub) && (jj < JB);
+            int32_t P[QA];
+            if (rvalid) {
+                if (q > 0) colex_unrank(BinomTab{c.btab, c.S}, sr, q, Nj - 1, P);
+            }
+            // sub-prefix factorisation (normalised: unit diagonal)
+            double Li[QA][QA], zp[QA], pp = 0.0;
+            bool pvalid = rvalid && t < c.T;
+            if (pvalid) {
+                pp = c.cyy[t];
+                double Lf[QA][QA];
+                for (int m = 0; m < q; ++m) {
+                    for (int jx = 0; jx < m; ++jx) {
+                        double s = Gat(c, P[m], P[jx], t);
+                        for (int l = 0; l < jx; ++l) s -= Lf[m][l] * Lf[jx][l];
+                        Lf[m][jx] = s / Lf[jx][jx];
+                    }
+                    double d = Gat(c, P[m], P[m], t);
+                    for (int l = 0; l < m; ++l) d -= Lf[m][l] * Lf[m][l];
+                    if (!(d > RANK_EPS)) pvalid = false;
+                    Lf[m][m] = sqrt(fmax(d, 0.0));
+                }
+                if (pvalid) {
+                    // Li = Lf^{-1} (lower), z' = Li b_P', p' = c - |z'|^2
+                    for (int m = 0; m < q; ++m) {
+                        for (int jx = 0; jx <= m; ++jx) {
+                            double s = (m == jx) ? 1.0 : 0.0;
+                            for (int l = jx; l < m; ++l) s -= Lf[m][l] * Li[l][jx];
+                            Li[m][jx] = s / Lf[m][m];
+                        }
+                        for (int jx = m + 1; jx < QA; ++jx) Li[m][jx] = 0.0;
+                    }
+                    for (int m = 0; m < q; ++m) {
+                        double s = 0.0;
+                        for (int l = 0; l <= m; ++l) s += Li[m][l] * c.bhat[(int64_t)P[l] * c.TP + t];
+                        zp[m] = s;
+                        pp -= s * s;
+                    }
+                }
+            }
+            // publish the sub-prefix (one writer per r / per task)
+            const int sid = MT ? t : r;
+            const bool writer = MT ? (jj == 0 && t < 64) : (jj == 0 && r < NR);
+            if (writer) {
+                double *f = subf + sid * SUBW;
+                for (int m = 0; m < QA; ++m)
+                    for (int l = 0; l < QA; ++l) f[m * QA + l] = (pvalid && m < q) ? Li[m][l] : 0.0;
+                for (int m = 0; m < QA; ++m) f[QA * QA + m] = (pvalid && m < q) ? zp[m] : 0.0;
+                f[QA * QA + QA] = pvalid ? pp : 0.0;
+                f[QA * QA + QA + 1] = pvalid ? 1.0 : 0.0;
+                if (!MT) {
+                    for (int m = 0; m < QA; ++m) s_sub[r][m] = (rvalid && m < q) ? P[m] : -1;
+                    s_iq[r] = (rvalid && q > 0) ? P[q - 1] : (rvalid ? -1 : 1 << 30);
+                } else if (t == 0) {
+                    for (int m = 0; m < QA; ++m) s_sub[0][m] = (rvalid && m < q) ? P[m] : -1;
+                    s_iq[0] = (rvalid && q > 0) ? P[q - 1] : (rvalid ? -1 : 1 << 30);
+                }
+            }
+            // record of (P', j)
+            const int64_t j = j0 + jj;
+            const int iq = (q > 0 && rvalid) ? P[q - 1] : -1;
+            bool jvalid = rvalid && (j > iq) && (j < Nj);
+            double rec[RECW];
+            for (int m = 0; m < RECW; ++m) rec[m] = 0.0;
+            bool ok = false;
+            if (jvalid && t < c.T && pvalid) {
+                double v[QA];
+                double d = Gat(c, j, j, t);
+                for (int m = 0; m < q; ++m) {
+                    double s = 0.0;
+                    for (int l = 0; l <= m; ++l) s += Li[m][l] * Gat(c, P[l], j, t);
+                    v[m] = s;
+                    d -= s * s;
+                }
+                if (d > RANK_EPS) {
+                    const double sj = sqrt(d);
+                    double zn = c.bhat[j * c.TP + t];
+                    for (int m = 0; m < q; ++m) zn -= v[m] * zp[m];
+                    zn /= sj;
+                    const double p = pp - zn * zn;
+                    for (int m = 0; m < q; ++m) rec[m] = v[m];
+                    rec[q] = 1.0 / d;
+                    rec[q + 1] = zn / sj;
+                    rec[q + 2] = p - theta_f;
+                    rec[q + 3] = p;
+                    ok = true;
+                }
+            } else if (MT && jvalid && t >= c.T) {
+                ok = true;  // padding task: contributes exactly zero
+            }
+            if (!ok) {
+                rec[q + 2] = __builtin_nan("");
+                rec[q + 3] = __builtin_nan("");
+            }
+            const int slot = MT ? (jj * TL + t) : (r * 64 + jj);
+            if (MT ? (jj < JB) : true) {
+                double *dst = recs + slot * RECW;
+                for (int m = 0; m < RECW; ++m) dst[m] = rec[m];
+            }
+            // validity masks: ST per r over jj; MT per jj over all tasks
+            if (!MT) {
+                const unsigned long long bal = __ballot(ok);
+                if (lane == 0) s_mask[r] = bal;
+            }
+        }
+        if (MT) {
+            if (tid < 64) s_mask[tid] = 0;
+        }
+        __syncthreads();
+        if (MT) {
+            // a j is live if every real task has a valid record
+            if (tid < JB) {
+                bool all = true;
+                for (int t = 0; t < c.T; ++t) {
+                    const double *rr = recs + (tid * TL + t) * RECW;
+                    all &= !__builtin_isnan(rr[q + 3]);
+                }
+                s_mask[tid] = all ? 1ull : 0ull;
+            }
+            __syncthreads();
+        }
+
+        // ---- sweep the last index k in chunks of KL per wave
+        const int64_t jhi = (j0 + JB < Nj ? j0 + JB : Nj) - 1;  // largest j of the block
+        const int64_t kstart = j0 + 1;
+        const int tl = MT ? (lane % TL) : 0;
+        const int kl = MT ? (lane / TL) : lane;
+        const int myt = tl;
+        for (int64_t kb = kstart + (int64_t)wave * KL; kb < c.S; kb += (int64_t)SEARCH_WAVES * KL) {
+            const int64_t k = kb + kl;
+            const bool kin = k < c.S;
+            const int64_t kc = kin ? k : c.S - 1;
+            // hoisted k-dependent part of each sub-prefix solve
+            double wq[NR][QA], dq[NR], zq[NR];
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                const int sid = MT ? myt : r;
+                const double *f = subf + sid * SUBW;
+                const int tt = MT ? myt : 0;
+                double g[QA];
+                for (int m = 0; m < q; ++m) {
+                    const int32_t pm = MT ? s_sub[0][m] : s_sub[r][m];
+                    g[m] = (pm >= 0 && tt < c.T) ? Gat(c, pm, kc, tt) : 0.0;
+                }
+                double dd = (tt < c.T) ? Gat(c, kc, kc, tt) : 1.0;
+                double zz = (tt < c.T) ? c.bhat[kc * c.TP + tt] : 0.0;
+                for (int m = 0; m < q; ++m) {
+                    double s = 0.0;
+                    for (int l = 0; l <= m; ++l) s += f[m * QA + l] * g[l];
+                    wq[r][m] = s;
+                    dd -= s * s;
+                    zz -= s * f[QA * QA + m];
+                }
+                dq[r] = dd;
+                zq[r] = zz;
+            }
+            const bool check = (kb <= jhi) || (kb + KL > c.S);
+            const int64_t jend = jhi + 1;
+            for (int64_t j = j0; j < jend; ++j) {
+                const int jj = (int)(j - j0);
+                if (MT) {
+                    if (!s_mask[jj]) continue;
+                    const double g = (myt < c.T) ? Gat(c, j, kc, myt) : 0.0;
+                    const double *rr = recs + (jj * TL + myt) * RECW;
+                    double u = g;
+                    for (int m = 0; m < q; ++m) u -= rr[m] * wq[0][m];
+                    const double d = dq[0] - rr[q] * (u * u);
+                    const double zeta = zq[0] - rr[q + 1] * u;
+                    // approximate term p - zeta^2/d: reciprocal + one Newton step
+                    double rc = __builtin_amdgcn_rcp(d);
+                    rc = rc * (2.0 - d * rc);
+                    double term = (myt < c.T) ? rr[q + 3] - zeta * zeta * rc : 0.0;
+                    double sum = term;
+                    for (int o = 1; o < TL; o <<= 1) sum += __shfl_xor(sum, o);
+                    bool pass = (sum <= theta_f) && (tl == 0);
+                    if (check) pass = pass && kin && (k > j);
+                    if (__ballot(pass)) {
+                        // exact per-task terms, same reduction order
+                        const bool tv = (myt < c.T);
+                        double ex = 0.0;
+                        if (tv) ex = (d > RANK_EPS) ? rr[q + 3] - zeta * zeta / d : INF;
+                        double es = ex;
+                        for (int o = 1; o < TL; o <<= 1) es += __shfl_xor(es, o);
+                        const double thc = fmin(theta_f, Ls[KP - 1]);
+                        bool take = pass && kin && (k > j) && (es <= thc);
+                        uint64_t rk = 0;
+                        if (take) {
+                            int32_t tup[MAXD];
+                            for (int m = 0; m < q; ++m) tup[m] = s_sub[0][m];
+                            tup[q] = (int32_t)j;
+                            tup[q + 1] = (int32_t)k;
+                            rk = lex_rank(BinomTab{c.btab, c.S}, c.S, D, tup);
+                            if (a.ranged && (rk < a.r0 || rk >= a.r1)) take = false;
+                        }
+                        unsigned long long m = __ballot(take);
+                        if (m && lane == 0) atomicAdd(c.cand_counter, (unsigned)__popcll(m));
+                        while (m) {
+                            const int src = __ffsll((long long)m) - 1;
+                            m &= m - 1;
+                            const double cs = __shfl(es, src);
+                            const uint64_t cr = (uint64_t)__shfl((long long)rk, src);
+                            list_insert(Ls, Lr, KP, cs, cr);
+                        }
+                        const double tw = Ls[KP - 1];
+                        if (tw < theta_pub) {
+                            theta_pub = tw;
+                            if (lane == 0) theta_publish(c.theta_bits, tw);
+                        }
+                    }
+                } else {
+                    const double g = Gat(c, j, kc, 0);
+                    bool pr[NR];
+                    double zr[NR], dr[NR];
+#pragma unroll
+                    for (int r = 0; r < NR; ++r) {
+                        const double *rr = recs + (r * 64 + jj) * RECW;
+                        double u = g;
+#pragma unroll
+                        for (int m = 0; m < q; ++m) u -= rr[m] * wq[r][m];
+                        const double d = dq[r] - rr[q] * (u * u);
+                        const double zeta = zq[r] - rr[q + 1] * u;
+                        pr[r] = zeta * zeta >= rr[q + 2] * d;
+                        zr[r] = zeta;
+                        dr[r] = d;
+                    }
+                    bool any = false;
+#pragma unroll
+                    for (int r = 0; r < NR; ++r) any |= pr[r];
+                    if (check) any = any && kin && (k > j);
+                    if (__ballot(any)) {
+                        for (int r = 0; r < NR; ++r) {
+                            if (!((s_mask[r] >> jj) & 1ull)) continue;
+                            const double *rr = recs + (r * 64 + jj) * RECW;
+                            const double d = dr[r];
+                            const double es = (d > RANK_EPS) ? rr[q + 3] - zr[r] * zr[r] / d : INF;
+                            const double thc = fmin(theta_f, Ls[KP - 1]);
+                            bool take = pr[r] && kin && (k > j) && (es <= thc);
+                            uint64_t rk = 0;
+                            if (take) {
+                                int32_t tup[MAXD];
+                                for (int m = 0; m < q; ++m) tup[m] = s_sub[r][m];
+                                tup[q] = (int32_t)j;
+                                tup[q + 1] = (int32_t)k;
+                                rk = lex_rank(BinomTab{c.btab, c.S}, c.S, D, tup);
+                                if (a.ranged && (rk < a.r0 || rk >= a.r1)) take = false;
+                            }
+                            unsigned long long m = __ballot(take);
+                            if (m && lane == 0) atomicAdd(c.cand_counter, (unsigned)__popcll(m));
+                            while (m) {
+                                const int src = __ffsll((long long)m) - 1;
+                                m &= m - 1;
+                                const double cs = __shfl(es, src);
+                                const uint64_t cr = (uint64_t)__shfl((long long)rk, src);
+                                list_insert(Ls, Lr, KP, cs, cr);
+                            }
+                        }
+                        const double tw = Ls[KP - 1];
+                        if (tw < theta_pub) {
+                            theta_pub = tw;
+                            if (lane == 0) theta_publish(c.theta_bits, tw);
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // write this wave's list
+    const int64_t gw = (int64_t)blockIdx.x * SEARCH_WAVES + wave;
+    for (int m = lane; m < KP; m += 64) {
+        c.list_sse[gw * KP + m] = Ls[m];
+        c.list_rank[gw * KP + m] = Lr[m];
+    }
+}
+
+// D = 1: every feature is a tuple; SSE = sum_t (c_t - b_t^2) over full-rank columns.
+__global__ __launch_bounds__(256) void search_d1_kernel(Ctx c, SearchArgs a) {
+    extern __shared__ double smem[];
+    const int KP = a.KP;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double *Ls = smem + (size_t)wave * KP * 2;
+    uint64_t *Lr = reinterpret_cast<uint64_t *>(Ls + KP);
+    for (int m = lane; m < KP; m += 64) {
+        Ls[m] = INF;
+        Lr[m] = ~0ull;
+    }
+    const int64_t gw = (int64_t)blockIdx.x * SEARCH_WAVES + wave;
+    const int64_t nw = (int64_t)gridDim.x * SEARCH_WAVES;
+    for (int64_t kb = gw * 64; kb < c.S; kb += nw * 64) {
+        const int64_t k = kb + lane;
+        double s = INF;
+        if (k < c.S) {
+            s = 0.0;
+            for (int t = 0; t < c.T; ++t) {
+                if (!(Gat(c, k, k, t) == 1.0)) {
+                    s = INF;
+                    break;
+                }
+                const double b = c.bhat[k * c.TP + t];
+                s += c.cyy[t] - b * b;
+            }
+            if (a.ranged && ((uint64_t)k < a.r0 || (uint64_t)k >= a.r1)) s = INF;
+        }
+        unsigned long long m = __ballot(s < INF && s <= Ls[KP - 1]);
+        while (m) {
+            const int src = __ffsll((long long)m) - 1;
+            m &= m - 1;
+            list_insert(Ls, Lr, KP, __shfl(s, src), (uint64_t)(kb + src));
+        }
+    }
+    for (int m = lane; m < KP; m += 64) {
+        c.list_sse[gw * KP + m] = Ls[m];
+        c.list_rank[gw * KP + m] = Lr[m];
+    }
+}
+
+// ----------------------------------------------------------------- merge
+// One workgroup: gather every list entry at or below the final bound, then
+// select the KP smallest (SSE, rank) keys with bitonic sorts in LDS, a
+// running top-KP carried across chunks when there are many.
+constexpr int MERGE_THREADS = 1024;
+constexpr int MERGE_CAP = 2048;
+
+__device__ void bitonic_sort_lds(double *ks, uint64_t *kr, int N) {
+    for (int k = 2; k <= N; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < N; i += blockDim.x) {
+                const int ixj = i ^ j;
+                if (ixj > i) {
+                    const bool up = (i & k) == 0;
+                    const double a = ks[i], b = ks[ixj];
+                    const uint64_t ra = kr[i], rb = kr[ixj];
+                    const bool gt = key_less(b, rb, a, ra);
+                    if (gt == up) {
+                        ks[i] = b;
+                        ks[ixj] = a;
+                        kr[i] = rb;
+                        kr[ixj] = ra;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+__global__ __launch_bounds__(MERGE_THREADS) void merge_kernel(Ctx c, int nlists, int KP, int L, int use_pre) {
+    __shared__ double ks[MERGE_CAP];
+    __shared__ uint64_t kr[MERGE_CAP];
+    __shared__ int64_t s_tot;
+    __shared__ int64_t wsum[MERGE_THREADS / 64];
+    const int tid = threadIdx.x;
+    double bound = theta_load(c.theta_bits);
+    if (use_pre) bound = fmin(bound, theta0_from_prepass(c, L, KP));
+    bound = bound < INF ? bound * (1.0 + THETA_SLACK) : INF;
+    // counts per list (lists are sorted ascending)
+    for (int l = tid; l < nlists; l += MERGE_THREADS) {
+        int n = 0;
+        const double *ls = c.list_sse + (int64_t)l * KP;
+        while (n < KP && ls[n] < INF && ls[n] <= bound) ++n;
+        c.list_count[l] = n;
+    }
+    __syncthreads();
+    // exclusive scan (serial over chunks per thread, then block scan)
+    const int per = (nlists + MERGE_THREADS - 1) / MERGE_THREADS;
+    int64_t local = 0;
+    for (int l = tid * per; l < nlists && l < (tid + 1) * per; ++l) local += c.list_count[l];
+    // block exclusive scan of local
+    int64_t incl = local;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t v = __shfl_up(incl, o);
+        if ((tid & 63) >= o) incl += v;
+    }
+    if ((tid & 63) == 63) wsum[tid >> 6] = incl;
+    __syncthreads();
+    if (tid == 0) {
+        int64_t acc = 0;
+        for (int w = 0; w < MERGE_THREADS / 64; ++w) {
+            const int64_t v = wsum[w];
+            wsum[w] = acc;
+            acc += v;
+        }
+        s_tot = acc;
+    }
+    __syncthreads();
+    int64_t off = wsum[tid >> 6] + incl - local;
+    for (int l = tid * per; l < nlists && l < (tid + 1) * per; ++l) {
+        const int n = c.list_count[l];
+        for (int e = 0; e < n; ++e) {
+            c.cand_sse[off + e] = c.list_sse[(int64_t)l * KP + e];
+            c.cand_rank[off + e] = c.list_rank[(int64_t)l * KP + e];
+        }
+        off += n;
+    }
+    __threadfence_block();
+    __syncthreads();
+    const int64_t total = s_tot;
+    // running selection
+    for (int i = tid; i < MERGE_CAP; i += MERGE_THREADS) {
+        ks[i] = INF;
+        kr[i] = ~0ull;
+    }
+    __syncthreads();
+    const int64_t chunk = MERGE_CAP - KP;
+    for (int64_t base = 0; base < total || base == 0; base += chunk) {
+        for (int i = tid; i < chunk; i += MERGE_THREADS) {
+            const int64_t e = base + i;
+            if (e < total) {
+                ks[KP + i] = c.cand_sse[e];
+                kr[KP + i] = c.cand_rank[e];
+            } else {
+                ks[KP + i] = INF;
+                kr[KP + i] = ~0ull;
+            }
+        }
+        __syncthreads();
+        bitonic_sort_lds(ks, kr, MERGE_CAP);
+        if (base + chunk >= total) break;
+    }
+    for (int i = tid; i < KP; i += MERGE_THREADS) {
+        c.merged_sse[i] = ks[i];
+        c.merged_rank[i] = kr[i];
+    }
+}
+
+// --------------------------------------------------------------- rescore
+// One workgroup per candidate: for each task, the (D x D) normal equations
+// of the centred columns are accumulated straight from F in a fixed order,
+// solved by Cholesky (pivot-ratio rank test), and the SSE is taken as the
+// squared norm of the explicit residual y_c - X_c beta.
+__global__ __launch_bounds__(256) void rescore_kernel(Ctx c, int D) {
+    constexpr int NACC = MAXD * (MAXD + 1) / 2 + MAXD;
+    __shared__ double red[NACC][256];
+    __shared__ double s_beta[MAXD];
+    __shared__ int s_ok;
+    const int cand = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int W = D + 1;
+    double *coef = c.resc_coef + (int64_t)cand * c.T * (c.D_max + 1);
+    if (!(c.merged_sse[cand] < INF)) {
+        if (tid == 0) c.resc_sse[cand] = INF;
+        for (int i = tid; i < c.T * (c.D_max + 1); i += 256) coef[i] = __builtin_nan("");
+        return;
+    }
+    int32_t tup[MAXD];
+    lex_unrank(BinomTab{c.btab, c.S}, c.S, D, c.merged_rank[cand], tup);
+    double total = 0.0;
+    bool valid = true;
+    for (int t = 0; t < c.T; ++t) {
+        const int64_t r0 = c.off_dev[t], r1 = c.off_dev[t + 1];
+        const double ym = c.ybar[t];
+        double mu[MAXD];
+        for (int m = 0; m < D; ++m) mu[m] = c.mu[(int64_t)t * c.S + tup[m]];
+        double acc[NACC];
+        for (int i = 0; i < NACC; ++i) acc[i] = 0.0;
+        for (int64_t i = r0 + tid; i < r1; i += 256) {
+            double x[MAXD];
+            for (int m = 0; m < D; ++m) x[m] = c.F[(int64_t)tup[m] * c.n_total + i] - mu[m];
+            const double yc = c.y[i] - ym;
+            int e = 0;
+            for (int m = 0; m < D; ++m)
+                for (int l = 0; l <= m; ++l) acc[e++] += x[m] * x[l];
+            for (int m = 0; m < D; ++m) acc[e++] += x[m] * yc;
+        }
+        const int nacc = D * (D + 1) / 2 + D;
+        for (int i = 0; i < nacc; ++i) red[i][tid] = acc[i];
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if (tid < o)
+                for (int i = 0; i < nacc; ++i) red[i][tid] += red[i][tid + o];
+            __syncthreads();
+        }
+        if (tid == 0) {
+            double M[MAXD][MAXD], v[MAXD], L[MAXD][MAXD], z[MAXD];
+            int e = 0;
+            for (int m = 0; m < D; ++m)
+                for (int l = 0; l <= m; ++l) {
+                    M[m][l] = red[e][0];
+                    M[l][m] = red[e][0];
+                    ++e;
+                }
+            for (int m = 0; m < D; ++m) v[m] = red[e++][0];
+            int ok = 1;
+            for (int m = 0; m < D && ok; ++m) {
+                for (int jx = 0; jx < m; ++jx) {
+                    double s = M[m][jx];
+                    for (int l = 0; l < jx; ++l) s -= L[m][l] * L[jx][l];
+                    L[m][jx] = s / L[jx][jx];
+                }
+                double d = M[m][m];
+                for (int l = 0; l < m; ++l) d -= L[m][l] * L[m][l];
+                if (!(M[m][m] > 0.0) || !(d > RANK_EPS * M[m][m])) ok = 0;
+                else L[m][m] = sqrt(d);
+            }
+            if (ok) {
+                for (int m = 0; m < D; ++m) {
+                    double s = v[m];
+                    for (int l = 0; l < m; ++l) s -= L[m][l] * z[l];
+                    z[m] = s / L[m][m];
+                }
+                for (int m = D - 1; m >= 0; --m) {
+                    double s = z[m];
+                    for (int l = m + 1; l < D; ++l) s -= L[l][m] * s_beta[l];
+                    s_beta[m] = s / L[m][m];
+                }
+            }
+            s_ok = ok;
+        }
+        __syncthreads();
+        if (!s_ok) {
+            valid = false;
+            __syncthreads();
+            break;
+        }
+        double beta[MAXD];
+        for (int m = 0; m < D; ++m) beta[m] = s_beta[m];
+        double ss = 0.0;
+        for (int64_t i = r0 + tid; i < r1; i += 256) {
+            double e = c.y[i] - ym;
+            for (int m = 0; m < D; ++m) e -= beta[m] * (c.F[(int64_t)tup[m] * c.n_total + i] - mu[m]);
+            ss += e * e;
+        }
+        red[0][tid] = ss;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if (tid < o) red[0][tid] += red[0][tid + o];
+            __syncthreads();
+        }
+        if (tid == 0) {
+            total += red[0][0];
+            double alpha = ym;
+            for (int m = 0; m < D; ++m) alpha -= beta[m] * mu[m];
+            coef[t * (c.D_max + 1)] = alpha;
+            for (int m = 0; m < D; ++m) coef[t * (c.D_max + 1) + 1 + m] = beta[m];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) c.resc_sse[cand] = valid ? total : INF;
+    (void)W;
+}
+
+// ----------------------------------------------------------------- final
+// Order the re-scored candidates by (SSE, rank) (rank by counting; invalid
+// ones last in candidate order) and write the k best.
+__global__ __launch_bounds__(1024) void final_kernel(Ctx c, int D, int k, int KP) {
+    for (int i = threadIdx.x; i < KP; i += blockDim.x) {
+        const double si = c.resc_sse[i];
+        const uint64_t ri = c.merged_rank[i];
+        const bool vi = si < INF;
+        int pos = 0;
+        for (int j = 0; j < KP; ++j) {
+            const double sj = c.resc_sse[j];
+            const bool vj = sj < INF;
+            const uint64_t rj = c.merged_rank[j];
+            bool before;
+            if (vi && vj) before = key_less(sj, rj, si, ri);
+            else if (vj) before = true;
+            else if (vi) before = false;
+            else before = j < i;
+            pos += before;
+        }
+        if (pos < k) {
+            c.res_sse[pos] = vi ? si : INF;
+            int32_t tup[MAXD];
+            if (vi) lex_unrank(BinomTab{c.btab, c.S}, c.S, D, ri, tup);
+            for (int m = 0; m < D; ++m) c.res_idx[pos * D + m] = vi ? tup[m] : -1;
+            for (int t = 0; t < c.T; ++t)
+                for (int m = 0; m <= D; ++m)
+                    c.res_coef[((int64_t)pos * c.T + t) * (D + 1) + m] =
+                        vi ? c.resc_coef[((int64_t)i * c.T + t) * (c.D_max + 1) + m] : __builtin_nan("");
+        }
+    }
+}
+
+// -------------------------------------------------------------- launcher
+template <int D, bool MT>
+static void launch_one(const Ctx &c, const SearchArgs &a, size_t lds, hipStream_t st) {
+    hipLaunchKernelGGL((search_kernel<D, MT>), dim3(c.search_wgs), dim3(SEARCH_WG), lds, st, c, a);
+}
+
+int launch_search(const Ctx &c, const SearchCall &sc, hipStream_t st) {
+    const int D = sc.D;
+    const bool MT = c.T > 1;
+    SearchArgs a{};
+    a.D = D;
+    a.KP = c.KP;
+    a.ranged = sc.ranged;
+    a.r0 = sc.r0;
+    a.r1 = sc.r1;
+    a.TL = MT ? c.TP : 1;
+    a.JB = MT ? (64 < SEARCH_WG / c.TP ? 64 : SEARCH_WG / c.TP) : JBLK;
+    a.R = MT ? 1 : SUBP;
+    a.L = (c.KP + PRE_Q - 1) / PRE_Q;
+    const int q = D - 2;
+    const int RECW = q + 4;
+    const int QA = q > 0 ? q : 1;
+    const int SUBW = QA * QA + QA + 2;
+    const size_t lds_lists = (size_t)SEARCH_WAVES * c.KP * 2 * sizeof(double);
+    const unsigned init_blocks = (unsigned)(((SISSO_MAX_D + 1) * (c.S + 1) + 255) / 256);
+
+    if (D == 1) {
+        int wgs = (int)((c.S + SEARCH_WG - 1) / SEARCH_WG);
+        if (wgs > c.search_wgs) wgs = c.search_wgs;
+        phase_begin(c, SISSO_PHASE_PREPASS, st);
+        hipLaunchKernelGGL(search_init_kernel, dim3(init_blocks), dim3(256), 0, st, c, 2, 1, JBLK);
+        phase_end(c, SISSO_PHASE_PREPASS, st);
+        phase_begin(c, SISSO_PHASE_SEARCH, st);
+        hipLaunchKernelGGL(search_d1_kernel, dim3(wgs), dim3(SEARCH_WG), lds_lists, st, c, a);
+        phase_end(c, SISSO_PHASE_SEARCH, st);
+        phase_begin(c, SISSO_PHASE_MERGE, st);
+        hipLaunchKernelGGL(merge_kernel, dim3(1), dim3(MERGE_THREADS), 0, st, c, wgs * SEARCH_WAVES,
+                           c.KP, a.L, 0);
+        phase_end(c, SISSO_PHASE_MERGE, st);
+    } else {
+        phase_begin(c, SISSO_PHASE_PREPASS, st);
+        hipLaunchKernelGGL(search_init_kernel, dim3(init_blocks), dim3(256), 0, st, c, D, a.R, a.JB);
+        hipLaunchKernelGGL(pre_select_kernel, dim3(1), dim3(256), 0, st, c, D);
+        hipLaunchKernelGGL(pre_extend_kernel, dim3(PRE_Q), dim3(256), 0, st, c, D, sc.ranged,
+                           sc.r0, sc.r1, a.L);
+        phase_end(c, SISSO_PHASE_PREPASS, st);
+        phase_begin(c, SISSO_PHASE_SEARCH, st);
+        const size_t lds = lds_lists + (size_t)256 * RECW * sizeof(double) + (size_t)64 * SUBW * sizeof(double);
+        switch (D) {
+            case 2: MT ? launch_one<2, true>(c, a, lds, st) : launch_one<2, false>(c, a, lds, st); break;
+            case 3: MT ? launch_one<3, true>(c, a, lds, st) : launch_one<3, false>(c, a, lds, st); break;
+            case 4: MT ? launch_one<4, true>(c, a, lds, st) : launch_one<4, false>(c, a, lds, st); break;
+            default: return -1;
+        }
+        phase_end(c, SISSO_PHASE_SEARCH, st);
+        phase_begin(c, SISSO_PHASE_MERGE, st);
+        hipLaunchKernelGGL(merge_kernel, dim3(1), dim3(MERGE_THREADS), 0, st, c,
+                           c.search_wgs * SEARCH_WAVES, c.KP, a.L, 1);
+        phase_end(c, SISSO_PHASE_MERGE, st);
+    }
+    phase_begin(c, SISSO_PHASE_RESCORE, st);
+    hipLaunchKernelGGL(rescore_kernel, dim3(c.KP), dim3(256), 0, st, c, D);
+    phase_end(c, SISSO_PHASE_RESCORE, st);
+    phase_begin(c, SISSO_PHASE_FINAL, st);
+    hipLaunchKernelGGL(final_kernel, dim3(1), dim3(1024), 0, st, c, D, sc.k, c.KP);
+    phase_end(c, SISSO_PHASE_FINAL, st);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace sl0

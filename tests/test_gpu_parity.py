@@ -1,0 +1,231 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Every case prints its name, seed and shape before it touches the GPU.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import make_config, make_problem, tiny_problem
+from tests.parity import compare_topk, total_ss
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _run(p, D, k, D_max=None, k_max=None, rng=None):
+    from paper_2502_20072_amd import L0Search
+    s = L0Search(p.F, p.y, p.task_offsets, D_max=D_max or max(D, 1), k_max=k_max or k)
+    s.gram()
+    if rng is None:
+        s.search(D, k)
+    else:
+        s.search_range(D, k, *rng)
+    out = s.topk()
+    s.close()
+    return out
+
+
+def _np_gram(p, t):
+    a, b = p.task_offsets[t], p.task_offsets[t + 1]
+    X = p.F[:, a:b] - p.F[:, a:b].mean(axis=1, keepdims=True)
+    yc = p.y[a:b] - p.y[a:b].mean()
+    nrm = np.sqrt(np.sum(X * X, axis=1))
+    G = (X @ X.T) / np.outer(nrm, nrm)
+    np.fill_diagonal(G, 1.0)
+    return G, (X @ yc) / nrm, float(yc @ yc)
+
+
+@pytest.mark.parametrize("S,n,T", [(1, 7, 1), (37, 50, 1), (128, 300, 1), (200, 100, 1),
+                                   (130, 1000, 3), (257, 700, 2)])
+def test_gram_matches_numpy(S, n, T):
+    from paper_2502_20072_amd import L0Search
+    _say(f"gram S={S} n={n} T={T}")
+    p = tiny_problem(100 + S, S=S, n=n, T=T, D=1)
+    s = L0Search(p.F, p.y, p.task_offsets, D_max=1, k_max=1)
+    s.gram()
+    for t in range(T):
+        G, b, c = s.gram_read(t)
+        Gr, br, cr = _np_gram(p, t)
+        np.testing.assert_allclose(G, Gr, rtol=0, atol=1e-13)
+        assert np.array_equal(G, G.T)
+        np.testing.assert_allclose(b, br, rtol=1e-12, atol=1e-12 * math.sqrt(cr))
+        assert abs(c - cr) <= 1e-12 * cr
+    s.close()
+
+
+SWEEP = []
+_rng = np.random.default_rng(2024)
+for _i in range(40):
+    _D = int(_rng.integers(1, 5))
+    _T = int(_rng.integers(1, 5))
+    _S = int(_rng.integers(_D, 41))
+    _n = int(_rng.integers((_D + 2) * _T, 65 + 20 * _T))
+    SWEEP.append((1000 + _i, _S, _n, _D, _T))
+
+
+@pytest.mark.parametrize("seed,S,n,D,T", SWEEP)
+def test_tiny_sweep_vs_oracle(seed, S, n, D, T):
+    _say(f"sweep seed={seed} S={S} n={n} D={D} T={T}")
+    sizes = None
+    if T > 1:
+        r = np.random.default_rng(seed)
+        cuts = np.sort(r.choice(np.arange(1, n), size=T - 1, replace=False))
+        sizes = np.diff(np.concatenate([[0], cuts, [n]]))
+        if np.any(sizes < D + 2):
+            sizes = None
+    p = tiny_problem(seed, S=S, n=n, T=T, D=D, sigma=0.3, task_sizes=sizes)
+    k = min(12, math.comb(S, D))
+    gidx, gsse, gcoef = _run(p, D, k)
+    oidx, osse, _ = oracle.topk(p.F, p.y, D, k, p.task_offsets)
+    compare_topk(p, D, k, gidx, gsse, oidx, osse, gcoef=gcoef)
+
+
+@pytest.mark.parametrize("D", [1, 2, 3, 4])
+def test_planted_exact_found(D):
+    _say(f"planted exact D={D}")
+    p = make_problem(n=80, S=70, D=D, k=10, seed=7 + D, beta=(1.5, -0.8, 0.6, -0.4)[:D], sigma=0.0)
+    gidx, gsse, _ = _run(p, D, 10)
+    assert list(gidx[0]) == p.planted
+    assert gsse[0] <= 1e-20 * total_ss(p)
+
+
+def test_config_plain_s200_d2_golden():
+    _say("golden plain_s200_d2")
+    g = json.load(open(os.path.join(GOLDEN, "oracle_topk_plain_s200_d2.json")))
+    p = make_config("plain_s200_d2")
+    gidx, gsse, gcoef = _run(p, g["D"], g["k"])
+    compare_topk(p, g["D"], g["k"], gidx, gsse, np.array(g["idx"]), np.array(g["sse"]), gcoef=gcoef)
+
+
+def test_config_plain_s1000_d3_golden():
+    path = os.path.join(GOLDEN, "oracle_topk_plain_s1000_d3.json")
+    if not os.path.exists(path):
+        pytest.skip("stored oracle result for plain_s1000_d3 not generated")
+    _say("golden plain_s1000_d3 (n=2000, S=1000, D=3, k=100)")
+    g = json.load(open(path))
+    p = make_config("plain_s1000_d3")
+    gidx, gsse, gcoef = _run(p, 3, 100)
+    compare_topk(p, 3, 100, gidx, gsse, np.array(g["idx"]), np.array(g["sse"]), gcoef=gcoef)
+    assert [int(v) for v in gidx[0]] == p.planted
+
+
+def test_range_split_equals_full():
+    _say("range split S=60 n=90 D=3")
+    p = tiny_problem(77, S=60, n=90, D=3, sigma=0.4)
+    N = math.comb(60, 3)
+    k = 40
+    fidx, fsse, _ = _run(p, 3, k)
+    parts = []
+    cuts = [0, 1, 5000, 17111, N]
+    for a, b in zip(cuts, cuts[1:]):
+        kk = min(k, b - a)
+        i, s, _ = _run(p, 3, kk, k_max=k, rng=(a, b))
+        for t, v in zip(i, s):
+            if np.isfinite(v):
+                from paper_2502_20072_amd import rank_of
+                r = rank_of(60, t)
+                assert a <= r < b
+                parts.append((float(v), tuple(int(x) for x in t)))
+    parts.sort()
+    assert [t for _, t in parts[:k]] == [tuple(int(x) for x in t) for t in fidx]
+    np.testing.assert_array_equal([v for v, _ in parts[:k]], fsse)
+
+
+def test_rank_deficient_never_returned():
+    _say("rank-deficient columns S=30")
+    p = tiny_problem(78, S=30, n=60, D=3, sigma=0.3)
+    F = p.F.copy()
+    F[5] = 0.5 * F[3] - 2.0 * F[4] + 1.0     # exact combination
+    F[9] = F[3]                              # exact duplicate
+    F[12] = 4.0                              # constant
+    y = p.y + 3.0 * F[3] - 1.0 * F[4]
+    from synth.problems import Problem
+    q = Problem(F=F, y=y, task_offsets=p.task_offsets, planted=[], D=3, k=50, exprs=p.exprs, meta={})
+    gidx, gsse, _ = _run(q, 3, 50)
+    for t in gidx:
+        t = tuple(int(v) for v in t)
+        assert not {3, 4, 5} <= set(t) and not {3, 9} <= set(t) and 12 not in t
+    oidx, osse, _ = oracle.topk(F, y, 3, 50)
+    compare_topk(q, 3, 50, gidx, gsse, oidx, osse)
+
+
+def test_deterministic_repeat():
+    _say("determinism S=120 n=150 D=3")
+    p = tiny_problem(79, S=120, n=150, D=3, sigma=0.5)
+    a = _run(p, 3, 64)
+    b = _run(p, 3, 64)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_abi_errors_and_states():
+    from paper_2502_20072_amd import L0Search, SissoError
+    from paper_2502_20072_amd import _binding as B
+    _say("abi errors")
+    p = tiny_problem(80, S=10, n=20, D=2)
+    s = L0Search(p.F, p.y, p.task_offsets, D_max=2, k_max=5)
+    with pytest.raises(SissoError) as e:
+        s.search(2, 5)
+    assert e.value.code == B.SISSO_ESTATE
+    s.gram()
+    for D, k, code in [(3, 5, B.SISSO_ENOTSUP), (0, 5, B.SISSO_EINVAL), (2, 0, B.SISSO_EINVAL),
+                       (2, 6, B.SISSO_EINVAL)]:
+        with pytest.raises(SissoError) as e:
+            s.search(D, k)
+        assert e.value.code == code
+    with pytest.raises(SissoError) as e:
+        B.sisso_l0_topk(s.handle, 5, 2, 1)
+    assert e.value.code == B.SISSO_ESTATE
+    with pytest.raises(SissoError) as e:
+        s.search_range(2, 5, 10, 10)
+    assert e.value.code == B.SISSO_EINVAL
+    s.search(2, 3)
+    with pytest.raises(SissoError) as e:
+        s.topk(4)
+    assert e.value.code == B.SISSO_ESTATE
+    idx, sse, _ = s.topk(3)
+    assert np.all(np.isfinite(sse))
+    s.close()
+    # too few rows in a task for D
+    q = tiny_problem(81, S=6, n=9, T=2, D=2, task_sizes=[3, 6])
+    s = L0Search(q.F, q.y, q.task_offsets, D_max=2, k_max=3).gram()
+    with pytest.raises(SissoError) as e:
+        s.search(2, 3)
+    assert e.value.code == B.SISSO_EINVAL
+    s.close()
+
+
+def test_nonfinite_input_reported():
+    from paper_2502_20072_amd import L0Search, SissoError
+    from paper_2502_20072_amd import _binding as B
+    _say("non-finite input")
+    p = tiny_problem(82, S=8, n=20, D=2)
+    F = p.F.copy()
+    F[3, 7] = np.nan
+    s = L0Search(F, p.y, p.task_offsets, D_max=2, k_max=3).gram().search(2, 3)
+    with pytest.raises(SissoError) as e:
+        s.topk()
+    assert e.value.code == B.SISSO_EINVAL
+    s.close()
+
+
+def test_fewer_valid_tuples_than_k():
+    _say("fewer valid tuples than k")
+    p = tiny_problem(83, S=4, n=30, D=2, sigma=0.3)
+    F = p.F.copy()
+    F[1] = F[0]
+    F[3] = F[2]
+    from synth.problems import Problem
+    q = Problem(F=F, y=p.y, task_offsets=p.task_offsets, planted=[], D=2, k=6, exprs=p.exprs, meta={})
+    gidx, gsse, _ = _run(q, 2, 6)
+    assert np.sum(np.isfinite(gsse)) == 4
+    oidx, osse, _ = oracle.topk(F, p.y, 2, 6)
+    compare_topk(q, 2, 6, gidx, gsse, oidx, osse)
