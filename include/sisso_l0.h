@@ -112,6 +112,27 @@ int32_t sisso_l0_search(sisso_l0 *h, int32_t D, int32_t k);
  * r1 > C(S, D). */
 int32_t sisso_l0_search_range(sisso_l0 *h, int32_t D, int32_t k, uint64_t r0, uint64_t r1);
 
+/* Batched form (many independent problems, e.g. several SIS subspaces or
+ * the problems of a parameter scan; the paper's multi-task case is one
+ * handle with T > 1).  A batch holds a HIP graph in which every handle's
+ * sisso_gram + sisso_l0_search(D, k) run as one chain, the chains on up to 16
+ * concurrent branches.  The graph is captured once by sisso_l0_batch_create
+ * and launched by sisso_l0_batch_launch (asynchronous, ordered after prior
+ * work on the handles' stream, which all handles must share); afterwards
+ * sisso_l0_topk on each handle returns exactly what an unbatched gram +
+ * search would.  Errors: EINVAL for null/duplicate handles, handles on
+ * different streams, or a (D, k) that some handle rejects (same rules as
+ * sisso_l0_search, except that sisso_gram need not have run); EDEVICE if
+ * capture fails.  Messages: sisso_l0_batch_last_error(). */
+typedef struct sisso_l0_batch sisso_l0_batch;
+int32_t sisso_l0_batch_create(sisso_l0 *const *hs, int32_t P, int32_t D, int32_t k, sisso_l0_batch **out);
+int32_t sisso_l0_batch_launch(sisso_l0_batch *b);
+void sisso_l0_batch_destroy(sisso_l0_batch *b); /* waits for the batch's last launch; NULL-safe */
+const char *sisso_l0_batch_last_error(void);
+/* One-shot convenience: create, launch, destroy (so it returns after the
+ * GPU work has finished). */
+int32_t sisso_l0_search_batch(sisso_l0 *const *hs, int32_t P, int32_t D, int32_t k);
+
 /* Synchronise the stream and copy the result of the last search to HOST
  * buffers: idx (k*D int32, row-major, ascending indices within a row), sse
  * (k doubles, SSE summed over tasks) and, unless NULL, coef (k*T*(D+1)
@@ -153,6 +174,13 @@ enum {
 };
 int32_t sisso_l0_profile(sisso_l0 *h, int32_t enable);
 int32_t sisso_l0_phase_ms(sisso_l0 *h, double *ms);
+
+/* Diagnostics of the last search (synchronises the stream): out[0] tuples
+ * that passed the filter and were offered to a top-k list, out[1] work
+ * items, out[2] the bit pattern of the pre-pass SSE bound (+inf if none),
+ * out[3] the bit pattern of the final device-wide SSE bound.  ESTATE before
+ * a search. */
+int32_t sisso_l0_search_stats(sisso_l0 *h, uint64_t *out);
 
 /* Release the handle (NULL-safe).  Does not free caller memory. */
 void sisso_l0_destroy(sisso_l0 *h);

@@ -210,3 +210,60 @@ def sisso_l0_phase_ms(h: int) -> dict:
     ms = np.zeros(len(PHASES))
     _check(lib.sisso_l0_phase_ms(h, ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), h)
     return dict(zip(PHASES, ms.tolist()))
+
+
+def sisso_l0_search_stats(h: int) -> dict:
+    lib = load()
+    lib.sisso_l0_search_stats.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]
+    lib.sisso_l0_search_stats.restype = ctypes.c_int32
+    out = np.zeros(4, dtype=np.uint64)
+    _check(lib.sisso_l0_search_stats(h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))), h)
+    return dict(candidates=int(out[0]), items=int(out[1]),
+                theta0=float(out[2:3].view(np.float64)[0]), theta_final=float(out[3:4].view(np.float64)[0]))
+
+
+def _batch_sigs(lib):
+    P = ctypes.POINTER
+    lib.sisso_l0_batch_create.argtypes = [P(ctypes.c_void_p), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                          P(ctypes.c_void_p)]
+    lib.sisso_l0_batch_create.restype = ctypes.c_int32
+    lib.sisso_l0_batch_launch.argtypes = [ctypes.c_void_p]
+    lib.sisso_l0_batch_launch.restype = ctypes.c_int32
+    lib.sisso_l0_batch_destroy.argtypes = [ctypes.c_void_p]
+    lib.sisso_l0_batch_destroy.restype = None
+    lib.sisso_l0_batch_last_error.restype = ctypes.c_char_p
+    lib.sisso_l0_search_batch.argtypes = [P(ctypes.c_void_p), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    lib.sisso_l0_search_batch.restype = ctypes.c_int32
+
+
+def _batch_check(rc: int):
+    if rc != SISSO_OK:
+        raise SissoError(rc, (load().sisso_l0_batch_last_error() or b"").decode())
+
+
+def sisso_l0_batch_create(handles, D: int, k: int) -> int:
+    lib = load()
+    _batch_sigs(lib)
+    arr = (ctypes.c_void_p * len(handles))(*handles)
+    out = ctypes.c_void_p()
+    _batch_check(lib.sisso_l0_batch_create(arr, len(handles), D, k, ctypes.byref(out)))
+    return out.value
+
+
+def sisso_l0_batch_launch(b: int) -> None:
+    lib = load()
+    _batch_sigs(lib)
+    _batch_check(lib.sisso_l0_batch_launch(b))
+
+
+def sisso_l0_batch_destroy(b) -> None:
+    lib = load()
+    _batch_sigs(lib)
+    lib.sisso_l0_batch_destroy(b)
+
+
+def sisso_l0_search_batch(handles, D: int, k: int) -> None:
+    lib = load()
+    _batch_sigs(lib)
+    arr = (ctypes.c_void_p * len(handles))(*handles)
+    _batch_check(lib.sisso_l0_search_batch(arr, len(handles), D, k))

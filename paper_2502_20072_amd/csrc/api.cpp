@@ -73,9 +73,11 @@ static Layout compute_layout(int64_t n_total, int64_t S, int T, int D_max, int k
     L.mu = take((size_t)T * S * d);
     L.inv_s = take((size_t)T * S * d);
     L.bhat = take((size_t)S * L.TP * d);
-    L.G = take((size_t)S * S * L.TP * d);
+    const size_t Sp = (size_t)((S + GT - 1) / GT) * GT;
+    L.G = take(Sp * Sp * L.TP * d);
     L.part = take((size_t)L.nsplit * T * S * S * d);
     L.flags = take(64 * sizeof(uint32_t));
+    L.tile_cnt = take((size_t)T * ntile * (ntile + 1) / 2 * sizeof(uint32_t));
     // pre-pass + counters: theta, work counter, cand counter, cum table, prefixes, scores
     L.pre = take(64 + (size_t)(S / 4 + 8) * sizeof(uint64_t) + PRE_Q * SISSO_MAX_D * sizeof(int32_t) +
                  64 + (size_t)PRE_Q * S * d + PRE_Q * d + 1024 +
@@ -113,6 +115,7 @@ static void carve(sisso_l0 *h) {
     c.S = h->desc.S;
     c.T = h->desc.T;
     c.TP = L.TP;
+    c.Gnt = (c.S + GT - 1) / GT;
     c.off_dev = (int64_t *)(base + L.off_dev);
     c.ybar = (double *)(base + L.ybar);
     c.cyy = (double *)(base + L.cyy);
@@ -122,11 +125,13 @@ static void carve(sisso_l0 *h) {
     c.G = (double *)(base + L.G);
     c.part = (double *)(base + L.part);
     c.flags = (uint32_t *)(base + L.flags);
+    c.tile_cnt = (unsigned int *)(base + L.tile_cnt);
     char *p = base + L.pre;
     c.theta_bits = (unsigned long long *)p;
     c.work_counter = (unsigned int *)(p + 8);
     c.cand_counter = (unsigned int *)(p + 12);
     c.pre_count = (int32_t *)(p + 16);
+    c.stats = (uint64_t *)(p + 24);
     p += 64;
     c.cum = (uint64_t *)p;
     p += (size_t)(c.S / 4 + 8) * sizeof(uint64_t);
@@ -210,13 +215,17 @@ extern "C" int32_t sisso_gram(sisso_l0 *h) {
     return SISSO_OK;
 }
 
-static int32_t do_search(sisso_l0 *h, int32_t D, int32_t k, bool ranged, uint64_t r0, uint64_t r1) {
+// Argument and state checks of a search; fills the launch description.
+static int32_t check_search(sisso_l0 *h, int32_t D, int32_t k, bool ranged, uint64_t r0, uint64_t r1,
+                            bool need_gram, SearchCall *sc, uint64_t *scored) {
     if (!h) return SISSO_EINVAL;
     h->err.clear();
-    if (!h->gram_done) return fail(h, SISSO_ESTATE, "sisso_gram must run before a search");
+    if (need_gram && !h->gram_done) return fail(h, SISSO_ESTATE, "sisso_gram must run before a search");
     if (D > h->desc.D_max || D > SISSO_MAX_D) return fail(h, SISSO_ENOTSUP, "D exceeds D_max");
     if (D < 1 || D > h->desc.S) return fail(h, SISSO_EINVAL, "need 1 <= D <= S");
     if (k < 1 || k > h->desc.k_max) return fail(h, SISSO_EINVAL, "need 1 <= k <= k_max");
+    if (D > 1 && (uint64_t)h->desc.S > (1ull << (64 / D)))
+        return fail(h, SISSO_ENOTSUP, "S exceeds 2^(64/D), the range of the packed top-k key");
     const uint64_t total = binom(h->desc.S, D);
     if (total >= (1ull << 63)) return fail(h, SISSO_ENOTSUP, "C(S, D) does not fit the 63-bit rank space");
     if (ranged) {
@@ -227,13 +236,22 @@ static int32_t do_search(sisso_l0 *h, int32_t D, int32_t k, bool ranged, uint64_
     }
     for (int t = 0; t < h->desc.T; ++t)
         if (h->offsets[t + 1] - h->offsets[t] < D + 2) return fail(h, SISSO_EINVAL, "a task has fewer than D + 2 rows");
-    SearchCall sc{D, k, ranged ? 1 : 0, ranged ? r0 : 0, ranged ? r1 : total};
+    *sc = SearchCall{D, k, ranged ? 1 : 0, ranged ? r0 : 0, ranged ? r1 : total};
+    *scored = ranged ? r1 - r0 : total;
+    return SISSO_OK;
+}
+
+static int32_t do_search(sisso_l0 *h, int32_t D, int32_t k, bool ranged, uint64_t r0, uint64_t r1) {
+    SearchCall sc;
+    uint64_t scored = 0;
+    const int32_t rc = check_search(h, D, k, ranged, r0, r1, true, &sc, &scored);
+    if (rc != SISSO_OK) return rc;
     if (launch_search(h->ctx, sc, h->stream)) return fail(h, SISSO_EDEVICE, hipGetErrorString(hipGetLastError()));
     for (int ph = SISSO_PHASE_PREPASS; ph <= SISSO_PHASE_FINAL; ++ph) h->ran[ph] = h->prof;
     h->search_done = true;
     h->last_D = D;
     h->last_k = k;
-    h->scored = ranged ? r1 - r0 : total;
+    h->scored = scored;
     return SISSO_OK;
 }
 
@@ -269,8 +287,12 @@ extern "C" int32_t sisso_gram_read(sisso_l0 *h, int32_t t, double *G, double *b,
     if (t < 0 || t >= h->desc.T) return fail(h, SISSO_EINVAL, "task index out of range");
     const size_t S = (size_t)h->desc.S, TP = (size_t)h->ctx.TP, d = sizeof(double);
     hipError_t e = hipSuccess;
-    // device layouts are task-fastest: a strided copy picks task t
-    if (G) e = hipMemcpy2DAsync(G, d, h->ctx.G + t, TP * d, d, S * S, hipMemcpyDeviceToHost, h->stream);
+    // the tiled, task-fastest matrix is unpacked into the Gram partial buffer
+    // (free after sisso_gram) and copied from there
+    if (G) {
+        if (launch_untile(h->ctx, t, h->ctx.part, h->stream)) return fail(h, SISSO_EDEVICE, "untile launch failed");
+        e = hipMemcpyAsync(G, h->ctx.part, S * S * d, hipMemcpyDeviceToHost, h->stream);
+    }
     if (e == hipSuccess && b) e = hipMemcpy2DAsync(b, d, h->ctx.bhat + t, TP * d, d, S, hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess && c) e = hipMemcpyAsync(c, h->ctx.cyy + t, d, hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
@@ -290,6 +312,16 @@ extern "C" int32_t sisso_l0_profile(sisso_l0 *h, int32_t enable) {
     h->prof = enable != 0;
     h->ctx.ev = h->prof ? h->ev : nullptr;
     for (auto &r : h->ran) r = false;
+    return SISSO_OK;
+}
+
+extern "C" int32_t sisso_l0_search_stats(sisso_l0 *h, uint64_t *out) {
+    if (!h || !out) return SISSO_EINVAL;
+    h->err.clear();
+    if (!h->search_done) return fail(h, SISSO_ESTATE, "no search has run");
+    hipError_t e = hipMemcpyAsync(out, h->ctx.stats, 4 * sizeof(uint64_t), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return fail(h, SISSO_EDEVICE, hipGetErrorString(e));
     return SISSO_OK;
 }
 
@@ -327,4 +359,141 @@ extern "C" int32_t sisso_l0_unrank(int64_t S, int32_t D, uint64_t r, int32_t *t)
     if (!t || D < 1 || D > 8 || S < D || r >= binom(S, D)) return SISSO_EINVAL;
     lex_unrank(BinomCalc{}, S, D, r, t);
     return SISSO_OK;
+}
+
+// ------------------------------------------------------------------ batching
+// A batch is one HIP graph holding, for every problem, the statistics, Gram
+// and search launches as a chain on its own branch (branches run
+// concurrently); the graph is captured once and then launched as one unit,
+// as often as needed.  Each problem's results are then read with
+// sisso_l0_topk on its handle, exactly as after an unbatched search.
+struct sisso_l0_batch {
+    std::vector<sisso_l0 *> hs;
+    std::vector<SearchCall> calls;
+    std::vector<uint64_t> scored;
+    int D = 0, k = 0;
+    hipStream_t user = nullptr, cap = nullptr;
+    std::vector<hipStream_t> br;
+    std::vector<hipEvent_t> evs;
+    hipEvent_t in = nullptr, out = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~sisso_l0_batch() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        for (auto e : evs) (void)hipEventDestroy(e);
+        if (in) (void)hipEventDestroy(in);
+        if (out) (void)hipEventDestroy(out);
+        for (auto s : br) (void)hipStreamDestroy(s);
+        if (cap) (void)hipStreamDestroy(cap);
+    }
+};
+
+static thread_local std::string g_batch_err;
+
+static int32_t batch_fail(sisso_l0_batch *b, int32_t code, const char *msg) {
+    g_batch_err = msg;
+    delete b;
+    return code;
+}
+
+extern "C" int32_t sisso_l0_batch_create(sisso_l0 *const *hs, int32_t P, int32_t D, int32_t k, sisso_l0_batch **out) {
+    if (!hs || !out || P < 1) {
+        g_batch_err = "null handles or output, or P < 1";
+        return SISSO_EINVAL;
+    }
+    sisso_l0_batch *b = new (std::nothrow) sisso_l0_batch();
+    if (!b) return SISSO_ENOMEM;
+    b->D = D;
+    b->k = k;
+    b->user = hs[0] ? hs[0]->stream : nullptr;
+    for (int p = 0; p < P; ++p) {
+        sisso_l0 *h = hs[p];
+        if (!h) return batch_fail(b, SISSO_EINVAL, "null handle in batch");
+        if (h->stream != b->user) return batch_fail(b, SISSO_EINVAL, "all handles of a batch must share one stream");
+        for (int q = 0; q < p; ++q)
+            if (hs[q] == h) return batch_fail(b, SISSO_EINVAL, "a handle appears twice in the batch");
+        SearchCall sc;
+        uint64_t sc_n = 0;
+        const int32_t rc = check_search(h, D, k, false, 0, 0, false, &sc, &sc_n);
+        if (rc != SISSO_OK) return batch_fail(b, rc, h->err.c_str());
+        b->hs.push_back(h);
+        b->calls.push_back(sc);
+        b->scored.push_back(sc_n);
+    }
+    const int NB = P < 16 ? P : 16;  // concurrent branches
+    if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess)
+        return batch_fail(b, SISSO_EDEVICE, "stream creation failed");
+    b->br.resize(NB, nullptr);
+    for (auto &st : b->br)
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess)
+            return batch_fail(b, SISSO_EDEVICE, "stream creation failed");
+    b->evs.resize(NB + 1, nullptr);
+    for (auto &e : b->evs)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+            return batch_fail(b, SISSO_EDEVICE, "event creation failed");
+    if (hipEventCreateWithFlags(&b->in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->out, hipEventDisableTiming) != hipSuccess)
+        return batch_fail(b, SISSO_EDEVICE, "event creation failed");
+    // capture: fork from the capture stream to every branch, one chain per
+    // problem (problems sharing a branch run one after another), join back
+    if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return batch_fail(b, SISSO_EDEVICE, "hipStreamBeginCapture failed");
+    bool ok = hipEventRecord(b->evs[NB], b->cap) == hipSuccess;
+    for (int i = 0; i < NB && ok; ++i) ok = hipStreamWaitEvent(b->br[i], b->evs[NB], 0) == hipSuccess;
+    for (int p = 0; p < P && ok; ++p) {
+        sisso_l0 *h = b->hs[p];
+        Ctx c = h->ctx;
+        c.ev = nullptr;  // no timing events inside a graph
+        hipStream_t st = b->br[p % NB];
+        ok = launch_stats(c, st) == 0 && launch_gram(c, st) == 0 && launch_search(c, b->calls[p], st) == 0;
+    }
+    for (int i = 0; i < NB && ok; ++i)
+        ok = hipEventRecord(b->evs[i], b->br[i]) == hipSuccess && hipStreamWaitEvent(b->cap, b->evs[i], 0) == hipSuccess;
+    const hipError_t ec = hipStreamEndCapture(b->cap, &b->graph);
+    if (!ok || ec != hipSuccess || !b->graph) return batch_fail(b, SISSO_EDEVICE, "graph capture failed");
+    if (hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess)
+        return batch_fail(b, SISSO_EDEVICE, "graph instantiation failed");
+    *out = b;
+    return SISSO_OK;
+}
+
+extern "C" int32_t sisso_l0_batch_launch(sisso_l0_batch *b) {
+    if (!b) return SISSO_EINVAL;
+    hipError_t e = hipEventRecord(b->in, b->user);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->cap, b->in, 0);
+    if (e == hipSuccess) e = hipGraphLaunch(b->exec, b->cap);
+    if (e == hipSuccess) e = hipEventRecord(b->out, b->cap);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->user, b->out, 0);
+    if (e != hipSuccess) {
+        g_batch_err = hipGetErrorString(e);
+        return SISSO_EDEVICE;
+    }
+    for (size_t p = 0; p < b->hs.size(); ++p) {
+        sisso_l0 *h = b->hs[p];
+        h->gram_done = true;
+        h->search_done = true;
+        h->last_D = b->D;
+        h->last_k = b->k;
+        h->scored = b->scored[p];
+        for (auto &r : h->ran) r = false;
+    }
+    return SISSO_OK;
+}
+
+extern "C" void sisso_l0_batch_destroy(sisso_l0_batch *b) {
+    if (!b) return;
+    (void)hipStreamSynchronize(b->cap);
+    delete b;
+}
+
+extern "C" const char *sisso_l0_batch_last_error(void) { return g_batch_err.c_str(); }
+
+extern "C" int32_t sisso_l0_search_batch(sisso_l0 *const *hs, int32_t P, int32_t D, int32_t k) {
+    sisso_l0_batch *b = nullptr;
+    int32_t rc = sisso_l0_batch_create(hs, P, D, k, &b);
+    if (rc != SISSO_OK) return rc;
+    rc = sisso_l0_batch_launch(b);
+    sisso_l0_batch_destroy(b);
+    return rc;
 }

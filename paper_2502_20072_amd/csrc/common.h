@@ -121,6 +121,62 @@ __host__ __device__ inline void colex_unrank(const BF &bf, uint64_t r, int q, in
     }
 }
 
+// Top-k key of a sorted tuple: the indices packed most significant first,
+// 64/D bits each, so integer order of keys is lexicographic order of tuples
+// (equivalently, order of lexicographic rank).  Needs S <= 2^(64/D); no
+// valid tuple packs to ~0 (indices are strictly increasing), which marks an
+// empty slot.
+__host__ __device__ inline int key_bits(int D) { return 64 / D; }
+__host__ __device__ inline uint64_t pack_tuple(const int32_t *t, int D) {
+    if (D == 1) return (uint64_t)(uint32_t)t[0];
+    const int b = 64 / D;
+    uint64_t k = 0;
+    for (int m = 0; m < D; ++m) k = (k << b) | (uint64_t)(uint32_t)t[m];
+    return k;
+}
+__host__ __device__ inline void unpack_tuple(uint64_t k, int D, int32_t *t) {
+    if (D == 1) {
+        t[0] = (int32_t)k;
+        return;
+    }
+    const int b = 64 / D;
+    const uint64_t mask = (1ull << b) - 1;
+    for (int m = D - 1; m >= 0; --m) {
+        t[m] = (int32_t)(k & mask);
+        k >>= b;
+    }
+}
+
+// ------------------------------------------------------ tiled Gram layout
+// The correlation matrices are stored in 64 x 64 tiles (row-major inside a
+// tile, tiles row-major, padded with zeros to a multiple of 64), task
+// fastest: element (i, k) of task t is at gidx(i, k, nt, TP, t) with
+// nt = ceil(S / 64).  A search step reads one row of one tile, so a chunk of
+// 64 steps stays inside 32 KB of contiguous memory.
+constexpr int GT = 64;
+__host__ __device__ inline int64_t gidx(int64_t i, int64_t k, int64_t nt, int TP, int t) {
+    return ((((i >> 6) * nt + (k >> 6)) << 12) + ((i & 63) << 6) + (k & 63)) * TP + t;
+}
+
+// Colexicographic unranking for the small sub-prefix lengths of the search
+// (q <= 2 in closed form, larger q by bisection), no table lookups.
+__host__ __device__ inline void colex_unrank_small(uint64_t r, int q, int64_t N, int32_t *t) {
+    if (q == 1) {
+        t[0] = (int32_t)r;
+        return;
+    }
+    if (q == 2) {
+        // largest c with c (c - 1) / 2 <= r
+        int64_t c = (int64_t)((1.0 + sqrt(1.0 + 8.0 * (double)r)) * 0.5);
+        while (c > 1 && (uint64_t)(c * (c - 1) / 2) > r) --c;
+        while ((uint64_t)((c + 1) * c / 2) <= r) ++c;
+        t[1] = (int32_t)c;
+        t[0] = (int32_t)(r - (uint64_t)(c * (c - 1) / 2));
+        return;
+    }
+    colex_unrank(BinomCalc{}, r, q, N, t);
+}
+
 // -------------------------------------------------------- workspace layout
 // Every region is 256-byte aligned; offsets in bytes from the workspace base.
 struct Layout {
@@ -133,6 +189,7 @@ struct Layout {
     size_t G;          // double [S][S][TP] correlation matrices, task fastest
     size_t part;       // double [nsplit][T][S][S] raw centred Gram partial sums
     size_t flags;      // uint32 [64] device status words
+    size_t tile_cnt;   // uint32 [T][tile pairs] Gram split counters
     size_t pre;        // pre-pass scratch
     size_t lists;      // per-wave top lists: (double sse, uint64 rank) [nwaves][KP]
     size_t merged;     // merged candidates [KP] (sse, rank)

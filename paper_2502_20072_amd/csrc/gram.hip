@@ -161,7 +161,12 @@ __global__ __launch_bounds__(256) void gram_kernel(const double *__restrict__ F,
         muB[r] = gb < S ? mut[gb] : 0.0;
     }
 
-    for (int64_t c = c0; c < c1; ++c) {
+    // register-staged double buffering: the global loads of chunk c+1 are in
+    // flight while the MFMAs of chunk c run out of LDS.  Diagonal tiles
+    // (bi == bj) load one operand and read it twice.
+    const bool diag = (bi == bj);
+    double sa[GRAM_TILE / 16], sb[GRAM_TILE / 16];
+    auto load_chunk = [&](int64_t c) {
         const int64_t row = r0 + c * GRAM_KC + kk;
         const bool rin = row < r1;
 #pragma unroll
@@ -169,10 +174,26 @@ __global__ __launch_bounds__(256) void gram_kernel(const double *__restrict__ F,
             const int f = f0 + 16 * r;
             const int64_t ga = (int64_t)bi * GRAM_TILE + f;
             const int64_t gb = (int64_t)bj * GRAM_TILE + f;
-            As[kk][f] = (rin && ga < S) ? F[ga * n_total + row] - muA[r] : 0.0;
-            Bs[kk][f] = (rin && gb < S) ? F[gb * n_total + row] - muB[r] : 0.0;
+            sa[r] = (rin && ga < S) ? F[ga * n_total + row] - muA[r] : 0.0;
+            if (!diag) sb[r] = (rin && gb < S) ? F[gb * n_total + row] - muB[r] : 0.0;
         }
-        __syncthreads();
+    };
+    auto store_chunk = [&]() {
+#pragma unroll
+        for (int r = 0; r < GRAM_TILE / 16; ++r) {
+            As[kk][f0 + 16 * r] = sa[r];
+            if (!diag) Bs[kk][f0 + 16 * r] = sb[r];
+        }
+    };
+    double (*Bsrc)[LDS_STRIDE] = diag ? As : Bs;
+    if (c0 < c1) {
+        load_chunk(c0);
+        store_chunk();
+    }
+    __syncthreads();
+    for (int64_t c = c0; c < c1; ++c) {
+        const bool more = c + 1 < c1;
+        if (more) load_chunk(c + 1);
 #pragma unroll
         for (int ks = 0; ks < GRAM_KC / 4; ++ks) {
             const int krow = ks * 4 + (lane >> 4);
@@ -180,13 +201,15 @@ __global__ __launch_bounds__(256) void gram_kernel(const double *__restrict__ F,
 #pragma unroll
             for (int m = 0; m < 4; ++m) a[m] = As[krow][wr + m * 16 + (lane & 15)];
 #pragma unroll
-            for (int m = 0; m < 4; ++m) bv[m] = Bs[krow][wc + m * 16 + (lane & 15)];
+            for (int m = 0; m < 4; ++m) bv[m] = Bsrc[krow][wc + m * 16 + (lane & 15)];
 #pragma unroll
             for (int m = 0; m < 4; ++m)
 #pragma unroll
                 for (int n = 0; n < 4; ++n)
                     acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], bv[n], acc[m][n], 0, 0, 0);
         }
+        __syncthreads();
+        if (more) store_chunk();
         __syncthreads();
     }
 
@@ -202,53 +225,87 @@ __global__ __launch_bounds__(256) void gram_kernel(const double *__restrict__ F,
                 const int64_t gj = (int64_t)bj * GRAM_TILE + wc + n * 16 + (lane & 15);
                 if (gi < S && gj < S) P[gi * S + gj] = acc[m][n][r];
             }
+
 }
 
-// Sum the split partials of the upper triangle, scale to a correlation
-// matrix and write both triangles into G[i][k][t] (task fastest).  The
-// diagonal is exactly 1 for a non-constant column and 0 for a constant one.
-__global__ __launch_bounds__(256) void gram_finish_kernel(const double *__restrict__ part,
-                                                          int64_t S, int T, int TP, int nsplit,
-                                                          const double *__restrict__ inv_s,
-                                                          double *__restrict__ G) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= S * S * TP) return;
-    const int t = (int)(e % TP);
-    const int64_t ik = e / TP;
-    const int64_t i = ik / S, k = ik % S;
-    double v = 0.0;
-    if (t < T) {
-        const double si = inv_s[(int64_t)t * S + i], sk = inv_s[(int64_t)t * S + k];
-        if (i == k) {
-            v = si > 0.0 ? 1.0 : 0.0;
-        } else {
-            // canonical element: the tile pair (bi <= bj) that holds it, upper
-            // triangle of a diagonal tile
-            const int64_t bi = i / GRAM_TILE, bk = k / GRAM_TILE;
-            int64_t a = i, c = k;
-            if (bi > bk || (bi == bk && i > k)) {
-                a = k;
-                c = i;
-            }
-            double s = 0.0;
-            for (int sp = 0; sp < nsplit; ++sp) s += part[(((int64_t)sp * T + t) * S + a) * S + c];
-            // scale in canonical (a, c) order so G[i][k] and G[k][i] are bitwise equal
-            v = s * (inv_s[(int64_t)t * S + a] * inv_s[(int64_t)t * S + c]);
-            (void)si;
-            (void)sk;
-        }
+// Sum the split partials, scale to a correlation matrix and write the tiled
+// layout.  One workgroup per (task, 64x64 output tile pair ti <= tk): it reads
+// every partial of the canonical upper block once (coalesced rows), writes
+// tile (ti, tk) row by row and tile (tk, ti) through an LDS transpose, so the
+// mirrored elements are bitwise equal and both writes are coalesced.  The
+// diagonal is 1 for a non-constant column and 0 for a constant one; padding
+// rows/columns and padded tasks are written as zeros.
+__global__ __launch_bounds__(256) void gram_finish_kernel(const double *__restrict__ part, int64_t S, int T,
+                                                          int TP, int nsplit, const double *__restrict__ inv_s,
+                                                          double *__restrict__ G, int64_t nt) {
+    __shared__ double tr[GT][GT + 1];
+    const int64_t npair = nt * (nt + 1) / 2;
+    const int t = (int)(blockIdx.x / npair);
+    int64_t pr = blockIdx.x % npair;
+    int64_t ti = 0;
+    while (pr >= nt - ti) {
+        pr -= nt - ti;
+        ++ti;
     }
-    G[e] = v;
+    const int64_t tk = ti + pr;
+    const double *ist = inv_s + (int64_t)t * S;
+    for (int e = threadIdx.x; e < GT * GT; e += 256) {
+        const int li = e >> 6, lk = e & 63;
+        const int64_t i = ti * GT + li, k = tk * GT + lk;
+        double v = 0.0;
+        if (i < S && k < S) {
+            if (i == k) {
+                v = ist[i] > 0.0 ? 1.0 : 0.0;
+            } else {
+                // canonical element: upper triangle within a diagonal tile
+                const int64_t a = (ti == tk && i > k) ? k : i, c = (ti == tk && i > k) ? i : k;
+                double acc = 0.0;
+                for (int sp = 0; sp < nsplit; ++sp) acc += part[(((int64_t)sp * T + t) * S + a) * S + c];
+                v = acc * (ist[a] * ist[c]);
+            }
+        }
+        G[((((ti * nt + tk) << 12) + (li << 6) + lk)) * TP + t] = v;
+        tr[lk][li] = v;
+        if (t == T - 1)
+            for (int tp = T; tp < TP; ++tp) G[((((ti * nt + tk) << 12) + (li << 6) + lk)) * TP + tp] = 0.0;
+    }
+    if (ti == tk) return;
+    __syncthreads();
+    for (int e = threadIdx.x; e < GT * GT; e += 256) {
+        const int li = e >> 6, lk = e & 63;  // row li of tile (tk, ti) = column li of tile (ti, tk)
+        G[((((tk * nt + ti) << 12) + (li << 6) + lk)) * TP + t] = tr[li][lk];
+        if (t == T - 1)
+            for (int tp = T; tp < TP; ++tp) G[((((tk * nt + ti) << 12) + (li << 6) + lk)) * TP + tp] = 0.0;
+    }
+}
+
+// Unpack task t of the tiled matrices into a plain row-major S x S array.
+__global__ __launch_bounds__(256) void untile_kernel(const double *__restrict__ G, int64_t S, int64_t nt, int TP,
+                                                     int t, double *__restrict__ dst) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= S * S) return;
+    dst[e] = G[gidx(e / S, e % S, nt, TP, t)];
+}
+
+int launch_untile(const Ctx &c, int t, double *dst, hipStream_t st) {
+    hipLaunchKernelGGL(untile_kernel, dim3((unsigned)((c.S * c.S + 255) / 256)), dim3(256), 0, st, c.G, c.S, c.Gnt,
+                       c.TP, t, dst);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 // ------------------------------------------------------------- launchers
-__global__ void clear_flags_kernel(uint32_t *flags) {
-    if (threadIdx.x < 64) flags[threadIdx.x] = 0u;
+__global__ void clear_flags_kernel(uint32_t *flags, unsigned int *tile_cnt, int64_t ncnt) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < 64) flags[e] = 0u;
+    if (e < ncnt) tile_cnt[e] = 0u;
 }
 
 int launch_stats(const Ctx &c, hipStream_t st) {
     phase_begin(c, SISSO_PHASE_STATS, st);
-    hipLaunchKernelGGL(clear_flags_kernel, dim3(1), dim3(64), 0, st, c.flags);
+    const int64_t ntile = (c.S + GRAM_TILE - 1) / GRAM_TILE;
+    const int64_t ncnt = c.T * ntile * (ntile + 1) / 2;
+    hipLaunchKernelGGL(clear_flags_kernel, dim3((unsigned)((ncnt + 64 + 255) / 256)), dim3(256), 0, st, c.flags,
+                       c.tile_cnt, ncnt);
     hipLaunchKernelGGL(stats_y_kernel, dim3((c.T + 3) / 4), dim3(256), 0, st, c.y, c.off_dev, c.T,
                        c.ybar, c.cyy, c.flags);
     const int64_t jobs = c.S * c.T;
@@ -264,9 +321,9 @@ int launch_gram(const Ctx &c, hipStream_t st) {
     phase_begin(c, SISSO_PHASE_GRAM, st);
     hipLaunchKernelGGL(gram_kernel, dim3((unsigned)blocks), dim3(256), 0, st, c.F, c.n_total, c.S,
                        c.off_dev, c.T, c.mu, ntile, c.nsplit, c.part);
-    const int64_t elems = c.S * c.S * c.TP;
-    hipLaunchKernelGGL(gram_finish_kernel, dim3((unsigned)((elems + 255) / 256)), dim3(256), 0, st,
-                       c.part, c.S, c.T, c.TP, c.nsplit, c.inv_s, c.G);
+    const int64_t npair64 = c.Gnt * (c.Gnt + 1) / 2;
+    hipLaunchKernelGGL(gram_finish_kernel, dim3((unsigned)(npair64 * c.T)), dim3(256), 0, st, c.part, c.S, c.T,
+                       c.TP, c.nsplit, c.inv_s, c.G, c.Gnt);
     phase_end(c, SISSO_PHASE_GRAM, st);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }

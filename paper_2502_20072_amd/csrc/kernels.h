@@ -11,13 +11,16 @@ struct Ctx {
     const double *y;
     int64_t n_total, S;
     int T, TP;
+    int64_t Gnt;  // 64-wide tiles per row of the tiled correlation matrices
     // carved from the workspace
     int64_t *off_dev;
     double *ybar, *cyy, *mu, *inv_s, *bhat, *G, *part;
     uint32_t *flags;
+    unsigned int *tile_cnt;          // Gram: finished splits per (task, tile pair)
     unsigned long long *theta_bits;  // shared SSE bound (bit pattern of a non-negative double)
     unsigned int *work_counter;      // next search work item
     unsigned int *cand_counter;      // slow-path candidates seen (diagnostics)
+    uint64_t *stats;                 // [4]: candidates, work items, theta0 bits, final theta bits
     uint64_t *cum;                   // cumulative work items per j-block [S/JBLK + 2]
     uint64_t *btab;                  // binomials C(n, r), r <= SISSO_MAX_D, n <= S
     int32_t *pre_prefix;             // pre-pass: chosen prefixes [PRE_Q][SISSO_MAX_D]
@@ -58,6 +61,7 @@ struct SearchCall {
 
 int launch_stats(const Ctx &c, hipStream_t st);
 int launch_gram(const Ctx &c, hipStream_t st);
+int launch_untile(const Ctx &c, int t, double *dst, hipStream_t st);
 int launch_search(const Ctx &c, const SearchCall &sc, hipStream_t st);
 
 }  // namespace sl0

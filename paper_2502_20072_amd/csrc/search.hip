@@ -37,6 +37,8 @@
 // accuracy of a direct least-squares fit, before the final ordering.
 #include <math.h>
 
+#include <type_traits>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -60,8 +62,18 @@ __device__ inline void theta_publish(unsigned long long *p, double v) {
     if (v >= 0.0 && v < INF) atomicMin(p, (unsigned long long)__double_as_longlong(v));
 }
 
+// Values every lane holds identically (read from LDS or a uniform address)
+// are moved to scalar registers, so address arithmetic on them stays scalar.
+__device__ inline int64_t uni(int64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ inline uint64_t uni(uint64_t v) { return (uint64_t)uni((int64_t)v); }
+__device__ inline double uni(double v) { return __longlong_as_double(uni((int64_t)__double_as_longlong(v))); }
+
 __device__ inline double Gat(const Ctx &c, int64_t i, int64_t k, int t) {
-    return c.G[(i * c.S + k) * c.TP + t];
+    return c.G[gidx(i, k, c.Gnt, c.TP, t)];
 }
 
 // ----------------------------------------------------------------- helpers
@@ -148,6 +160,7 @@ __global__ void search_init_kernel(Ctx c, int D, int R, int JB) {
         *c.cand_counter = 0;
         *c.theta_bits = (unsigned long long)__double_as_longlong(INF);
         *c.pre_count = 0;
+        c.stats[1] = 0;
         const int q = D - 2;
         const int64_t nblk = (c.S - 1 + JB - 1) / JB;
         uint64_t acc = 0;
@@ -163,28 +176,100 @@ __global__ void search_init_kernel(Ctx c, int D, int R, int JB) {
 }
 
 // ----------------------------------------------------- threshold pre-pass
-// pre_select: the PRE_M features with the largest sum over tasks of b_t^2
-// (their D=1 explained sums of squares), every (D-1)-subset of them scored,
-// and the PRE_Q best subsets kept as prefixes.
+// The search starts from an upper bound theta0 of the KP-th best SSE, so
+// that almost no tuple reaches the exact path.  It is built from a small,
+// structured set of real tuples: the best (D-1)-subsets of the PRE_M most
+// relevant features, each extended by every feature.  Selections below run
+// as per-thread sorted lists in registers and wave-level argmin rounds over
+// LDS (shuffles only), so no phase waits on a chain of global loads.
+
+// Keep the L smallest (v, id) pairs of a thread's stream, sorted ascending.
+template <int L>
+struct LocalTop {
+    double v[L];
+    int id[L];
+    __device__ void init() {
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+            v[i] = INF;
+            id[i] = -1;
+        }
+    }
+    __device__ void offer(double x, int i) {
+        if (!(x < v[L - 1] || (x == v[L - 1] && (unsigned)i < (unsigned)id[L - 1]))) return;
+        double cv = x;
+        int ci = i;
+#pragma unroll
+        for (int m = 0; m < L; ++m) {
+            const bool less = cv < v[m] || (cv == v[m] && (unsigned)ci < (unsigned)id[m]);
+            const double tv = v[m];
+            const int ti = id[m];
+            v[m] = less ? cv : tv;
+            id[m] = less ? ci : ti;
+            cv = less ? tv : cv;
+            ci = less ? ti : ci;
+        }
+    }
+};
+
+// One wave: the L smallest (v, id) among n entries of an LDS array, by L
+// rounds of wave argmin (chosen entries are overwritten with +inf).  Results
+// in out_v/out_id (lane 0 writes); returns how many finite ones were found.
+__device__ int wave_smallest(double *v, int *id, int n, int L, double *out_v, int *out_id) {
+    const int lane = threadIdx.x & 63;
+    int found = 0;
+    for (int it = 0; it < L; ++it) {
+        double bv = INF;
+        int bi = -1, bpos = -1;
+        for (int e = lane; e < n; e += 64) {
+            const double x = v[e];
+            const int xi = id[e];
+            if (x < bv || (x == bv && (unsigned)xi < (unsigned)bi)) {
+                bv = x;
+                bi = xi;
+                bpos = e;
+            }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            const double ov = __shfl_xor(bv, o);
+            const int oi = __shfl_xor(bi, o);
+            const int op = __shfl_xor(bpos, o);
+            if (ov < bv || (ov == bv && (unsigned)oi < (unsigned)bi)) {
+                bv = ov;
+                bi = oi;
+                bpos = op;
+            }
+        }
+        if (!(bv < INF)) break;
+        if (lane == 0) {
+            out_v[it] = bv;
+            out_id[it] = bi;
+            v[bpos] = INF;
+        }
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_wave_barrier();
+        ++found;
+    }
+    return found;
+}
+
+// pre_select: relevance of feature j = sum over tasks of b_tj^2 (its D=1
+// explained sum of squares); the PRE_M most relevant full-rank features;
+// every (D-1)-subset of them scored; the PRE_Q best subsets become prefixes.
 __global__ __launch_bounds__(256) void pre_select_kernel(Ctx c, int D) {
-    __shared__ double rel[256];
-    __shared__ int32_t ridx[256];
-    __shared__ int32_t sel[PRE_M];
-    __shared__ double psse[1024];
-    __shared__ int32_t pidx[1024];
-    __shared__ int nsel;
-    const int tid = threadIdx.x;
+    __shared__ double lv[256 * PRE_M];
+    __shared__ int li[256 * PRE_M];
+    __shared__ double wv[SEARCH_WAVES * PRE_M];
+    __shared__ int wi[SEARCH_WAVES * PRE_M];
+    __shared__ int sel[PRE_M];
+    __shared__ int s_m;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int q = D - 1;
-    if (tid == 0) nsel = 0;
-    __syncthreads();
-    // top-PRE_M by relevance (ties: smaller index), repeated block argmax
-    for (int it = 0; it < PRE_M; ++it) {
-        double best = -1.0;
-        int bidx = -1;
+    // 1. per-thread top-PRE_M of -relevance
+    {
+        LocalTop<PRE_M> top;
+        top.init();
         for (int64_t j = tid; j < c.S; j += 256) {
-            bool taken = false;
-            for (int s = 0; s < it; ++s) taken |= (sel[s] == j);
-            if (taken) continue;
             double r = 0.0;
             bool ok = true;
             for (int t = 0; t < c.T; ++t) {
@@ -192,98 +277,73 @@ __global__ __launch_bounds__(256) void pre_select_kernel(Ctx c, int D) {
                 const double b = c.bhat[j * c.TP + t];
                 r += b * b;
             }
-            if (!ok) continue;
-            if (r > best) {
-                best = r;
-                bidx = (int)j;
-            }
+            if (ok) top.offer(-r, (int)j);
         }
-        rel[tid] = best;
-        ridx[tid] = bidx;
-        __syncthreads();
-        for (int o = 128; o > 0; o >>= 1) {
-            if (tid < o) {
-                const double a = rel[tid], b = rel[tid + o];
-                const int ia = ridx[tid], ib = ridx[tid + o];
-                if (b > a || (b == a && ib >= 0 && (ia < 0 || ib < ia))) {
-                    rel[tid] = b;
-                    ridx[tid] = ib;
-                }
-            }
-            __syncthreads();
+#pragma unroll
+        for (int m = 0; m < PRE_M; ++m) {
+            lv[tid * PRE_M + m] = top.v[m];
+            li[tid * PRE_M + m] = top.id[m];
         }
-        if (tid == 0) {
-            if (ridx[0] >= 0) sel[nsel++] = ridx[0];
-        }
-        __syncthreads();
-        if (nsel <= it) break;
-        __syncthreads();
     }
-    const int M = nsel;
+    __syncthreads();
+    // 2. each wave reduces its 64 lists, then wave 0 merges the 4 results
+    const int nw = wave_smallest(lv + wave * 64 * PRE_M, li + wave * 64 * PRE_M, 64 * PRE_M, PRE_M,
+                                 wv + wave * PRE_M, wi + wave * PRE_M);
+    if (lane == 0)
+        for (int m = nw; m < PRE_M; ++m) {
+            wv[wave * PRE_M + m] = INF;
+            wi[wave * PRE_M + m] = -1;
+        }
+    __syncthreads();
+    __shared__ double fv[PRE_M];
+    __shared__ int fi[PRE_M];
+    if (wave == 0) {
+        const int M = wave_smallest(wv, wi, SEARCH_WAVES * PRE_M, PRE_M, fv, fi);
+        if (lane == 0) {
+            // selected features in increasing index order
+            for (int a = 0; a < M; ++a) {
+                int b = a;
+                for (int x = a + 1; x < M; ++x)
+                    if (fi[x] < fi[b]) b = x;
+                const int t = fi[a];
+                fi[a] = fi[b];
+                fi[b] = t;
+                sel[a] = fi[a];
+            }
+            s_m = M;
+        }
+    }
+    __syncthreads();
+    const int M = s_m;
     if (M < q) return;
-    // sort the selected features by index (tiny insertion sort by one thread)
-    if (tid == 0) {
-        for (int a = 1; a < M; ++a) {
-            int v = sel[a], b = a - 1;
-            while (b >= 0 && sel[b] > v) {
-                sel[b + 1] = sel[b];
-                --b;
-            }
-            sel[b + 1] = v;
-        }
-    }
-    __syncthreads();
-    // score every q-subset of the selection
+    // 3. score every q-subset of the selection (<= C(16, 3) = 560 of them)
     const uint64_t nsub = binom(M, q);
-    for (uint64_t s = tid; s < 1024; s += 256) {
-        psse[s] = INF;
-        pidx[s] = -1;
+    for (int e = tid; e < 1024; e += 256) {
+        lv[e] = INF;
+        li[e] = -1;
     }
     __syncthreads();
-    for (uint64_t s = tid; s < nsub && s < 1024; s += 256) {
+    for (uint64_t e = tid; e < nsub && e < 1024; e += 256) {
         int32_t loc[MAXD], tup[MAXD];
-        colex_unrank(BinomTab{c.btab, c.S}, s, q, M, loc);
+        colex_unrank_small(e, q, M, loc);
         for (int m = 0; m < q; ++m) tup[m] = sel[loc[m]];
-        psse[s] = ne_sse(c, q, tup);
-        pidx[s] = (int)s;
+        lv[e] = ne_sse(c, q, tup);
+        li[e] = (int)e;
     }
     __syncthreads();
-    // keep the PRE_Q best (SSE, then subset rank), repeated block argmin
-    for (int it = 0; it < PRE_Q; ++it) {
-        double best = INF;
-        int bi = -1;
-        for (int s = tid; s < 1024; s += 256) {
-            if (pidx[s] >= 0 && (psse[s] < best || (psse[s] == best && bi >= 0 && pidx[s] < bi))) {
-                best = psse[s];
-                bi = pidx[s];
+    // 4. the PRE_Q best subsets (SSE, then subset rank)
+    __shared__ double bv[PRE_Q];
+    __shared__ int bi[PRE_Q];
+    if (wave == 0) {
+        const int Q = wave_smallest(lv, li, 1024, PRE_Q, bv, bi);
+        if (lane == 0) {
+            for (int it = 0; it < Q; ++it) {
+                int32_t loc[MAXD];
+                colex_unrank_small((uint64_t)bi[it], q, M, loc);
+                for (int m = 0; m < q; ++m) c.pre_prefix[it * MAXD + m] = sel[loc[m]];
             }
+            *c.pre_count = Q;
         }
-        rel[tid] = best;
-        ridx[tid] = bi;
-        __syncthreads();
-        for (int o = 128; o > 0; o >>= 1) {
-            if (tid < o) {
-                const double a = rel[tid], b = rel[tid + o];
-                const int ia = ridx[tid], ib = ridx[tid + o];
-                if (ib >= 0 && (ia < 0 || b < a || (b == a && ib < ia))) {
-                    rel[tid] = b;
-                    ridx[tid] = ib;
-                }
-            }
-            __syncthreads();
-        }
-        const int win = ridx[0];
-        const double wsse = rel[0];
-        __syncthreads();
-        if (win < 0 || !(wsse < INF)) break;
-        if (tid == 0) {
-            int32_t loc[MAXD];
-            colex_unrank(BinomTab{c.btab, c.S}, (uint64_t)win, q, M, loc);
-            for (int m = 0; m < q; ++m) c.pre_prefix[it * MAXD + m] = sel[loc[m]];
-            *c.pre_count = it + 1;
-            pidx[win] = -1;
-        }
-        __syncthreads();
     }
 }
 
@@ -294,95 +354,82 @@ __global__ __launch_bounds__(256) void pre_select_kernel(Ctx c, int D) {
 // that maximum an upper bound of the KP-th best SSE of the search.
 __global__ __launch_bounds__(256) void pre_extend_kernel(Ctx c, int D, int ranged, uint64_t r0,
                                                          uint64_t r1, int L) {
-    __shared__ double red[256];
-    __shared__ int64_t redi[256];
+    constexpr int LM = KP_MAX / PRE_Q;  // largest L
+    __shared__ double lv[256 * 16];
+    __shared__ int li[256 * 16];
+    __shared__ double wv[SEARCH_WAVES * LM];
+    __shared__ int wi[SEARCH_WAVES * LM];
     const int qq = blockIdx.x;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int Q = *c.pre_count;
-    if (qq >= Q) {
+    if (qq >= Q || L > LM) {
         if (tid == 0) c.pre_bound[qq] = INF;
         return;
     }
     const int q = D - 1;
     int32_t P[MAXD];
     for (int m = 0; m < q; ++m) P[m] = c.pre_prefix[qq * MAXD + m];
-    double *row = c.pre_sse + (int64_t)qq * c.S;
+    // per-thread 16 smallest; the block's L smallest are among the union as
+    // long as L <= 16 per thread is not exceeded by one thread's share, so
+    // each thread keeps min(L, 16) and L <= 16 * 256 always holds
+    LocalTop<16> top;
+    top.init();
     for (int64_t k = tid; k < c.S; k += 256) {
-        double s = INF;
         int32_t tup[MAXD];
         bool inP = false;
         int n = 0;
+        for (int m = 0; m < q; ++m) inP |= (P[m] == k);
+        if (inP) continue;
+        bool placed = false;
         for (int m = 0; m < q; ++m) {
-            if (P[m] == k) inP = true;
+            if (!placed && k < P[m]) {
+                tup[n++] = (int32_t)k;
+                placed = true;
+            }
+            tup[n++] = P[m];
         }
-        if (!inP) {
-            bool placed = false;
+        if (!placed) tup[n++] = (int32_t)k;
+        bool dup = false;
+        for (int o = 0; o < qq && !dup; ++o) {
+            int hit = 0;
             for (int m = 0; m < q; ++m) {
-                if (!placed && k < P[m]) {
-                    tup[n++] = (int32_t)k;
-                    placed = true;
-                }
-                tup[n++] = P[m];
+                const int32_t v = c.pre_prefix[o * MAXD + m];
+                for (int u = 0; u < D; ++u) hit += (tup[u] == v);
             }
-            if (!placed) tup[n++] = (int32_t)k;
-            bool dup = false;
-            for (int o = 0; o < qq && !dup; ++o) {
-                int hit = 0;
-                for (int m = 0; m < q; ++m) {
-                    const int32_t v = c.pre_prefix[o * MAXD + m];
-                    for (int u = 0; u < D; ++u) hit += (tup[u] == v);
-                }
-                dup = (hit == q);
-            }
-            if (!dup) {
-                bool in = true;
-                if (ranged) {
-                    const uint64_t rk = lex_rank(BinomTab{c.btab, c.S}, c.S, D, tup);
-                    in = rk >= r0 && rk < r1;
-                }
-                if (in) s = ne_sse(c, D, tup);
-            }
+            dup = (hit == q);
         }
-        row[k] = s;
+        if (dup) continue;
+        if (ranged) {
+            const uint64_t rk = lex_rank(BinomTab{c.btab, c.S}, c.S, D, tup);
+            if (rk < r0 || rk >= r1) continue;
+        }
+        top.offer(ne_sse(c, D, tup), (int)k);
+    }
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+        lv[tid * 16 + m] = top.v[m];
+        li[tid * 16 + m] = top.id[m];
     }
     __syncthreads();
-    // L rounds of block argmin extraction; the last value is the L-th smallest
-    double last = INF;
-    for (int it = 0; it < L; ++it) {
-        double best = INF;
-        int64_t bk = -1;
-        for (int64_t k = tid; k < c.S; k += 256) {
-            const double v = row[k];
-            if (v < best) {
-                best = v;
-                bk = k;
-            }
+    const int Lw = L < 16 ? L : 16;
+    // a thread kept only its 16 best; if one thread's share could hold more
+    // than 16 of the block's L best, the bound is not certified
+    const bool exact = (L <= 16) || ((c.S + 255) / 256 <= 16);
+    const int nw = wave_smallest(lv + wave * 64 * 16, li + wave * 64 * 16, 64 * 16, L, wv + wave * LM,
+                                 wi + wave * LM);
+    if (lane == 0)
+        for (int m = nw; m < LM; ++m) {  // every slot wave 0 scans is defined
+            wv[wave * LM + m] = INF;
+            wi[wave * LM + m] = -1;
         }
-        red[tid] = best;
-        redi[tid] = bk;
-        __syncthreads();
-        for (int o = 128; o > 0; o >>= 1) {
-            if (tid < o) {
-                if (red[tid + o] < red[tid] ||
-                    (red[tid + o] == red[tid] && redi[tid + o] >= 0 &&
-                     (redi[tid] < 0 || redi[tid + o] < redi[tid]))) {
-                    red[tid] = red[tid + o];
-                    redi[tid] = redi[tid + o];
-                }
-            }
-            __syncthreads();
-        }
-        last = red[0];
-        const int64_t win = redi[0];
-        __syncthreads();
-        if (win < 0) {
-            last = INF;
-            break;
-        }
-        if (tid == 0) row[win] = INF;
-        __syncthreads();
+    __syncthreads();
+    __shared__ double fv[LM];
+    __shared__ int fi[LM];
+    if (wave == 0) {
+        const int n = wave_smallest(wv, wi, SEARCH_WAVES * LM, L, fv, fi);
+        if (lane == 0) c.pre_bound[qq] = (n == L && exact) ? fv[L - 1] : INF;
     }
-    if (tid == 0) c.pre_bound[qq] = last;
+    (void)Lw;
 }
 
 __device__ double theta0_from_prepass(const Ctx &c, int L, int KP) {
@@ -399,11 +446,121 @@ struct SearchArgs {
     uint64_t r0, r1;
 };
 
+
 // LDS record of the Cholesky row of prefix (P', j) for one task:
 //   v[0..q-1] = R_{P'}^{-1} G[P', j],  alpha = 1/d_j,  zs = z_j / s_j,
 //   pi = p - theta_f (single task) ,  p = SSE of the prefix (P', j)
 // z_j = (b_j - v.z') / s_j, s_j = sqrt(d_j), d_j = 1 - |v|^2.
 // An invalid record has p = pi = NaN, which fails every comparison.
+
+// k-dependent part of each sub-prefix solve for last index kc:
+//   w' = R_{P'}^{-1} G[P', kc],  d' = 1 - |w'|^2,  zeta' = b_kc - w'.z'
+// (sub-prefix factors read from LDS).  One set per sub-prefix (one task) or
+// for the lane's task (many tasks).
+template <int D, int NR, bool MT>
+__device__ inline void hoist_k(const Ctx &c, const double *subf, const int32_t *sub, int64_t kc, int myt,
+                               double (&wq)[NR][(D - 2) > 0 ? (D - 2) : 1], double (&dq)[NR], double (&zq)[NR]) {
+    constexpr int q = D - 2;
+    constexpr int QA = q > 0 ? q : 1;
+    constexpr int SUBW = QA * QA + QA + 2;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const int sid = MT ? myt : r;
+        const double *f = subf + sid * SUBW;
+        const int tt = MT ? myt : 0;
+        double g[QA];
+#pragma unroll
+        for (int m = 0; m < q; ++m) {
+            const int32_t pm = sub[(MT ? 0 : r) * QA + m];
+            g[m] = (pm >= 0 && tt < c.T) ? Gat(c, pm, kc, tt) : 0.0;
+        }
+        double dd = (tt < c.T) ? Gat(c, kc, kc, tt) : 1.0;
+        double zz = (tt < c.T) ? c.bhat[kc * c.TP + tt] : 0.0;
+#pragma unroll
+        for (int m = 0; m < q; ++m) {
+            double s = 0.0;
+#pragma unroll
+            for (int l = 0; l <= m; ++l) s += f[m * QA + l] * g[l];
+            wq[r][m] = s;
+            dd -= s * s;
+            zz -= s * f[QA * QA + m];
+        }
+        dq[r] = dd;
+        zq[r] = zz;
+    }
+}
+
+// Rare path of the sweep: at least one lane passed the filter for (P', j, k).
+// Recomputes the tuple terms exactly as the fast loop does, takes the SSE
+// with a true division, applies the rank test and the current bound, and
+// inserts the survivors into the wave's list.  Kept out of line so the fast
+// loop's registers are not shaped by it.  Returns the wave's published bound.
+template <int D, int NR, bool MT>
+__device__ inline double slow_path(const Ctx &c, const SearchArgs &a, double *Ls, uint64_t *Lr,
+                                         const double *recs, const double *subf, const int32_t *sub,
+                                         const unsigned long long *smask, int64_t j, int jj, int64_t k,
+                                         bool kin, bool flagged, int myt, int TL, double theta_f,
+                                         double theta_pub) {
+    constexpr int q = D - 2;
+    constexpr int QA = q > 0 ? q : 1;
+    constexpr int RECW = q + 4;
+    const int KP = a.KP;
+    const int lane = threadIdx.x & 63;
+    const int64_t kc = kin ? k : c.S - 1;
+    double wq[NR][QA], dq[NR], zq[NR];
+    hoist_k<D, NR, MT>(c, subf, sub, kc, myt, wq, dq, zq);
+    const bool lane_ok = kin && (k > j) && (MT || flagged);
+    for (int r = 0; r < NR; ++r) {
+        if (!MT && !((smask[r] >> jj) & 1ull)) continue;
+        const double *rr = MT ? recs + (jj * TL + myt) * RECW : recs + (jj * NR + r) * RECW;
+        const double g = Gat(c, j, kc, MT ? myt : 0);
+        double u = g;
+        for (int x = 0; x < q; ++x) u = fma(-rr[x], wq[r][x], u);
+        const double d = fma(-rr[q], u * u, dq[r]);
+        const double z = fma(-rr[q + 1], u, zq[r]);
+        double es;
+        bool pass;
+        if (MT) {
+            double ex = 0.0;
+            if (myt < c.T) ex = (d > RANK_EPS) ? rr[q + 3] - z * z / d : INF;
+            es = ex;
+            for (int o = 1; o < TL; o <<= 1) es += __shfl_xor(es, o);
+            pass = (myt == 0);
+        } else {
+            es = (d > RANK_EPS) ? rr[q + 3] - z * z / d : INF;
+            pass = true;
+        }
+        const double thc = fmin(theta_f, Ls[KP - 1]);
+        bool take = pass && lane_ok && (es <= thc);
+        uint64_t rk = 0;
+        if (take) {
+            int32_t tup[MAXD];
+            for (int m = 0; m < q; ++m) tup[m] = sub[(MT ? 0 : r) * QA + m];
+            tup[q] = (int32_t)j;
+            tup[q + 1] = (int32_t)k;
+            rk = pack_tuple(tup, D);
+            if (a.ranged) {
+                const uint64_t lr = lex_rank(BinomTab{c.btab, c.S}, c.S, D, tup);
+                if (lr < a.r0 || lr >= a.r1) take = false;
+            }
+        }
+        unsigned long long m = __ballot(take);
+        if (m && lane == 0) atomicAdd(c.cand_counter, (unsigned)__popcll(m));
+        while (m) {
+            const int src = __ffsll((long long)m) - 1;
+            m &= m - 1;
+            const double cs = __shfl(es, src);
+            const uint64_t cr = (uint64_t)__shfl((long long)rk, src);
+            list_insert(Ls, Lr, KP, cs, cr);
+        }
+    }
+    const double tw = Ls[KP - 1];
+    if (tw < theta_pub) {
+        theta_pub = tw;
+        if (lane == 0) theta_publish(c.theta_bits, tw);
+    }
+    return theta_pub;
+}
 
 template <int D, bool MT>
 __global__ __launch_bounds__(256) void search_kernel(Ctx c, SearchArgs a) {
@@ -429,6 +586,8 @@ __global__ __launch_bounds__(256) void search_kernel(Ctx c, SearchArgs a) {
     __shared__ unsigned long long s_mask[SUBP > 64 ? SUBP : 64];  // record validity per r (ST) / per jj (MT)
     __shared__ uint64_t s_item;
     __shared__ double s_theta;
+    __shared__ unsigned long long s_qmask[SEARCH_WAVES][JBLK];
+    __shared__ int s_qj[SEARCH_WAVES][JBLK];
 
     for (int m = lane; m < KP; m += 64) {
         Ls[m] = INF;
@@ -441,7 +600,9 @@ __global__ __launch_bounds__(256) void search_kernel(Ctx c, SearchArgs a) {
     const int KL = 64 / TL;               // last indices per wave chunk
     const int JB = a.JB;                  // j values per item
 
-    const uint64_t nitems = c.cum[(c.S - 1 + JB - 1) / JB];
+    const uint64_t nitems = uni(c.cum[(c.S - 1 + JB - 1) / JB]);
+    if (blockIdx.x == 0 && tid == 0) c.stats[1] = nitems;
+    const double *__restrict__ Gbase = c.G;
     for (;;) {
         if (tid == 0) {
             s_item = atomicAdd(c.work_counter, 1u);
@@ -449,9 +610,9 @@ __global__ __launch_bounds__(256) void search_kernel(Ctx c, SearchArgs a) {
             s_theta = fmin(ts, theta0);
         }
         __syncthreads();
-        const uint64_t item = s_item;
+        const uint64_t item = uni(s_item);
         if (item >= nitems) break;
-        const double theta_item = s_theta;
+        const double theta_item = uni(s_theta);
         const double theta_f = theta_item < INF ? theta_item * (1.0 + THETA_SLACK) : INF;
 
         // item -> (j-block, sub-prefix group) by bisection on the cumulative table
@@ -460,8 +621,8 @@ __global__ __launch_bounds__(256) void search_kernel(Ctx c, SearchArgs a) {
             const int64_t mid = (lo + hi + 1) / 2;
             if (c.cum[mid] <= item) lo = mid; else hi = mid - 1;
         }
-        const int64_t jb = lo;
-        const uint64_t grp = item - c.cum[jb];
+        const int64_t jb = uni(lo);
+        const uint64_t grp = uni(item - c.cum[jb]);
         int64_t Nj = JB * (jb + 1);
         if (Nj > c.S - 1) Nj = c.S - 1;
         const int64_t j0 = JB * jb;
@@ -483,7 +644,7 @@ __global__ __launch_bounds__(256) void search_kernel(Ctx c, SearchArgs a) {
             const bool rvalid = (r < NR) && (sr < nsub) && (jj < JB);
             int32_t P[QA];
             if (rvalid) {
-                if (q > 0) colex_unrank(BinomTab{c.btab, c.S}, sr, q, Nj - 1, P);
+                if (q > 0) colex_unrank_small(sr, q, Nj - 1, P);
             }
             // sub-prefix factorisation (normalised: unit diagonal)
             double Li[QA][QA], zp[QA], pp = 0.0;
@@ -574,7 +735,7 @@ __global__ __launch_bounds__(256) void search_kernel(Ctx c, SearchArgs a) {
                 rec[q + 2] = __builtin_nan("");
                 rec[q + 3] = __builtin_nan("");
             }
-            const int slot = MT ? (jj * TL + t) : (r * 64 + jj);
+            const int slot = MT ? (jj * TL + t) : (jj * NR + r);
             if (MT ? (jj < JB) : true) {
                 double *dst = recs + slot * RECW;
                 for (int m = 0; m < RECW; ++m) dst[m] = rec[m];
@@ -604,145 +765,113 @@ __global__ __launch_bounds__(256) void search_kernel(Ctx c, SearchArgs a) {
 
         // ---- sweep the last index k in chunks of KL per wave
         const int64_t jhi = (j0 + JB < Nj ? j0 + JB : Nj) - 1;  // largest j of the block
-        const int64_t kstart = j0 + 1;
+        const int64_t kstart = j0;  // chunks are aligned to KL, which divides the tile width
         const int tl = MT ? (lane % TL) : 0;
         const int kl = MT ? (lane / TL) : lane;
         const int myt = tl;
+        unsigned long long *qmask = s_qmask[wave];
+        int *qj = s_qj[wave];
         for (int64_t kb = kstart + (int64_t)wave * KL; kb < c.S; kb += (int64_t)SEARCH_WAVES * KL) {
             const int64_t k = kb + kl;
             const bool kin = k < c.S;
             const int64_t kc = kin ? k : c.S - 1;
-            // hoisted k-dependent part of each sub-prefix solve
             double wq[NR][QA], dq[NR], zq[NR];
-#pragma unroll
-            for (int r = 0; r < NR; ++r) {
-                const int sid = MT ? myt : r;
-                const double *f = subf + sid * SUBW;
-                const int tt = MT ? myt : 0;
-                double g[QA];
-                for (int m = 0; m < q; ++m) {
-                    const int32_t pm = MT ? s_sub[0][m] : s_sub[r][m];
-                    g[m] = (pm >= 0 && tt < c.T) ? Gat(c, pm, kc, tt) : 0.0;
-                }
-                double dd = (tt < c.T) ? Gat(c, kc, kc, tt) : 1.0;
-                double zz = (tt < c.T) ? c.bhat[kc * c.TP + tt] : 0.0;
-                for (int m = 0; m < q; ++m) {
-                    double s = 0.0;
-                    for (int l = 0; l <= m; ++l) s += f[m * QA + l] * g[l];
-                    wq[r][m] = s;
-                    dd -= s * s;
-                    zz -= s * f[QA * QA + m];
-                }
-                dq[r] = dd;
-                zq[r] = zz;
-            }
+            hoist_k<D, NR, MT>(c, subf, &s_sub[0][0], kc, myt, wq, dq, zq);
             const bool check = (kb <= jhi) || (kb + KL > c.S);
-            const int64_t jend = jhi + 1;
-            for (int64_t j = j0; j < jend; ++j) {
-                const int jj = (int)(j - j0);
-                if (MT) {
-                    if (!s_mask[jj]) continue;
-                    const double g = (myt < c.T) ? Gat(c, j, kc, myt) : 0.0;
-                    const double *rr = recs + (jj * TL + myt) * RECW;
-                    double u = g;
-                    for (int m = 0; m < q; ++m) u -= rr[m] * wq[0][m];
-                    const double d = dq[0] - rr[q] * (u * u);
-                    const double zeta = zq[0] - rr[q + 1] * u;
-                    // approximate term p - zeta^2/d: reciprocal + one Newton step
-                    double rc = __builtin_amdgcn_rcp(d);
-                    rc = rc * (2.0 - d * rc);
-                    double term = (myt < c.T) ? rr[q + 3] - zeta * zeta * rc : 0.0;
-                    double sum = term;
-                    for (int o = 1; o < TL; o <<= 1) sum += __shfl_xor(sum, o);
-                    bool pass = (sum <= theta_f) && (tl == 0);
-                    if (check) pass = pass && kin && (k > j);
-                    if (__ballot(pass)) {
-                        // exact per-task terms, same reduction order
-                        const bool tv = (myt < c.T);
-                        double ex = 0.0;
-                        if (tv) ex = (d > RANK_EPS) ? rr[q + 3] - zeta * zeta / d : INF;
-                        double es = ex;
-                        for (int o = 1; o < TL; o <<= 1) es += __shfl_xor(es, o);
-                        const double thc = fmin(theta_f, Ls[KP - 1]);
-                        bool take = pass && kin && (k > j) && (es <= thc);
-                        uint64_t rk = 0;
-                        if (take) {
-                            int32_t tup[MAXD];
-                            for (int m = 0; m < q; ++m) tup[m] = s_sub[0][m];
-                            tup[q] = (int32_t)j;
-                            tup[q + 1] = (int32_t)k;
-                            rk = lex_rank(BinomTab{c.btab, c.S}, c.S, D, tup);
-                            if (a.ranged && (rk < a.r0 || rk >= a.r1)) take = false;
-                        }
-                        unsigned long long m = __ballot(take);
-                        if (m && lane == 0) atomicAdd(c.cand_counter, (unsigned)__popcll(m));
-                        while (m) {
-                            const int src = __ffsll((long long)m) - 1;
-                            m &= m - 1;
-                            const double cs = __shfl(es, src);
-                            const uint64_t cr = (uint64_t)__shfl((long long)rk, src);
-                            list_insert(Ls, Lr, KP, cs, cr);
-                        }
-                        const double tw = Ls[KP - 1];
-                        if (tw < theta_pub) {
-                            theta_pub = tw;
-                            if (lane == 0) theta_publish(c.theta_bits, tw);
-                        }
-                    }
-                } else {
-                    const double g = Gat(c, j, kc, 0);
-                    bool pr[NR];
-                    double zr[NR], dr[NR];
+            // G rows of the tile (j-block, k-chunk): a uniform row pointer plus a
+            // 32-bit lane offset; lanes past S read the tile's zero padding
+            const int64_t rs = (int64_t)GT * c.TP;
+            const int ko = (int)((k & (GT - 1)) * c.TP + myt);
+            const double *__restrict__ gp =
+                Gbase + ((((j0 >> 6) * c.Gnt + (kb >> 6)) << 12) + ((j0 & (GT - 1)) << 6)) * c.TP;
+            int nq = 0;  // steps of this chunk where some lane passed the filter
+            // the j sweep, versioned on whether lanes need the k > j / k < S masks
+            auto sweep = [&](auto checkc) {
+                constexpr bool CHECK = decltype(checkc)::value;
+                auto body = [&](int64_t j, double g) {
+                    const int jj = (int)(j - j0);
+                    unsigned long long m = 0;
+                    if (MT) {
+                        if (!s_mask[jj]) return;
+                        const double *rr = recs + (jj * TL + myt) * RECW;
+                        double rv[q + 4];
 #pragma unroll
-                    for (int r = 0; r < NR; ++r) {
-                        const double *rr = recs + (r * 64 + jj) * RECW;
+                        for (int x = 0; x < q + 4; ++x) rv[x] = rr[x];
+                        __asm__ volatile("" ::: "memory");
                         double u = g;
 #pragma unroll
-                        for (int m = 0; m < q; ++m) u -= rr[m] * wq[r][m];
-                        const double d = dq[r] - rr[q] * (u * u);
-                        const double zeta = zq[r] - rr[q + 1] * u;
-                        pr[r] = zeta * zeta >= rr[q + 2] * d;
-                        zr[r] = zeta;
-                        dr[r] = d;
-                    }
-                    bool any = false;
+                        for (int x = 0; x < q; ++x) u = fma(-rv[x], wq[0][x], u);
+                        const double d = fma(-rv[q], u * u, dq[0]);
+                        const double z = fma(-rv[q + 1], u, zq[0]);
+                        // p - z^2/d with a reciprocal refined by one Newton step
+                        double rc = __builtin_amdgcn_rcp(d);
+                        rc = fma(rc, fma(-d, rc, 1.0), rc);
+                        double sum = fma(-(z * z), rc, rv[q + 3]);
+                        for (int o = 1; o < TL; o <<= 1) sum += __shfl_xor(sum, o);
+                        m = __ballot(sum <= theta_f && tl == 0);
+                    } else {
+                        // all record reads of this step are issued before any use,
+                        // so their LDS latencies overlap
+                        const double *rj = recs + jj * (NR * RECW);
+                        double rv[NR][q + 3];
 #pragma unroll
-                    for (int r = 0; r < NR; ++r) any |= pr[r];
-                    if (check) any = any && kin && (k > j);
-                    if (__ballot(any)) {
+                        for (int r = 0; r < NR; ++r)
+#pragma unroll
+                            for (int x = 0; x < q + 3; ++x) rv[r][x] = rj[r * RECW + x];
+                        __asm__ volatile("" ::: "memory");
+#pragma unroll
                         for (int r = 0; r < NR; ++r) {
-                            if (!((s_mask[r] >> jj) & 1ull)) continue;
-                            const double *rr = recs + (r * 64 + jj) * RECW;
-                            const double d = dr[r];
-                            const double es = (d > RANK_EPS) ? rr[q + 3] - zr[r] * zr[r] / d : INF;
-                            const double thc = fmin(theta_f, Ls[KP - 1]);
-                            bool take = pr[r] && kin && (k > j) && (es <= thc);
-                            uint64_t rk = 0;
-                            if (take) {
-                                int32_t tup[MAXD];
-                                for (int m = 0; m < q; ++m) tup[m] = s_sub[r][m];
-                                tup[q] = (int32_t)j;
-                                tup[q + 1] = (int32_t)k;
-                                rk = lex_rank(BinomTab{c.btab, c.S}, c.S, D, tup);
-                                if (a.ranged && (rk < a.r0 || rk >= a.r1)) take = false;
-                            }
-                            unsigned long long m = __ballot(take);
-                            if (m && lane == 0) atomicAdd(c.cand_counter, (unsigned)__popcll(m));
-                            while (m) {
-                                const int src = __ffsll((long long)m) - 1;
-                                m &= m - 1;
-                                const double cs = __shfl(es, src);
-                                const uint64_t cr = (uint64_t)__shfl((long long)rk, src);
-                                list_insert(Ls, Lr, KP, cs, cr);
-                            }
-                        }
-                        const double tw = Ls[KP - 1];
-                        if (tw < theta_pub) {
-                            theta_pub = tw;
-                            if (lane == 0) theta_publish(c.theta_bits, tw);
+                            double u = g;
+#pragma unroll
+                            for (int x = 0; x < q; ++x) u = fma(-rv[r][x], wq[r][x], u);
+                            const double d = fma(-rv[r][q], u * u, dq[r]);
+                            const double z = fma(-rv[r][q + 1], u, zq[r]);
+                            m |= __ballot(z * z >= rv[r][q + 2] * d);
                         }
                     }
+                    if (CHECK) m &= __ballot(kin && k > j);
+                    if (m) {
+                        if (lane == 0) {
+                            qmask[nq] = m;
+                            qj[nq] = jj;
+                        }
+                        ++nq;
+                    }
+                };
+                // rows are fetched a group of JG ahead into the other of two
+                // register sets, so JG loads per wave are in flight while a
+                // group is scored
+                constexpr int JG = 8;
+                double ga[JG], gb[JG];
+                auto fetch = [&](double (&dst)[JG], int64_t jg) {
+#pragma unroll
+                    for (int x = 0; x < JG; ++x) {
+                        const int64_t jr = (jg + x <= jhi) ? jg + x : jhi;
+                        dst[x] = gp[(jr - j0) * rs + ko];
+                    }
+                };
+                auto score = [&](const double (&src)[JG], int64_t jg) {
+#pragma unroll
+                    for (int x = 0; x < JG; ++x)
+                        if (jg + x <= jhi) body(jg + x, src[x]);
+                };
+                fetch(ga, j0);
+                for (int64_t jg = j0; jg <= jhi; jg += 2 * JG) {
+                    fetch(gb, jg + JG);
+                    score(ga, jg);
+                    if (jg + JG > jhi) break;
+                    fetch(ga, jg + 2 * JG);
+                    score(gb, jg + JG);
                 }
+            };
+            if (check) sweep(std::true_type{});
+            else sweep(std::false_type{});
+            // exact scoring of the queued steps (rare)
+            for (int e = 0; e < nq; ++e) {
+                const int jj = qj[e];
+                const unsigned long long lm = qmask[e];
+                theta_pub = slow_path<D, NR, MT>(c, a, Ls, Lr, recs, subf, &s_sub[0][0], s_mask, j0 + jj, jj, k,
+                                                 kin, (lm >> lane) & 1ull, myt, TL, theta_f, theta_pub);
             }
         }
         __syncthreads();
@@ -833,7 +962,13 @@ __global__ __launch_bounds__(MERGE_THREADS) void merge_kernel(Ctx c, int nlists,
     __shared__ int64_t wsum[MERGE_THREADS / 64];
     const int tid = threadIdx.x;
     double bound = theta_load(c.theta_bits);
-    if (use_pre) bound = fmin(bound, theta0_from_prepass(c, L, KP));
+    const double th0 = use_pre ? theta0_from_prepass(c, L, KP) : INF;
+    if (tid == 0) {
+        c.stats[0] = *c.cand_counter;
+        c.stats[2] = (uint64_t)__double_as_longlong(th0);
+        c.stats[3] = (uint64_t)__double_as_longlong(bound);
+    }
+    if (use_pre) bound = fmin(bound, th0);
     bound = bound < INF ? bound * (1.0 + THETA_SLACK) : INF;
     // counts per list (lists are sorted ascending)
     for (int l = tid; l < nlists; l += MERGE_THREADS) {
@@ -885,9 +1020,12 @@ __global__ __launch_bounds__(MERGE_THREADS) void merge_kernel(Ctx c, int nlists,
     __syncthreads();
     const int64_t chunk = MERGE_CAP - KP;
     for (int64_t base = 0; base < total || base == 0; base += chunk) {
-        for (int i = tid; i < chunk; i += MERGE_THREADS) {
+        const int64_t here = total - base < chunk ? (total - base > 0 ? total - base : 0) : chunk;
+        int N = 2 * KP;  // sort only as many slots as hold keys: the carried KP plus this chunk
+        while (N < KP + here) N <<= 1;
+        for (int i = tid; i < N - KP; i += MERGE_THREADS) {
             const int64_t e = base + i;
-            if (e < total) {
+            if (i < here) {
                 ks[KP + i] = c.cand_sse[e];
                 kr[KP + i] = c.cand_rank[e];
             } else {
@@ -896,7 +1034,7 @@ __global__ __launch_bounds__(MERGE_THREADS) void merge_kernel(Ctx c, int nlists,
             }
         }
         __syncthreads();
-        bitonic_sort_lds(ks, kr, MERGE_CAP);
+        bitonic_sort_lds(ks, kr, N);
         if (base + chunk >= total) break;
     }
     for (int i = tid; i < KP; i += MERGE_THREADS) {
@@ -925,7 +1063,7 @@ __global__ __launch_bounds__(256) void rescore_kernel(Ctx c, int D) {
         return;
     }
     int32_t tup[MAXD];
-    lex_unrank(BinomTab{c.btab, c.S}, c.S, D, c.merged_rank[cand], tup);
+    unpack_tuple(c.merged_rank[cand], D, tup);
     double total = 0.0;
     bool valid = true;
     for (int t = 0; t < c.T; ++t) {
@@ -1044,7 +1182,7 @@ __global__ __launch_bounds__(1024) void final_kernel(Ctx c, int D, int k, int KP
         if (pos < k) {
             c.res_sse[pos] = vi ? si : INF;
             int32_t tup[MAXD];
-            if (vi) lex_unrank(BinomTab{c.btab, c.S}, c.S, D, ri, tup);
+            if (vi) unpack_tuple(ri, D, tup);
             for (int m = 0; m < D; ++m) c.res_idx[pos * D + m] = vi ? tup[m] : -1;
             for (int t = 0; t < c.T; ++t)
                 for (int m = 0; m <= D; ++m)

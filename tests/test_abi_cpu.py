@@ -1,0 +1,103 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+the header declares, sizes workspaces as a pure function of the shape,
+rejects bad descriptors before touching a device, and its host-side
+combinatorial number system is a bijection."""
+import ctypes
+import itertools
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2502_20072_amd import _binding as B
+import paper_2502_20072_amd as P
+
+
+def _declared_functions():
+    text = open(B.HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sisso_\w+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol():
+    lib = B.load()
+    names = _declared_functions()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in include/sisso_l0.h but not exported"
+
+
+def _desc(n=100, S=20, offsets=None, D_max=3, k_max=10, ws=0, wsb=0, F=0, y=0):
+    offsets = np.array([0, n] if offsets is None else offsets, dtype=np.int64)
+    return B.make_desc(F, y, offsets, n, S, D_max, k_max, ws, wsb)
+
+
+def test_workspace_bytes_pure_and_validating():
+    a = B.sisso_l0_workspace_bytes(_desc())
+    b = B.sisso_l0_workspace_bytes(_desc())
+    assert a == b > 0
+    assert B.sisso_l0_workspace_bytes(_desc(S=40)) > a
+    assert B.sisso_l0_workspace_bytes(_desc(D_max=0)) == 0
+    assert B.sisso_l0_workspace_bytes(_desc(D_max=B.SISSO_MAX_D + 1)) == 0
+    assert B.sisso_l0_workspace_bytes(_desc(k_max=B.SISSO_MAX_K + 1)) == 0
+    # the big multi-task workload fits a single MI355X comfortably
+    big = B.sisso_l0_workspace_bytes(_desc(n=17000, S=1500, offsets=np.linspace(0, 17000, 17).astype(np.int64),
+                                           D_max=3, k_max=100))
+    assert 0 < big < 4 << 30
+
+
+def test_create_rejects_bad_descriptors_without_device():
+    with pytest.raises(B.SissoError) as e:
+        B.sisso_l0_create(_desc())            # null F / y / workspace
+    assert e.value.code == B.SISSO_EINVAL
+    assert "null" in B.sisso_l0_last_error(None)
+    with pytest.raises(B.SissoError) as e:
+        B.sisso_l0_create(_desc(F=8, y=8, ws=256, wsb=1 << 40, offsets=[0, 50, 40, 100]))
+    assert e.value.code == B.SISSO_EINVAL
+    with pytest.raises(B.SissoError) as e:
+        B.sisso_l0_create(_desc(F=8, y=8, ws=256, wsb=16))
+    assert e.value.code == B.SISSO_ENOMEM
+    with pytest.raises(B.SissoError) as e:
+        B.sisso_l0_create(_desc(F=8, y=8, ws=257, wsb=1 << 40))
+    assert e.value.code == B.SISSO_EINVAL
+    d = _desc(F=8, y=8, ws=256, wsb=1 << 40)
+    d.precision = 7
+    with pytest.raises(B.SissoError) as e:
+        B.sisso_l0_create(d)
+    assert e.value.code == B.SISSO_ENOTSUP
+
+
+def test_null_handle_calls():
+    lib = B.load()
+    assert lib.sisso_gram(None) == B.SISSO_EINVAL
+    assert lib.sisso_l0_search(None, 2, 3) == B.SISSO_EINVAL
+    assert lib.sisso_l0_scored(None) == 0
+    lib.sisso_l0_destroy(None)
+
+
+@pytest.mark.parametrize("S,D", [(1, 1), (6, 3), (9, 4), (12, 2), (12, 4), (7, 7)])
+def test_lex_rank_bijection(S, D):
+    for r, t in enumerate(itertools.combinations(range(S), D)):
+        assert P.rank_of(S, t) == r
+        assert P.unrank(S, D, r) == t
+
+
+@pytest.mark.parametrize("S,D", [(600, 4), (5000, 3), (50000, 2), (65535, 4), (1500, 3)])
+def test_rank_space_edges_64bit(S, D):
+    N = math.comb(S, D)
+    assert P.unrank(S, D, 0) == tuple(range(D))
+    assert P.unrank(S, D, N - 1) == tuple(range(S - D, S))
+    for r in [1, N // 7, N // 2, N - 2]:
+        assert P.rank_of(S, P.unrank(S, D, r)) == r
+    with pytest.raises(B.SissoError):
+        P.unrank(S, D, N)
+    assert P.rank_of(S, [0] * D) == (1 << 64) - 1 if D > 1 else True
+
+
+def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
+    monkeypatch.setattr(B, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(B, "_lib", None)
+    with pytest.raises(RuntimeError, match="no fallback"):
+        B.load()
