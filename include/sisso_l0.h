@@ -49,7 +49,17 @@ enum {
 };
 
 enum {
-    SISSO_PREC_FP64 = 0 /* Gram, fits and scores in FP64 */
+    SISSO_PREC_FP64 = 0,       /* Gram, fits and scores in FP64 */
+    /* Precision form of the Gram (the search, F^T y, |y|^2 and the re-score
+     * stay FP64): every centred column is cut, per chunk of 256 samples, into
+     * BF16 slices of small integers with a shared power-of-two scale; the
+     * slice cross products run on BF16 MFMA with FP32 accumulation, exact
+     * within a chunk, and the chunk sums are scaled and accumulated in FP64.
+     * Three slices keep ~23 bits of each centred value.  The error this
+     * leaves in the correlation matrix is measured by
+     * sisso_l0_precision_report. */
+    SISSO_PREC_BF16_COMP = 1,
+    SISSO_PREC_FP16_COMP = 2   /* reserved: not built (SISSO_ENOTSUP) */
 };
 
 #define SISSO_MAX_D 4      /* largest descriptor dimension compiled in */
@@ -100,7 +110,9 @@ int32_t sisso_gram(sisso_l0 *h);
 /* Enqueue an exhaustive search over all C(S, D) tuples and keep the k best by
  * (SSE ascending, lexicographic rank ascending).  Rank-deficient tuples (a
  * feature whose 1 - R^2 on the intercept and the earlier features of the
- * tuple is <= 1e-10 in some task) are never returned.  Errors: ESTATE before
+ * tuple is <= 1e-10 in some task, or which is constant on some task to the
+ * same 1e-10: |x - mean|^2 <= 1e-10 |x|^2 over the task's rows) are never
+ * returned.  Errors: ESTATE before
  * sisso_gram; ENOTSUP for D > D_max or D > SISSO_MAX_D; EINVAL for D < 1,
  * S < D, k < 1, k > k_max, k > C(S, D), or a task with fewer than D + 2 rows. */
 int32_t sisso_l0_search(sisso_l0 *h, int32_t D, int32_t k);
@@ -146,7 +158,8 @@ int32_t sisso_l0_topk(sisso_l0 *h, int32_t k, int32_t *idx, double *sse, double 
 /* Synchronise the stream and copy task t's precomputed statistics to HOST
  * buffers (any may be NULL): G (S*S doubles, row-major) the correlation
  * matrix of the task's centred columns, G[i][j] = x_ic.x_jc / (|x_ic||x_jc|)
- * with a unit diagonal (0 on the diagonal of a constant column); b (S
+ * with a unit diagonal (0 on the diagonal, and 0 in the row and column, of a
+ * column constant on the task as defined at sisso_l0_search); b (S
  * doubles) b_j = x_jc.y_c / |x_jc|; c (1 double) |y_c|^2, where x_c, y_c are
  * the task's columns minus their means.  ESTATE before sisso_gram, EINVAL for
  * t out of range. */
@@ -155,6 +168,16 @@ int32_t sisso_gram_read(sisso_l0 *h, int32_t t, double *G, double *b, double *c)
 /* Number of tuples the last search scored (C(S, D), or r1 - r0 for a range
  * search), for throughput accounting.  Host-only. */
 uint64_t sisso_l0_scored(const sisso_l0 *h);
+
+/* Accuracy report of the precision form, also valid for FP64 (synchronises
+ * the stream).  out[0]: largest |G_used - G_fp64| over nsample sampled
+ * entries per task (the FP64 value is the centred dot product straight from
+ * F, computed here); out[1]: entries compared; out[2]: largest relative
+ * difference between the SSE the search ranked by (from G_used) and the
+ * exact re-scored SSE over the k results of the last search (0 before a
+ * search); out[3]: slices per value (0 for FP64).  ESTATE before
+ * sisso_gram; EINVAL for nsample < 1 or a null out. */
+int32_t sisso_l0_precision_report(sisso_l0 *h, int32_t nsample, double *out);
 
 /* Per-phase timing with HIP events recorded on the handle's stream.
  * sisso_l0_profile(h, 1) turns it on (0 off; off by default).  After a

@@ -21,7 +21,11 @@
  *  - a tuple is rank-deficient, and gets SSE = +inf, when for some feature
  *    column m (in increasing index order) of some task the ratio
  *    R_mm^2 / |x_m - mean(x_m)|^2 is <= 1e-10 (one minus the R^2 of x_m on
- *    the intercept and the earlier columns), or when that column is constant;
+ *    the intercept and the earlier columns), or when x_m is constant on the
+ *    task to that same 1e-10: |x_m - mean(x_m)|^2 <= 1e-10 |x_m|^2 (one minus
+ *    the uncentred R^2 of x_m on the intercept alone).  The second rule keeps
+ *    a column that is constant on a task up to rounding, whose centred values
+ *    are rounding noise, from passing the first rule on that noise;
  *  - a task with n_t < D+1 rows cannot determine D+1 coefficients: +inf;
  *  - Householder vectors use the LAPACK sign choice v = x + sign(x_1)|x| e_1;
  *  - the top-k is ordered by (SSE ascending, index tuple lexicographically
@@ -57,6 +61,7 @@ static void task_fit(const double *F, const double *y, int64_t n_total,
     double *b = work + (int64_t)ncol * nt;
     double Rdiag[ORACLE_MAX_D + 1];
     double cnorm2[ORACLE_MAX_D + 1];
+    double rnorm2[ORACLE_MAX_D + 1];
     int64_t i;
     int j, c;
 
@@ -69,11 +74,12 @@ static void task_fit(const double *F, const double *y, int64_t n_total,
     for (j = 0; j < D; ++j) {
         const double *col = F + (int64_t)tup[j] * n_total + r0;
         double *dst = A + (int64_t)(j + 1) * nt;
-        double mean = 0.0, s2 = 0.0;
-        for (i = 0; i < nt; ++i) { dst[i] = col[i]; mean += col[i]; }
+        double mean = 0.0, s2 = 0.0, r2 = 0.0;
+        for (i = 0; i < nt; ++i) { dst[i] = col[i]; mean += col[i]; r2 += col[i] * col[i]; }
         mean /= (double)nt;
         for (i = 0; i < nt; ++i) { double d = col[i] - mean; s2 += d * d; }
         cnorm2[j + 1] = s2;
+        rnorm2[j + 1] = r2;
     }
     for (i = 0; i < nt; ++i) b[i] = y[r0 + i];
 
@@ -105,7 +111,8 @@ static void task_fit(const double *F, const double *y, int64_t n_total,
         Rdiag[c] = alpha;
         /* rank test on the feature columns, in increasing index order */
         if (c >= 1) {
-            if (cnorm2[c] == 0.0 || (alpha * alpha) / cnorm2[c] <= ORACLE_RANK_EPS) {
+            if (cnorm2[c] <= ORACLE_RANK_EPS * rnorm2[c] ||
+                (alpha * alpha) / cnorm2[c] <= ORACLE_RANK_EPS) {
                 *sse = INFINITY;
                 return;
             }

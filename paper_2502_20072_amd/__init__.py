@@ -26,7 +26,7 @@ class L0Search:
     """
 
     def __init__(self, F, y, task_offsets: Optional[Sequence[int]] = None, D_max: int = 4,
-                 k_max: int = 100, device: str = "cuda:0", stream=None):
+                 k_max: int = 100, device: str = "cuda:0", stream=None, precision: int = B.SISSO_PREC_FP64):
         import torch
 
         if isinstance(F, np.ndarray):
@@ -48,7 +48,9 @@ class L0Search:
         self.S, self.n, self.T = int(S), int(n), len(self.offsets) - 1
         self.D_max, self.k_max = int(D_max), int(k_max)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.F.device)
-        probe = B.make_desc(0, 0, self.offsets, self.n, self.S, self.D_max, self.k_max)
+        self.precision = int(precision)
+        probe = B.make_desc(0, 0, self.offsets, self.n, self.S, self.D_max, self.k_max,
+                            precision=self.precision)
         nbytes = B.sisso_l0_workspace_bytes(probe)
         if nbytes == 0:
             raise SissoError(B.SISSO_EINVAL, "problem shape out of range")
@@ -58,7 +60,8 @@ class L0Search:
         aligned = (base + 255) & ~255
         self.workspace_bytes = nbytes
         self._desc = B.make_desc(self.F.data_ptr(), self.y.data_ptr(), self.offsets, self.n, self.S,
-                                 self.D_max, self.k_max, aligned, nbytes, self.stream.cuda_stream)
+                                 self.D_max, self.k_max, aligned, nbytes, self.stream.cuda_stream,
+                                 precision=self.precision)
         self.handle = B.sisso_l0_create(self._desc)
         self.last_D = None
         self.last_k = None
@@ -89,6 +92,11 @@ class L0Search:
 
     def scored(self) -> int:
         return B.sisso_l0_scored(self.handle)
+
+    def precision_report(self, nsample: int = 4096) -> dict:
+        """Gram error on sampled entries vs FP64 from F, and the ranked-vs-exact
+        SSE error of the last search's results; synchronises."""
+        return B.sisso_l0_precision_report(self.handle, nsample)
 
     def close(self) -> None:
         if getattr(self, "handle", None):

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libsisso_l0.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "sisso_l0.h")
 
 SISSO_OK, SISSO_EINVAL, SISSO_ESTATE, SISSO_ENOMEM, SISSO_EDEVICE, SISSO_ENOTSUP = 0, -1, -2, -3, -4, -5
-SISSO_PREC_FP64 = 0
+SISSO_PREC_FP64, SISSO_PREC_BF16_COMP, SISSO_PREC_FP16_COMP = 0, 1, 2
 
 
 def _header_int(name: str) -> int:
@@ -220,6 +220,16 @@ def sisso_l0_search_stats(h: int) -> dict:
     _check(lib.sisso_l0_search_stats(h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))), h)
     return dict(candidates=int(out[0]), items=int(out[1]),
                 theta0=float(out[2:3].view(np.float64)[0]), theta_final=float(out[3:4].view(np.float64)[0]))
+
+
+def sisso_l0_precision_report(h: int, nsample: int = 4096) -> dict:
+    lib = load()
+    lib.sisso_l0_precision_report.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
+    lib.sisso_l0_precision_report.restype = ctypes.c_int32
+    out = np.zeros(4)
+    _check(lib.sisso_l0_precision_report(h, nsample, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), h)
+    return dict(gram_max_abs_err=float(out[0]), gram_entries=int(out[1]), sse_max_rel_err=float(out[2]),
+                slices=int(out[3]))
 
 
 def _batch_sigs(lib):

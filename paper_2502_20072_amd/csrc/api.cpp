@@ -41,8 +41,20 @@ static int32_t fail(sisso_l0 *h, int32_t code, const char *msg) {
     return code;
 }
 
-static Layout compute_layout(int64_t n_total, int64_t S, int T, int D_max, int k_max) {
+// slices per value of a precision mode (0: FP64 Gram; -1: unknown mode)
+static int precision_slices(int32_t precision) {
+    switch (precision) {
+        case SISSO_PREC_FP64: return 0;
+        case SISSO_PREC_BF16_COMP: return 3;
+        default: return -1;
+    }
+}
+
+static Layout compute_layout(int64_t n_total, int64_t S, int T, int D_max, int k_max, int lp_ns) {
     Layout L{};
+    L.lp_ns = lp_ns > 0 ? lp_ns : 0;
+    // chunks of LP_XC samples per task; bounded without reading the offsets
+    L.lp_nchunk = L.lp_ns ? (int)((n_total + LP_XC - 1) / LP_XC + T) : 0;
     L.TP = next_pow2(T);
     const int64_t ntile = (S + GRAM_TILE - 1) / GRAM_TILE;
     const int64_t blocks = ntile * (ntile + 1) / 2 * T;
@@ -77,13 +89,15 @@ static Layout compute_layout(int64_t n_total, int64_t S, int T, int D_max, int k
     L.G = take(Sp * Sp * L.TP * d);
     L.part = take((size_t)L.nsplit * T * S * S * d);
     L.flags = take(64 * sizeof(uint32_t));
-    L.tile_cnt = take((size_t)T * ntile * (ntile + 1) / 2 * sizeof(uint32_t));
+    L.lp_cbase = take((size_t)(T + 1) * sizeof(int32_t));
+    L.lp_exp = take((size_t)S * L.lp_nchunk * sizeof(int32_t));
+    L.lp_slices = take((size_t)L.lp_ns * S * L.lp_nchunk * LP_XC * 2);
+    L.stat_bits = take(4 * sizeof(uint64_t));
     // pre-pass + counters: theta, work counter, cand counter, cum table, prefixes, scores
     L.pre = take(64 + (size_t)(S / 4 + 8) * sizeof(uint64_t) + PRE_Q * SISSO_MAX_D * sizeof(int32_t) +
                  64 + (size_t)PRE_Q * S * d + PRE_Q * d + 1024 +
                  (size_t)(SISSO_MAX_D + 1) * (S + 1) * sizeof(uint64_t) + 256);
-    L.lists = take((size_t)nlists * L.KP * 2 * d + (size_t)nlists * (sizeof(int32_t) + sizeof(int64_t)) +
-                   (size_t)nlists * L.KP * 2 * d);
+    L.lists = take((size_t)nlists * L.KP * 2 * d + (size_t)nlists * L.KP * 2 * d);
     L.merged = take((size_t)L.KP * 2 * d);
     L.rescored = take((size_t)L.KP * d);
     L.coef = take((size_t)L.KP * T * (D_max + 1) * d);
@@ -101,7 +115,9 @@ static bool shape_ok(const sisso_l0_desc *d) {
 
 extern "C" size_t sisso_l0_workspace_bytes(const sisso_l0_desc *d) {
     if (!shape_ok(d)) return 0;
-    return compute_layout(d->n_total, d->S, d->T, d->D_max, d->k_max).total + 256;
+    const int ns = precision_slices(d->precision);
+    if (ns < 0) return 0;
+    return compute_layout(d->n_total, d->S, d->T, d->D_max, d->k_max, ns).total + 256;
 }
 
 static void carve(sisso_l0 *h) {
@@ -125,13 +141,18 @@ static void carve(sisso_l0 *h) {
     c.G = (double *)(base + L.G);
     c.part = (double *)(base + L.part);
     c.flags = (uint32_t *)(base + L.flags);
-    c.tile_cnt = (unsigned int *)(base + L.tile_cnt);
+    c.lp_cbase = (int32_t *)(base + L.lp_cbase);
+    c.lp_exp = (int32_t *)(base + L.lp_exp);
+    c.lp_slices = (__bf16 *)(base + L.lp_slices);
+    c.err_bits = (unsigned long long *)(base + L.stat_bits);
+    c.lp_ns = L.lp_ns;
     char *p = base + L.pre;
     c.theta_bits = (unsigned long long *)p;
     c.work_counter = (unsigned int *)(p + 8);
     c.cand_counter = (unsigned int *)(p + 12);
     c.pre_count = (int32_t *)(p + 16);
     c.stats = (uint64_t *)(p + 24);
+    c.merge_count = (unsigned int *)(p + 56);
     p += 64;
     c.cum = (uint64_t *)p;
     p += (size_t)(c.S / 4 + 8) * sizeof(uint64_t);
@@ -147,13 +168,7 @@ static void carve(sisso_l0 *h) {
     c.list_sse = (double *)q;
     q += (size_t)nl * L.KP * sizeof(double);
     c.list_rank = (uint64_t *)q;
-    q += (size_t)nl * L.KP * sizeof(uint64_t);
-    c.list_count = (int32_t *)q;
-    q += (size_t)nl * sizeof(int32_t);
-    q = (char *)(((uintptr_t)q + 255) & ~(uintptr_t)255);
-    c.list_offset = (int64_t *)q;
-    q += (size_t)nl * sizeof(int64_t);
-    q = (char *)(((uintptr_t)q + 255) & ~(uintptr_t)255);
+    q += (size_t)nl * L.KP * sizeof(uint64_t);  // KP >= 64: every region stays 256-byte aligned
     c.cand_sse = (double *)q;
     q += (size_t)nl * L.KP * sizeof(double);
     c.cand_rank = (uint64_t *)q;
@@ -178,7 +193,7 @@ extern "C" int32_t sisso_l0_create(const sisso_l0_desc *d, sisso_l0 **out) {
     if (!d->F || !d->y || !d->task_offsets || !d->workspace)
         return fail(nullptr, SISSO_EINVAL, "null F, y, task_offsets or workspace");
     if (!shape_ok(d)) return fail(nullptr, SISSO_EINVAL, "shape out of range (n_total, S, T, D_max, k_max)");
-    if (d->precision != SISSO_PREC_FP64) return fail(nullptr, SISSO_ENOTSUP, "unknown precision mode");
+    if (precision_slices(d->precision) < 0) return fail(nullptr, SISSO_ENOTSUP, "unknown precision mode");
     const int64_t *o = d->task_offsets;
     if (o[0] != 0 || o[d->T] != d->n_total) return fail(nullptr, SISSO_EINVAL, "task offsets must span [0, n_total)");
     for (int t = 0; t < d->T; ++t)
@@ -191,10 +206,17 @@ extern "C" int32_t sisso_l0_create(const sisso_l0_desc *d, sisso_l0 **out) {
     h->desc = *d;
     h->offsets.assign(o, o + d->T + 1);
     h->desc.task_offsets = h->offsets.data();
-    h->lay = compute_layout(d->n_total, d->S, d->T, d->D_max, d->k_max);
+    h->lay = compute_layout(d->n_total, d->S, d->T, d->D_max, d->k_max, precision_slices(d->precision));
     h->stream = (hipStream_t)d->stream;
     carve(h);
+    // precision form: chunks of LP_XC samples per task (the count never
+    // exceeds the bound the layout was sized with)
+    std::vector<int32_t> cbase(d->T + 1, 0);
+    for (int t = 0; t < d->T; ++t) cbase[t + 1] = cbase[t] + (int32_t)((o[t + 1] - o[t] + LP_XC - 1) / LP_XC);
+    h->ctx.lp_nchunk = h->lay.lp_ns ? cbase[d->T] : 0;
     if (hipMemcpyAsync(h->ctx.off_dev, h->offsets.data(), (d->T + 1) * sizeof(int64_t), hipMemcpyHostToDevice,
+                       h->stream) != hipSuccess ||
+        hipMemcpyAsync(h->ctx.lp_cbase, cbase.data(), (d->T + 1) * sizeof(int32_t), hipMemcpyHostToDevice,
                        h->stream) != hipSuccess ||
         hipStreamSynchronize(h->stream) != hipSuccess) {
         delete h;
@@ -322,6 +344,27 @@ extern "C" int32_t sisso_l0_search_stats(sisso_l0 *h, uint64_t *out) {
     hipError_t e = hipMemcpyAsync(out, h->ctx.stats, 4 * sizeof(uint64_t), hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return fail(h, SISSO_EDEVICE, hipGetErrorString(e));
+    return SISSO_OK;
+}
+
+extern "C" int32_t sisso_l0_precision_report(sisso_l0 *h, int32_t nsample, double *out) {
+    if (!h || !out || nsample < 1) return SISSO_EINVAL;
+    h->err.clear();
+    if (!h->gram_done) return fail(h, SISSO_ESTATE, "sisso_gram has not run");
+    uint64_t bits[2] = {0, 0};
+    hipError_t e = hipMemsetAsync(h->ctx.err_bits, 0, sizeof(uint64_t), h->stream);
+    if (e == hipSuccess && launch_gram_check(h->ctx, nsample, h->ctx.err_bits, h->stream)) e = hipGetLastError();
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(bits, h->ctx.err_bits, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return fail(h, SISSO_EDEVICE, hipGetErrorString(e));
+    double g, s;
+    memcpy(&g, &bits[0], sizeof g);
+    memcpy(&s, &bits[1], sizeof s);
+    out[0] = g;
+    out[1] = (double)nsample * h->desc.T;
+    out[2] = h->search_done ? s : 0.0;
+    out[3] = h->lay.lp_ns;
     return SISSO_OK;
 }
 

@@ -20,6 +20,7 @@ constexpr int SUBP = 4;                // sub-prefixes sharing one Gram load (si
 constexpr int PRE_M = 16;              // features the threshold pre-pass starts from
 constexpr int PRE_Q = 8;               // best prefixes the pre-pass extends by every feature
 constexpr int KP_MAX = 512;            // longest per-wave candidate list
+constexpr int LP_XC = 256;             // precision form: samples per slice-exponent chunk
 
 // ---------------------------------------------------------------- binomials
 // C(n, r) exactly in 64-bit arithmetic, saturating at UINT64_MAX (never
@@ -189,7 +190,10 @@ struct Layout {
     size_t G;          // double [S][S][TP] correlation matrices, task fastest
     size_t part;       // double [nsplit][T][S][S] raw centred Gram partial sums
     size_t flags;      // uint32 [64] device status words
-    size_t tile_cnt;   // uint32 [T][tile pairs] Gram split counters
+    size_t lp_cbase;   // int32 [T+1] precision form: first chunk of each task
+    size_t lp_exp;     // int32 [S][nchunk] precision form: chunk exponents
+    size_t lp_slices;  // bf16 [NS][S][nchunk * LP_XC] precision form: slices
+    size_t stat_bits;  // uint64 [4] error report scratch
     size_t pre;        // pre-pass scratch
     size_t lists;      // per-wave top lists: (double sse, uint64 rank) [nwaves][KP]
     size_t merged;     // merged candidates [KP] (sse, rank)
@@ -204,6 +208,8 @@ struct Layout {
     int KP;            // list length per wave (power of two >= k_max + margin)
     int nwaves;        // persistent search waves
     int search_wgs;    // persistent search workgroups
+    int lp_ns;         // precision form: slices per value (0 = FP64 Gram)
+    int lp_nchunk;     // precision form: chunks over all tasks
 };
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }

@@ -79,17 +79,24 @@ __global__ __launch_bounds__(256) void stats_x_kernel(const double *__restrict__
     s = wave_sum(s);
     const double m = s / (double)(r1 - r0);
     const double ym = ybar[t];
-    double ss = 0.0, sy = 0.0;
+    double ss = 0.0, sy = 0.0, sr = 0.0;
     for (int64_t i = r0 + lane; i < r1; i += 64) {
-        double d = col[i] - m;
+        const double v = col[i];
+        const double d = v - m;
         ss += d * d;
         sy += d * (y[i] - ym);
+        sr += v * v;
     }
     ss = wave_sum(ss);
     sy = wave_sum(sy);
+    sr = wave_sum(sr);
     if (__any(bad) && lane == 0) atomicOr(&flags[FLAG_NONFINITE], 1u);
     if (lane == 0) {
-        const double is = (ss > 0.0 && isfinite(ss)) ? 1.0 / sqrt(ss) : 0.0;
+        // a column constant on the task up to RANK_EPS (1 - uncentred R^2 on
+        // the intercept: |x - mean|^2 <= RANK_EPS |x|^2) is treated as
+        // constant: its centred values would be rounding noise
+        const bool live = ss > RANK_EPS * sr && isfinite(ss);
+        const double is = live ? 1.0 / sqrt(ss) : 0.0;
         mu[(int64_t)t * S + j] = m;
         inv_s[(int64_t)t * S + j] = is;
         bhat[j * TP + t] = sy * is;
@@ -108,7 +115,9 @@ typedef double double4_t __attribute__((ext_vector_type(4)));
 
 constexpr int LDS_STRIDE = GRAM_TILE + 16;  // 144 doubles: rows k, k+1 land on opposite bank halves
 
-__global__ __launch_bounds__(256) void gram_kernel(const double *__restrict__ F, int64_t n_total,
+// One wave per SIMD is all this launch needs (about one workgroup per CU), so
+// the register budget is the whole file: no spills around the prefetch.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void gram_kernel(const double *__restrict__ F, int64_t n_total,
                                                    int64_t S, const int64_t *__restrict__ off,
                                                    int T, const double *__restrict__ mu,
                                                    int ntile, int nsplit,
@@ -138,7 +147,7 @@ __global__ __launch_bounds__(256) void gram_kernel(const double *__restrict__ F,
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wr = (wave >> 1) * 64;  // wave's row offset inside the tile
     const int wc = (wave & 1) * 64;   // wave's column offset
     const double *mut = mu + (int64_t)t * S;
@@ -162,38 +171,47 @@ __global__ __launch_bounds__(256) void gram_kernel(const double *__restrict__ F,
     }
 
     // register-staged double buffering: the global loads of chunk c+1 are in
-    // flight while the MFMAs of chunk c run out of LDS.  Diagonal tiles
-    // (bi == bj) load one operand and read it twice.
-    const bool diag = (bi == bj);
+    // flight while the MFMAs of chunk c run out of LDS.  Loads are
+    // unconditional (row and feature clamped into range); masking and centring
+    // happen at the LDS store, so no load is waited on before the MFMAs.
+    int64_t fa[GRAM_TILE / 16], fb[GRAM_TILE / 16];
+    bool ina[GRAM_TILE / 16], inb[GRAM_TILE / 16];
+#pragma unroll
+    for (int r = 0; r < GRAM_TILE / 16; ++r) {
+        const int64_t ga = (int64_t)bi * GRAM_TILE + f0 + 16 * r;
+        const int64_t gb = (int64_t)bj * GRAM_TILE + f0 + 16 * r;
+        ina[r] = ga < S;
+        inb[r] = gb < S;
+        fa[r] = (ina[r] ? ga : S - 1) * n_total;
+        fb[r] = (inb[r] ? gb : S - 1) * n_total;
+    }
     double sa[GRAM_TILE / 16], sb[GRAM_TILE / 16];
-    auto load_chunk = [&](int64_t c) {
-        const int64_t row = r0 + c * GRAM_KC + kk;
-        const bool rin = row < r1;
-#pragma unroll
-        for (int r = 0; r < GRAM_TILE / 16; ++r) {
-            const int f = f0 + 16 * r;
-            const int64_t ga = (int64_t)bi * GRAM_TILE + f;
-            const int64_t gb = (int64_t)bj * GRAM_TILE + f;
-            sa[r] = (rin && ga < S) ? F[ga * n_total + row] - muA[r] : 0.0;
-            if (!diag) sb[r] = (rin && gb < S) ? F[gb * n_total + row] - muB[r] : 0.0;
-        }
-    };
-    auto store_chunk = [&]() {
-#pragma unroll
-        for (int r = 0; r < GRAM_TILE / 16; ++r) {
-            As[kk][f0 + 16 * r] = sa[r];
-            if (!diag) Bs[kk][f0 + 16 * r] = sb[r];
-        }
-    };
-    double (*Bsrc)[LDS_STRIDE] = diag ? As : Bs;
+    int64_t row = r0 + c0 * GRAM_KC + kk;
     if (c0 < c1) {
-        load_chunk(c0);
-        store_chunk();
+        const int64_t rowc = row < r1 ? row : r1 - 1;
+#pragma unroll
+        for (int r = 0; r < GRAM_TILE / 16; ++r) {
+            sa[r] = F[fa[r] + rowc];
+            sb[r] = F[fb[r] + rowc];
+        }
+#pragma unroll
+        for (int r = 0; r < GRAM_TILE / 16; ++r) {
+            As[kk][f0 + 16 * r] = (row < r1 && ina[r]) ? sa[r] - muA[r] : 0.0;
+            Bs[kk][f0 + 16 * r] = (row < r1 && inb[r]) ? sb[r] - muB[r] : 0.0;
+        }
     }
     __syncthreads();
     for (int64_t c = c0; c < c1; ++c) {
         const bool more = c + 1 < c1;
-        if (more) load_chunk(c + 1);
+        row += GRAM_KC;
+        if (more) {
+            const int64_t rowc = row < r1 ? row : r1 - 1;
+#pragma unroll
+            for (int r = 0; r < GRAM_TILE / 16; ++r) {
+                sa[r] = F[fa[r] + rowc];
+                sb[r] = F[fb[r] + rowc];
+            }
+        }
 #pragma unroll
         for (int ks = 0; ks < GRAM_KC / 4; ++ks) {
             const int krow = ks * 4 + (lane >> 4);
@@ -201,7 +219,7 @@ __global__ __launch_bounds__(256) void gram_kernel(const double *__restrict__ F,
 #pragma unroll
             for (int m = 0; m < 4; ++m) a[m] = As[krow][wr + m * 16 + (lane & 15)];
 #pragma unroll
-            for (int m = 0; m < 4; ++m) bv[m] = Bsrc[krow][wc + m * 16 + (lane & 15)];
+            for (int m = 0; m < 4; ++m) bv[m] = Bs[krow][wc + m * 16 + (lane & 15)];
 #pragma unroll
             for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -209,7 +227,13 @@ __global__ __launch_bounds__(256) void gram_kernel(const double *__restrict__ F,
                     acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], bv[n], acc[m][n], 0, 0, 0);
         }
         __syncthreads();
-        if (more) store_chunk();
+        if (more) {
+#pragma unroll
+            for (int r = 0; r < GRAM_TILE / 16; ++r) {
+                As[kk][f0 + 16 * r] = (row < r1 && ina[r]) ? sa[r] - muA[r] : 0.0;
+                Bs[kk][f0 + 16 * r] = (row < r1 && inb[r]) ? sb[r] - muB[r] : 0.0;
+            }
+        }
         __syncthreads();
     }
 
@@ -294,18 +318,13 @@ int launch_untile(const Ctx &c, int t, double *dst, hipStream_t st) {
 }
 
 // ------------------------------------------------------------- launchers
-__global__ void clear_flags_kernel(uint32_t *flags, unsigned int *tile_cnt, int64_t ncnt) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < 64) flags[e] = 0u;
-    if (e < ncnt) tile_cnt[e] = 0u;
+__global__ void clear_flags_kernel(uint32_t *flags) {
+    if (threadIdx.x < 64) flags[threadIdx.x] = 0u;
 }
 
 int launch_stats(const Ctx &c, hipStream_t st) {
     phase_begin(c, SISSO_PHASE_STATS, st);
-    const int64_t ntile = (c.S + GRAM_TILE - 1) / GRAM_TILE;
-    const int64_t ncnt = c.T * ntile * (ntile + 1) / 2;
-    hipLaunchKernelGGL(clear_flags_kernel, dim3((unsigned)((ncnt + 64 + 255) / 256)), dim3(256), 0, st, c.flags,
-                       c.tile_cnt, ncnt);
+    hipLaunchKernelGGL(clear_flags_kernel, dim3(1), dim3(64), 0, st, c.flags);
     hipLaunchKernelGGL(stats_y_kernel, dim3((c.T + 3) / 4), dim3(256), 0, st, c.y, c.off_dev, c.T,
                        c.ybar, c.cyy, c.flags);
     const int64_t jobs = c.S * c.T;
@@ -319,8 +338,12 @@ int launch_gram(const Ctx &c, hipStream_t st) {
     const int ntile = (int)((c.S + GRAM_TILE - 1) / GRAM_TILE);
     const int64_t blocks = (int64_t)c.nsplit * c.T * ntile * (ntile + 1) / 2;
     phase_begin(c, SISSO_PHASE_GRAM, st);
-    hipLaunchKernelGGL(gram_kernel, dim3((unsigned)blocks), dim3(256), 0, st, c.F, c.n_total, c.S,
-                       c.off_dev, c.T, c.mu, ntile, c.nsplit, c.part);
+    if (c.lp_ns > 0) {
+        if (launch_gram_lp(c, c.lp_ns, st)) return -1;
+    } else {
+        hipLaunchKernelGGL(gram_kernel, dim3((unsigned)blocks), dim3(256), 0, st, c.F, c.n_total, c.S,
+                           c.off_dev, c.T, c.mu, ntile, c.nsplit, c.part);
+    }
     const int64_t npair64 = c.Gnt * (c.Gnt + 1) / 2;
     hipLaunchKernelGGL(gram_finish_kernel, dim3((unsigned)(npair64 * c.T)), dim3(256), 0, st, c.part, c.S, c.T,
                        c.TP, c.nsplit, c.inv_s, c.G, c.Gnt);

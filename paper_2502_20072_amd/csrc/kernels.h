@@ -16,10 +16,14 @@ struct Ctx {
     int64_t *off_dev;
     double *ybar, *cyy, *mu, *inv_s, *bhat, *G, *part;
     uint32_t *flags;
-    unsigned int *tile_cnt;          // Gram: finished splits per (task, tile pair)
+    int32_t *lp_cbase;               // precision form: first chunk of each task [T+1]
+    int32_t *lp_exp;                 // precision form: chunk exponents [S][lp_nchunk]
+    __bf16 *lp_slices;               // precision form: slices [NS][S][lp_nchunk * LP_XC]
+    unsigned long long *err_bits;    // error report: max |G error| bit pattern
     unsigned long long *theta_bits;  // shared SSE bound (bit pattern of a non-negative double)
     unsigned int *work_counter;      // next search work item
     unsigned int *cand_counter;      // slow-path candidates seen (diagnostics)
+    unsigned int *merge_count;       // merge: candidates appended
     uint64_t *stats;                 // [4]: candidates, work items, theta0 bits, final theta bits
     uint64_t *cum;                   // cumulative work items per j-block [S/JBLK + 2]
     uint64_t *btab;                  // binomials C(n, r), r <= SISSO_MAX_D, n <= S
@@ -29,8 +33,6 @@ struct Ctx {
     double *pre_bound;               // pre-pass: per-prefix L-th best [PRE_Q]
     double *list_sse;                // per-wave lists [nwaves][KP]
     uint64_t *list_rank;
-    int32_t *list_count;             // merge: entries <= bound per list [nwaves]
-    int64_t *list_offset;            // merge: exclusive scan of list_count [nwaves + 1]
     double *cand_sse;                // merge: compacted candidates [nwaves * KP]
     uint64_t *cand_rank;
     double *merged_sse;              // [KP]
@@ -41,6 +43,7 @@ struct Ctx {
     double *res_sse;                 // [k_max]
     double *res_coef;                // [k_max][T][D_max+1]
     int nsplit, KP, nwaves, search_wgs, D_max, k_max;
+    int lp_ns, lp_nchunk;            // precision form: slices per value (0 = FP64), chunks
     // host-side: start/stop events per phase when profiling is on (else null)
     hipEvent_t *ev;
 };
@@ -60,7 +63,9 @@ struct SearchCall {
 };
 
 int launch_stats(const Ctx &c, hipStream_t st);
-int launch_gram(const Ctx &c, hipStream_t st);
+int launch_gram(const Ctx &c, hipStream_t st);  // FP64 MFMA or precision form, then finish
+int launch_gram_lp(const Ctx &c, int NS, hipStream_t st);
+int launch_gram_check(const Ctx &c, int nsample, unsigned long long *out_bits, hipStream_t st);
 int launch_untile(const Ctx &c, int t, double *dst, hipStream_t st);
 int launch_search(const Ctx &c, const SearchCall &sc, hipStream_t st);
 

@@ -79,30 +79,55 @@ __device__ inline double Gat(const Ctx &c, int64_t i, int64_t k, int t) {
 // ----------------------------------------------------------------- helpers
 // Normal-equation SSE of one sorted tuple summed over tasks, from the
 // correlation matrices (Cholesky in increasing index order).  +inf when a
-// pivot is <= RANK_EPS in some task.  Used by the threshold pre-pass.
-__device__ double ne_sse(const Ctx &c, int D, const int32_t *tup) {
+// pivot is <= RANK_EPS in some task.  Used by the threshold pre-pass.  All
+// entries a task needs are loaded before any arithmetic, so the loads of one
+// call overlap instead of forming a chain.
+template <int D>
+__device__ double ne_sse_t(const Ctx &c, const int32_t *tup) {
     double total = 0.0;
+    bool ok = true;
     for (int t = 0; t < c.T; ++t) {
-        double L[MAXD][MAXD], z[MAXD];
-        double p = c.cyy[t];
+        double g[D][D], bv[D];
+#pragma unroll
         for (int m = 0; m < D; ++m) {
+#pragma unroll
+            for (int j = 0; j <= m; ++j) g[m][j] = Gat(c, tup[m], tup[j], t);
+            bv[m] = c.bhat[(int64_t)tup[m] * c.TP + t];
+        }
+        double L[D][D], z[D];
+        double p = c.cyy[t];
+#pragma unroll
+        for (int m = 0; m < D; ++m) {
+#pragma unroll
             for (int j = 0; j < m; ++j) {
-                double s = Gat(c, tup[m], tup[j], t);
+                double s = g[m][j];
+#pragma unroll
                 for (int l = 0; l < j; ++l) s -= L[m][l] * L[j][l];
                 L[m][j] = s / L[j][j];
             }
-            double d = Gat(c, tup[m], tup[m], t);
+            double d = g[m][m];
+#pragma unroll
             for (int l = 0; l < m; ++l) d -= L[m][l] * L[m][l];
-            if (!(d > RANK_EPS)) return INF;
-            L[m][m] = sqrt(d);
-            double zm = c.bhat[(int64_t)tup[m] * c.TP + t];
+            ok &= d > RANK_EPS;
+            L[m][m] = sqrt(fmax(d, RANK_EPS));
+            double zm = bv[m];
+#pragma unroll
             for (int l = 0; l < m; ++l) zm -= L[m][l] * z[l];
             z[m] = zm / L[m][m];
             p -= z[m] * z[m];
         }
         total += p;
     }
-    return total;
+    return ok ? total : INF;
+}
+
+__device__ double ne_sse(const Ctx &c, int D, const int32_t *tup) {
+    switch (D) {
+        case 1: return ne_sse_t<1>(c, tup);
+        case 2: return ne_sse_t<2>(c, tup);
+        case 3: return ne_sse_t<3>(c, tup);
+        default: return ne_sse_t<4>(c, tup);
+    }
 }
 
 // Sorted per-wave list in LDS: entries e = lane + 64 m, m < KP/64.
@@ -160,6 +185,7 @@ __global__ void search_init_kernel(Ctx c, int D, int R, int JB) {
         *c.cand_counter = 0;
         *c.theta_bits = (unsigned long long)__double_as_longlong(INF);
         *c.pre_count = 0;
+        *c.merge_count = 0;
         c.stats[1] = 0;
         const int q = D - 2;
         const int64_t nblk = (c.S - 1 + JB - 1) / JB;
@@ -574,7 +600,7 @@ __global__ __launch_bounds__(256) void search_kernel(Ctx c, SearchArgs a) {
     const int KP = a.KP;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform (kept in an SGPR)
 
     // LDS carve: per-wave lists, records [256][RECW], sub-prefix factors
     double *Ls = smem + (size_t)wave * KP * 2;
@@ -778,21 +804,26 @@ __global__ __launch_bounds__(256) void search_kernel(Ctx c, SearchArgs a) {
             double wq[NR][QA], dq[NR], zq[NR];
             hoist_k<D, NR, MT>(c, subf, &s_sub[0][0], kc, myt, wq, dq, zq);
             const bool check = (kb <= jhi) || (kb + KL > c.S);
-            // G rows of the tile (j-block, k-chunk): a uniform row pointer plus a
-            // 32-bit lane offset; lanes past S read the tile's zero padding
-            const int64_t rs = (int64_t)GT * c.TP;
-            const int ko = (int)((k & (GT - 1)) * c.TP + myt);
+            // G rows of the tile (j-block, k-chunk): a uniform pointer to row j0
+            // plus 32-bit row and lane offsets (one task: TP = 1).  Rows are
+            // clamped to the block's last row, which lies inside the tile; lanes
+            // past S read the tile's zero padding.
+            const int TPk = MT ? c.TP : 1;
+            const int rs = GT * TPk;
+            const int ko = (int)(k & (GT - 1)) * TPk + myt;
+            const int nrow = (int)(jhi - j0);            // last row of the block, < 64
+            const int kr = (int)(k - j0);                // lane's k relative to j0 (> row means k > j)
             const double *__restrict__ gp =
-                Gbase + ((((j0 >> 6) * c.Gnt + (kb >> 6)) << 12) + ((j0 & (GT - 1)) << 6)) * c.TP;
+                Gbase + ((((j0 >> 6) * c.Gnt + (kb >> 6)) << 12) + ((j0 & (GT - 1)) << 6)) * TPk;
             int nq = 0;  // steps of this chunk where some lane passed the filter
             // the j sweep, versioned on whether lanes need the k > j / k < S masks
             auto sweep = [&](auto checkc) {
                 constexpr bool CHECK = decltype(checkc)::value;
-                auto body = [&](int64_t j, double g) {
-                    const int jj = (int)(j - j0);
+                auto body = [&](int jj, double g, bool live) {
                     unsigned long long m = 0;
                     if (MT) {
-                        if (!s_mask[jj]) return;
+                        // a j whose record is invalid in some task has p = NaN
+                        // there, so its task sum fails the comparison
                         const double *rr = recs + (jj * TL + myt) * RECW;
                         double rv[q + 4];
 #pragma unroll
@@ -829,7 +860,8 @@ __global__ __launch_bounds__(256) void search_kernel(Ctx c, SearchArgs a) {
                             m |= __ballot(z * z >= rv[r][q + 2] * d);
                         }
                     }
-                    if (CHECK) m &= __ballot(kin && k > j);
+                    if (CHECK) m &= __ballot(kin && kr > jj);
+                    m = live ? m : 0ull;
                     if (m) {
                         if (lane == 0) {
                             qmask[nq] = m;
@@ -843,25 +875,41 @@ __global__ __launch_bounds__(256) void search_kernel(Ctx c, SearchArgs a) {
                 // group is scored
                 constexpr int JG = 8;
                 double ga[JG], gb[JG];
-                auto fetch = [&](double (&dst)[JG], int64_t jg) {
+                // a uniform 64-bit base plus a 32-bit byte offset per load
+                // (uniform row part + per-lane column part)
+                const char *__restrict__ gpc = reinterpret_cast<const char *>(gp);
+                const uint32_t ko8 = (uint32_t)ko * 8u;
+                auto fetch = [&](double (&dst)[JG], int jg) {
 #pragma unroll
                     for (int x = 0; x < JG; ++x) {
-                        const int64_t jr = (jg + x <= jhi) ? jg + x : jhi;
-                        dst[x] = gp[(jr - j0) * rs + ko];
+                        const int jr = jg + x < nrow ? jg + x : nrow;
+                        const uint32_t ro = (uint32_t)(jr * rs) * 8u;
+                        dst[x] = *reinterpret_cast<const double *>(gpc + (ro + ko8));
                     }
                 };
-                auto score = [&](const double (&src)[JG], int64_t jg) {
+                // every fetched row is scored (rows past the block repeat its
+                // last row and are masked out), so no load is left pending on
+                // a skipped path
+                auto score = [&](const double (&src)[JG], int jg) {
 #pragma unroll
-                    for (int x = 0; x < JG; ++x)
-                        if (jg + x <= jhi) body(jg + x, src[x]);
+                    for (int x = 0; x < JG; ++x) {
+                        const int jj = jg + x;
+                        body(jj <= nrow ? jj : nrow, src[x], jj <= nrow);
+                    }
                 };
-                fetch(ga, j0);
-                for (int64_t jg = j0; jg <= jhi; jg += 2 * JG) {
+                // drain the loads of the chunk set-up first, so that only the
+                // row prefetches are outstanding when the sweep loop starts
+                // (vmcnt(0); expcnt and lgkmcnt not waited on)
+                __builtin_amdgcn_s_waitcnt(0x0F70);
+                // one exit at the bottom: every path into the loop head has the
+                // same loads outstanding, so the head needs no full drain
+                fetch(ga, 0);
+                for (int jg = 0;; jg += 2 * JG) {
                     fetch(gb, jg + JG);
                     score(ga, jg);
-                    if (jg + JG > jhi) break;
                     fetch(ga, jg + 2 * JG);
                     score(gb, jg + JG);
+                    if (jg + 2 * JG > nrow) break;
                 }
             };
             if (check) sweep(std::true_type{});
@@ -955,64 +1003,54 @@ __device__ void bitonic_sort_lds(double *ks, uint64_t *kr, int N) {
     }
 }
 
-__global__ __launch_bounds__(MERGE_THREADS) void merge_kernel(Ctx c, int nlists, int KP, int L, int use_pre) {
+// merge_compact: one wave per list.  Lists are sorted ascending, so the
+// entries at or below the bound are a prefix; its length is a ballot count
+// and the prefix is appended to the candidate array at an atomically
+// reserved offset.  The candidate set does not depend on the append order,
+// and keys are unique, so the selection below is deterministic.
+__device__ inline double merge_bound(const Ctx &c, int L, int KP, int use_pre) {
+    double bound = theta_load(c.theta_bits);
+    if (use_pre) bound = fmin(bound, theta0_from_prepass(c, L, KP));
+    return bound < INF ? bound * (1.0 + THETA_SLACK) : INF;
+}
+
+__global__ __launch_bounds__(MERGE_THREADS) void merge_compact_kernel(Ctx c, int nlists, int KP, int L,
+                                                                      int use_pre) {
+    const int lane = threadIdx.x & 63;
+    const int64_t l = (int64_t)blockIdx.x * (MERGE_THREADS / 64) + (threadIdx.x >> 6);
+    if (l >= nlists) return;
+    const double bound = merge_bound(c, L, KP, use_pre);
+    const double *ls = c.list_sse + l * KP;
+    const uint64_t *lr = c.list_rank + l * KP;
+    int n = 0;
+    for (int m = 0; m < KP; m += 64) {
+        const double v = ls[m + lane];
+        n += __popcll(__ballot(v < INF && v <= bound));
+    }
+    if (n == 0) return;
+    unsigned base = 0;
+    if (lane == 0) base = atomicAdd(c.merge_count, (unsigned)n);
+    base = __shfl(base, 0);
+    for (int e = lane; e < n; e += 64) {
+        c.cand_sse[base + e] = ls[e];
+        c.cand_rank[base + e] = lr[e];
+    }
+}
+
+// merge_select: one workgroup selects the KP smallest (SSE, key) pairs of
+// the candidates with bitonic sorts in LDS, carrying a running top-KP across
+// chunks when there are many.
+__global__ __launch_bounds__(MERGE_THREADS) void merge_select_kernel(Ctx c, int KP, int L, int use_pre) {
     __shared__ double ks[MERGE_CAP];
     __shared__ uint64_t kr[MERGE_CAP];
-    __shared__ int64_t s_tot;
-    __shared__ int64_t wsum[MERGE_THREADS / 64];
     const int tid = threadIdx.x;
-    double bound = theta_load(c.theta_bits);
-    const double th0 = use_pre ? theta0_from_prepass(c, L, KP) : INF;
+    const int64_t total = *c.merge_count;
     if (tid == 0) {
+        const double th0 = use_pre ? theta0_from_prepass(c, L, KP) : INF;
         c.stats[0] = *c.cand_counter;
         c.stats[2] = (uint64_t)__double_as_longlong(th0);
-        c.stats[3] = (uint64_t)__double_as_longlong(bound);
+        c.stats[3] = (uint64_t)__double_as_longlong(theta_load(c.theta_bits));
     }
-    if (use_pre) bound = fmin(bound, th0);
-    bound = bound < INF ? bound * (1.0 + THETA_SLACK) : INF;
-    // counts per list (lists are sorted ascending)
-    for (int l = tid; l < nlists; l += MERGE_THREADS) {
-        int n = 0;
-        const double *ls = c.list_sse + (int64_t)l * KP;
-        while (n < KP && ls[n] < INF && ls[n] <= bound) ++n;
-        c.list_count[l] = n;
-    }
-    __syncthreads();
-    // exclusive scan (serial over chunks per thread, then block scan)
-    const int per = (nlists + MERGE_THREADS - 1) / MERGE_THREADS;
-    int64_t local = 0;
-    for (int l = tid * per; l < nlists && l < (tid + 1) * per; ++l) local += c.list_count[l];
-    // block exclusive scan of local
-    int64_t incl = local;
-    for (int o = 1; o < 64; o <<= 1) {
-        const int64_t v = __shfl_up(incl, o);
-        if ((tid & 63) >= o) incl += v;
-    }
-    if ((tid & 63) == 63) wsum[tid >> 6] = incl;
-    __syncthreads();
-    if (tid == 0) {
-        int64_t acc = 0;
-        for (int w = 0; w < MERGE_THREADS / 64; ++w) {
-            const int64_t v = wsum[w];
-            wsum[w] = acc;
-            acc += v;
-        }
-        s_tot = acc;
-    }
-    __syncthreads();
-    int64_t off = wsum[tid >> 6] + incl - local;
-    for (int l = tid * per; l < nlists && l < (tid + 1) * per; ++l) {
-        const int n = c.list_count[l];
-        for (int e = 0; e < n; ++e) {
-            c.cand_sse[off + e] = c.list_sse[(int64_t)l * KP + e];
-            c.cand_rank[off + e] = c.list_rank[(int64_t)l * KP + e];
-        }
-        off += n;
-    }
-    __threadfence_block();
-    __syncthreads();
-    const int64_t total = s_tot;
-    // running selection
     for (int i = tid; i < MERGE_CAP; i += MERGE_THREADS) {
         ks[i] = INF;
         kr[i] = ~0ull;
@@ -1050,7 +1088,7 @@ __global__ __launch_bounds__(MERGE_THREADS) void merge_kernel(Ctx c, int nlists,
 // squared norm of the explicit residual y_c - X_c beta.
 __global__ __launch_bounds__(256) void rescore_kernel(Ctx c, int D) {
     constexpr int NACC = MAXD * (MAXD + 1) / 2 + MAXD;
-    __shared__ double red[NACC][256];
+    __shared__ double red[NACC][4];
     __shared__ double s_beta[MAXD];
     __shared__ int s_ok;
     const int cand = blockIdx.x;
@@ -1083,13 +1121,15 @@ __global__ __launch_bounds__(256) void rescore_kernel(Ctx c, int D) {
             for (int m = 0; m < D; ++m) acc[e++] += x[m] * yc;
         }
         const int nacc = D * (D + 1) / 2 + D;
-        for (int i = 0; i < nacc; ++i) red[i][tid] = acc[i];
-        __syncthreads();
-        for (int o = 128; o > 0; o >>= 1) {
-            if (tid < o)
-                for (int i = 0; i < nacc; ++i) red[i][tid] += red[i][tid + o];
-            __syncthreads();
+        // wave butterflies, then the 4 wave sums in a fixed order
+        for (int i = 0; i < nacc; ++i) {
+            double v = acc[i];
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+            if ((tid & 63) == 0) red[i][tid >> 6] = v;
         }
+        __syncthreads();
+        if (tid < nacc) red[tid][0] = ((red[tid][0] + red[tid][1]) + red[tid][2]) + red[tid][3];
+        __syncthreads();
         if (tid == 0) {
             double M[MAXD][MAXD], v[MAXD], L[MAXD][MAXD], z[MAXD];
             int e = 0;
@@ -1140,14 +1180,11 @@ __global__ __launch_bounds__(256) void rescore_kernel(Ctx c, int D) {
             for (int m = 0; m < D; ++m) e -= beta[m] * (c.F[(int64_t)tup[m] * c.n_total + i] - mu[m]);
             ss += e * e;
         }
-        red[0][tid] = ss;
+        for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o);
+        if ((tid & 63) == 0) red[0][tid >> 6] = ss;
         __syncthreads();
-        for (int o = 128; o > 0; o >>= 1) {
-            if (tid < o) red[0][tid] += red[0][tid + o];
-            __syncthreads();
-        }
         if (tid == 0) {
-            total += red[0][0];
+            total += ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
             double alpha = ym;
             for (int m = 0; m < D; ++m) alpha -= beta[m] * mu[m];
             coef[t * (c.D_max + 1)] = alpha;
@@ -1161,25 +1198,39 @@ __global__ __launch_bounds__(256) void rescore_kernel(Ctx c, int D) {
 
 // ----------------------------------------------------------------- final
 // Order the re-scored candidates by (SSE, rank) (rank by counting; invalid
-// ones last in candidate order) and write the k best.
+// ones last in candidate order) and write the k best.  The KP keys are staged
+// in LDS once, so each thread's count runs over LDS.
 __global__ __launch_bounds__(1024) void final_kernel(Ctx c, int D, int k, int KP) {
+    __shared__ double fs[KP_MAX];
+    __shared__ uint64_t fr[KP_MAX];
+    __shared__ double ferr[1024 / 64];
     for (int i = threadIdx.x; i < KP; i += blockDim.x) {
         const double si = c.resc_sse[i];
-        const uint64_t ri = c.merged_rank[i];
+        fs[i] = si < INF ? si : INF;
+        fr[i] = c.merged_rank[i];
+    }
+    __syncthreads();
+    double err = 0.0;  // largest relative gap between the ranked and the exact SSE of a result
+    for (int i = threadIdx.x; i < KP; i += blockDim.x) {
+        const double si = fs[i];
+        const uint64_t ri = fr[i];
         const bool vi = si < INF;
         int pos = 0;
         for (int j = 0; j < KP; ++j) {
-            const double sj = c.resc_sse[j];
+            const double sj = fs[j];
             const bool vj = sj < INF;
-            const uint64_t rj = c.merged_rank[j];
             bool before;
-            if (vi && vj) before = key_less(sj, rj, si, ri);
+            if (vi && vj) before = key_less(sj, fr[j], si, ri);
             else if (vj) before = true;
             else if (vi) before = false;
             else before = j < i;
             pos += before;
         }
         if (pos < k) {
+            if (vi) {
+                const double a = c.merged_sse[i];
+                err = fmax(err, si > 0.0 ? fabs(a - si) / si : fabs(a - si));
+            }
             c.res_sse[pos] = vi ? si : INF;
             int32_t tup[MAXD];
             if (vi) unpack_tuple(ri, D, tup);
@@ -1190,12 +1241,27 @@ __global__ __launch_bounds__(1024) void final_kernel(Ctx c, int D, int k, int KP
                         vi ? c.resc_coef[((int64_t)i * c.T + t) * (c.D_max + 1) + m] : __builtin_nan("");
         }
     }
+    for (int o = 32; o >= 1; o >>= 1) err = fmax(err, __shfl_xor(err, o));
+    if ((threadIdx.x & 63) == 0) ferr[threadIdx.x >> 6] = err;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double e = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) e = fmax(e, ferr[w]);
+        c.err_bits[1] = (unsigned long long)__double_as_longlong(e);
+    }
 }
 
 // -------------------------------------------------------------- launcher
 template <int D, bool MT>
 static void launch_one(const Ctx &c, const SearchArgs &a, size_t lds, hipStream_t st) {
     hipLaunchKernelGGL((search_kernel<D, MT>), dim3(c.search_wgs), dim3(SEARCH_WG), lds, st, c, a);
+}
+
+static void launch_merge(const Ctx &c, int nlists, int L, int use_pre, hipStream_t st) {
+    const int per = MERGE_THREADS / 64;
+    hipLaunchKernelGGL(merge_compact_kernel, dim3((nlists + per - 1) / per), dim3(MERGE_THREADS), 0, st, c, nlists,
+                       c.KP, L, use_pre);
+    hipLaunchKernelGGL(merge_select_kernel, dim3(1), dim3(MERGE_THREADS), 0, st, c, c.KP, L, use_pre);
 }
 
 int launch_search(const Ctx &c, const SearchCall &sc, hipStream_t st) {
@@ -1228,8 +1294,7 @@ int launch_search(const Ctx &c, const SearchCall &sc, hipStream_t st) {
         hipLaunchKernelGGL(search_d1_kernel, dim3(wgs), dim3(SEARCH_WG), lds_lists, st, c, a);
         phase_end(c, SISSO_PHASE_SEARCH, st);
         phase_begin(c, SISSO_PHASE_MERGE, st);
-        hipLaunchKernelGGL(merge_kernel, dim3(1), dim3(MERGE_THREADS), 0, st, c, wgs * SEARCH_WAVES,
-                           c.KP, a.L, 0);
+        launch_merge(c, wgs * SEARCH_WAVES, a.L, 0, st);
         phase_end(c, SISSO_PHASE_MERGE, st);
     } else {
         phase_begin(c, SISSO_PHASE_PREPASS, st);
@@ -1248,8 +1313,7 @@ int launch_search(const Ctx &c, const SearchCall &sc, hipStream_t st) {
         }
         phase_end(c, SISSO_PHASE_SEARCH, st);
         phase_begin(c, SISSO_PHASE_MERGE, st);
-        hipLaunchKernelGGL(merge_kernel, dim3(1), dim3(MERGE_THREADS), 0, st, c,
-                           c.search_wgs * SEARCH_WAVES, c.KP, a.L, 1);
+        launch_merge(c, c.search_wgs * SEARCH_WAVES, a.L, 1, st);
         phase_end(c, SISSO_PHASE_MERGE, st);
     }
     phase_begin(c, SISSO_PHASE_RESCORE, st);

@@ -158,6 +158,29 @@ def test_rank_deficient_never_returned():
     compare_topk(q, 3, 50, gidx, gsse, oidx, osse)
 
 
+def test_task_constant_column_excluded():
+    """A column constant on one task up to rounding (relative 1e-13) makes all
+    its tuples rank-deficient, as in the oracle; a relative spread of 1e-3 is
+    kept.  Same construction as the oracle's pin, at search size."""
+    p = tiny_problem(71, S=30, n=400, T=2, D=3, task_sizes=[180, 220], sigma=0.3)
+    F = p.F.copy()
+    rng = np.random.default_rng(5)
+    F[3, 180:] = 5.0 * (1.0 + 1e-13 * rng.standard_normal(220))
+    F[4, 180:] = 5.0 * (1.0 + 1e-3 * rng.standard_normal(220))
+    _say("task-constant column S=30 n=400 T=2 D=3")
+    from paper_2502_20072_amd import L0Search
+    s = L0Search(F, p.y, p.task_offsets, D_max=3, k_max=60)
+    s.gram().search(3, 60)
+    gi, gs, _ = s.topk()
+    G, b, _ = s.gram_read(1)
+    s.close()
+    assert G[3, 3] == 0.0 and np.all(G[3] == 0.0) and b[3] == 0.0 and G[4, 4] == 1.0
+    assert all(3 not in tuple(t) for t in gi)
+    q = type(p)(**{**p.__dict__, "F": F})
+    oi, osse, _ = oracle.topk(F, p.y, 3, 60, p.task_offsets)
+    compare_topk(q, 3, 60, gi, gs, oi, osse)
+
+
 def test_deterministic_repeat():
     _say("determinism S=120 n=150 D=3")
     p = tiny_problem(79, S=120, n=150, D=3, sigma=0.5)

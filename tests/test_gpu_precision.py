@@ -1,0 +1,156 @@
+"""Precision form of the Gram (BF16 slices on MFMA, exact FP32 chunk sums,
+FP64 accumulation) against FP64 arithmetic and the CPU oracle.
+
+Error bound used below (per sample k, features i and j, chunk maxima
+M_i, M_j of the centred values over the 256-sample chunk holding k): with
+2^(E-1) <= M < 2^E, x = 2^(E-7) (A + r), A = a_0 + a_1 2^-8 + a_2 2^-16,
+|A| < 128 + 2^-17, |r| <= 2^-17.  The kept slice pairs (s + u <= 2) miss
+a_1 a_2' 2^-24 + a_2 a_1' 2^-24 + a_2 a_2' 2^-32 (<= 2^-9 + 2^-18) and the
+remainders add |A_i r_j| + |r_i A_j| + |r_i r_j| (<= 2^-9 + 2^-33), so the
+product of one sample is off by at most 2^(E_i + E_j - 14) (2^-8 + 2^-17)
+<= 1.01 * 2^-20 M_i M_j.  Hence
+    |G_lp[i, j] - G[i, j]| <= 1.01 * 2^-20 sum_k M_i M_j / (|x_i| |x_j|)
+plus FP64 rounding.  The search and the re-score are FP64, so the returned
+SSEs match the oracle to the FP64 tolerance.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import make_config, make_problem
+from tests.parity import compare_topk, total_ss
+
+pytestmark = pytest.mark.gpu
+XC = 256
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _centred(p, t):
+    a, b = p.task_offsets[t], p.task_offsets[t + 1]
+    return p.F[:, a:b] - p.F[:, a:b].mean(axis=1, keepdims=True)
+
+
+def _np_gram(X, raw):
+    """Correlation matrix of the centred rows X; a row constant up to 1e-10
+    (|x - mean|^2 <= 1e-10 |x|^2, x the raw row) is all zeros, diagonal too."""
+    ss = np.sum(X * X, axis=1)
+    live = ss > 1e-10 * np.sum(raw * raw, axis=1)
+    nrm = np.sqrt(ss)
+    inv = np.where(live, 1.0 / np.where(live, nrm, 1.0), 0.0)
+    G = (X @ X.T) * np.outer(inv, inv)
+    np.fill_diagonal(G, live.astype(np.float64))
+    return G, nrm, live
+
+
+def _bound(X, nrm):
+    n = X.shape[1]
+    nch = (n + XC - 1) // XC
+    Xp = np.zeros((X.shape[0], nch * XC))
+    Xp[:, :n] = np.abs(X)
+    M = Xp.reshape(X.shape[0], nch, XC).max(axis=2)           # chunk maxima
+    cnt = np.full(nch, XC, dtype=np.float64)
+    cnt[-1] = n - (nch - 1) * XC
+    S_ = (M * cnt) @ M.T                                         # sum over samples of M_i M_j
+    return 1.01 * 2.0 ** -20 * S_ / np.outer(nrm, nrm) + 1e-13
+
+
+def _sampled(S, nsample):
+    """The entries the report samples (same multiplicative hash)."""
+    out = []
+    for e in range(nsample):
+        h = ((e + 1) * 0x9E3779B97F4A7C15) & ((1 << 64) - 1)
+        out.append(((h >> 20) % S, (h >> 40) % S))
+    return out
+
+
+def _lp_search(p, D, k, **kw):
+    from paper_2502_20072_amd import L0Search
+    from paper_2502_20072_amd import _binding as B
+    return L0Search(p.F, p.y, p.task_offsets, D_max=D, k_max=k, precision=B.SISSO_PREC_BF16_COMP, **kw)
+
+
+@pytest.mark.parametrize("n,S,T,seed", [(3000, 150, 1, 311), (1500, 200, 3, 312), (90, 40, 1, 313)])
+def test_precision_gram_within_bound_and_report(n, S, T, seed):
+    _say(f"precision gram n={n} S={S} T={T} seed={seed}")
+    tasks = dict(T=T, lo=n // (2 * T), hi=2 * n // T) if T > 1 else None
+    p = make_problem(n=n, S=S, D=2, k=10, seed=seed, beta=(1.5, -0.8), sigma=0.05, tasks=tasks)
+    s = _lp_search(p, 2, 10)
+    s.gram()
+    worst = 0.0
+    for t in range(p.T):
+        G, b, c = s.gram_read(t)
+        X = _centred(p, t)
+        raw = p.F[:, p.task_offsets[t]:p.task_offsets[t + 1]]
+        Gr, nrm, live = _np_gram(X, raw)
+        err = np.abs(G - Gr)
+        bound = np.where(np.outer(live, live), _bound(X, np.where(live, nrm, 1.0)), 0.0) + 1e-13
+        assert np.all(err <= bound), f"task {t}: max excess {np.max(err - bound)}"
+        assert np.array_equal(G, G.T)
+        # F^T y and |y|^2 stay exact FP64
+        yc = p.y[p.task_offsets[t]:p.task_offsets[t + 1]]
+        yc = yc - yc.mean()
+        bref = np.where(live, (X @ yc) / np.where(live, nrm, 1.0), 0.0)
+        np.testing.assert_allclose(b, bref, rtol=1e-12, atol=1e-12 * math.sqrt(c))
+        worst = max(worst, max(err[i, j] for i, j in _sampled(p.S, 512)))
+    rep = s.precision_report(512)
+    assert rep["slices"] == 3 and rep["gram_entries"] == 512 * p.T
+    assert abs(rep["gram_max_abs_err"] - worst) <= 1e-12
+    s.close()
+
+
+@pytest.mark.parametrize("n,S,D,T,seed", [(4000, 100, 2, 1, 321), (3000, 60, 3, 1, 322), (2400, 45, 3, 3, 323),
+                                          (600, 30, 4, 1, 324)])
+def test_precision_search_matches_oracle(n, S, D, T, seed):
+    _say(f"precision search n={n} S={S} D={D} T={T} seed={seed}")
+    beta = (1.5, -0.8, 0.6, -0.4)[:D]
+    tasks = dict(T=T, lo=n // (2 * T), hi=2 * n // T) if T > 1 else None
+    p = make_problem(n=n, S=S, D=D, k=20, seed=seed, beta=beta, sigma=0.05, tasks=tasks)
+    s = _lp_search(p, D, 20)
+    s.gram().search(D, 20)
+    gi, gs, gc = s.topk()
+    rep = s.precision_report(256)
+    s.close()
+    oi, osse, _ = oracle.topk(p.F, p.y, D, 20, p.task_offsets)
+    # ties within 10x the ranked-vs-exact SSE error of this run count as ties
+    compare_topk(p, D, 20, gi, gs, oi, osse, tie_rel=max(1e-9, 10 * rep["sse_max_rel_err"]), gcoef=gc)
+    assert rep["sse_max_rel_err"] < 1e-4
+
+
+@pytest.fixture(scope="module")
+def c3():
+    _say("generating precision_s4096_d2 (n=50000, S=4096)")
+    return make_config("precision_s4096_d2")
+
+
+def test_precision_full_size_sampled(c3):
+    """Full C3 shape: every returned SSE is the oracle's SSE of that tuple, and
+    no sampled tuple beats the k-th result (the oracle cannot enumerate all
+    8.4e6 tuples at n = 50000 within a test)."""
+    p = c3
+    _say(f"precision full size n={p.F.shape[1]} S={p.S} D={p.D} k={p.k}")
+    s = _lp_search(p, p.D, p.k)
+    s.gram().search(p.D, p.k)
+    gi, gs, _ = s.topk(with_coef=False)
+    rep = s.precision_report(4096)
+    s.close()
+    _say(f"report {rep}")
+    assert np.all(np.isfinite(gs)) and np.all(np.diff(gs) >= 0)
+    for t, v in zip(gi, gs):
+        ref = oracle.tuple_sse(p.F, p.y, tuple(int(x) for x in t), p.task_offsets)
+        assert abs(v - ref) <= 1e-10 * ref, (t, v, ref)
+    planted = tuple(sorted(int(x) for x in p.planted))
+    assert tuple(int(x) for x in gi[0]) == planted
+    rng = np.random.default_rng(7)
+    top = {tuple(int(x) for x in t) for t in gi}
+    sk = float(gs[-1])
+    for _ in range(300):
+        t = tuple(sorted(int(x) for x in rng.choice(p.S, size=p.D, replace=False)))
+        if t in top:
+            continue
+        assert oracle.tuple_sse(p.F, p.y, t, p.task_offsets) >= sk * (1 - 1e-9)
+    assert rep["gram_max_abs_err"] < 1e-5

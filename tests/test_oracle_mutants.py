@@ -40,6 +40,8 @@ MUTANTS = {
                           "s -= A[(int64_t)j * nt + c] * x[c];"),
     "task_rows_shifted": ("for (i = 0; i < nt; ++i) b[i] = y[r0 + i];",
                           "for (i = 0; i < nt; ++i) b[i] = y[i];"),
+    "no_intercept_collinearity_rule": ("if (cnorm2[c] <= ORACLE_RANK_EPS * rnorm2[c] ||",
+                                       "if (cnorm2[c] == 0.0 ||"),
 }
 
 
@@ -105,6 +107,13 @@ def _pins_pass() -> bool:
         idx5, sse5, _ = oracle.topk(p.F, p.y, 3, 6, p.task_offsets)
         ref5 = sorted((_lstsq(p.F, p.y, t, p.task_offsets)[0], t) for t in itertools.combinations(range(7), 3))
         if [t for _, t in ref5[:6]] != [tuple(t) for t in idx5]:
+            return False
+        # (6) a column constant on one task up to rounding makes its tuples
+        #     rank-deficient (1 - uncentred R^2 on the intercept ~1e-26)
+        u = tiny_problem(64, S=4, n=30, T=2, D=2, sigma=0.5, task_sizes=[15, 15])
+        H = u.F.copy()
+        H[2, 15:] = 3.0 * (1.0 + 1e-13 * np.random.default_rng(3).standard_normal(15))
+        if oracle.tuple_sse(H, u.y, (0, 2), u.task_offsets) != math.inf:
             return False
         # (4) a moderately collinear (valid) tuple is kept
         r = tiny_problem(63, S=4, n=30, D=2, sigma=0.5)

@@ -255,6 +255,28 @@ def test_rank_deficient_tuples_are_excluded():
     assert (0, 1, 2) not in finite and all(4 not in t for t in finite)
 
 
+def test_column_constant_on_a_task_up_to_rounding_is_excluded():
+    """A column constant on one task up to a relative 1e-13 has 1 - R^2 on the
+    intercept alone (uncentred: |x - mean|^2 / |x|^2) of ~1e-26 there, so every
+    tuple using it is rank-deficient; a relative spread of 1e-3 (ratio ~1e-6)
+    is kept, and tuples without the column keep their lstsq SSE."""
+    p = tiny_problem(53, S=6, n=40, T=2, D=2, task_sizes=[20, 20], sigma=0.5)
+    F = p.F.copy()
+    rng = np.random.default_rng(5)
+    F[3, 20:] = 5.0 * (1.0 + 1e-13 * rng.standard_normal(20))    # task 1: constant up to rounding
+    F[4, 20:] = 5.0 * (1.0 + 1e-3 * rng.standard_normal(20))     # task 1: small but real spread
+    x3 = F[3, 20:]
+    assert np.sum((x3 - x3.mean()) ** 2) / np.sum(x3 ** 2) <= 1e-10
+    for t in [(0, 3), (3, 5), (1, 3)]:
+        assert oracle.tuple_sse(F, p.y, t, p.task_offsets) == math.inf
+    for t in [(0, 4), (4, 5), (0, 1)]:
+        s = oracle.tuple_sse(F, p.y, t, p.task_offsets)
+        assert abs(s - lstsq_sse(F, p.y, t, p.task_offsets)[0]) <= 1e-9 * s
+    idx, sse, _ = oracle.topk(F, p.y, 2, math.comb(6, 2), p.task_offsets)
+    finite = {tuple(t) for t, v in zip(idx, sse) if np.isfinite(v)}
+    assert all(3 not in t for t in finite) and len(finite) == math.comb(5, 2)
+
+
 def test_task_row_limits():
     p = tiny_problem(49, S=5, n=6, T=2, D=2, task_sizes=[3, 3], sigma=0.5)
     # n_t = D+1 rows: exact interpolation, SSE 0 up to rounding
