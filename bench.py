@@ -76,6 +76,10 @@ def main() -> int:
     ap.add_argument("--workload", default="plain_s1000_d3")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--precision", choices=("fp64", "bf16"), default="fp64",
+                    help="Gram precision form (the search and the re-score are FP64 either way)")
+    ap.add_argument("--tune-cache", default=os.environ.get("SISSO_AUTOTUNE_CACHE"),
+                    help="JSON cache of the search-grid autotuner (default: tune every run)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the search shards by "
@@ -99,8 +103,12 @@ def main() -> int:
     dev = torch.device("cuda:0")
     print(f"bench: workload={args.workload} n={p.n} S={p.S} T={p.T} D={D} k={k} "
           f"tuples={ntup}", file=sys.stderr, flush=True)
-    s = L0Search(p.F, p.y, p.task_offsets, D_max=D, k_max=k, device="cuda:0")
+    prec = B.SISSO_PREC_BF16_COMP if args.precision == "bf16" else B.SISSO_PREC_FP64
+    s = L0Search(p.F, p.y, p.task_offsets, D_max=D, k_max=k, device="cuda:0", precision=prec)
     stream = s.stream
+    # launch tuning on the problem itself (changes no arithmetic), before timing
+    s.gram()
+    grid = s.autotune(D, k, args.tune_cache)
 
     def step():
         s.gram()
@@ -159,11 +167,15 @@ def main() -> int:
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "n": p.n, "S": p.S, "T": p.T, "D": D, "k": k,
-                   "tuples": ntup, "form": "plain FP64"},
+                   "tuples": ntup, "form": "plain FP64" if prec == B.SISSO_PREC_FP64 else
+                   "precision form (Gram from BF16 slices, FP64 search and re-score)",
+                   "search_grid": grid},
         "topk_matches_oracle": matches,
         "phase_ms": acc,
         "roofline": roofline,
     }
+    if prec != B.SISSO_PREC_FP64:
+        res["precision_report"] = s.precision_report(4096)
     s.close()
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(p, D, k, args.cpu_seconds)

@@ -145,6 +145,24 @@ const char *sisso_l0_batch_last_error(void);
  * GPU work has finished). */
 int32_t sisso_l0_search_batch(sisso_l0 *const *hs, int32_t P, int32_t D, int32_t k);
 
+/* Launch tuning.  The persistent search kernel runs on a grid of
+ * workgroups (default 1024) whose best size depends on the problem; it
+ * changes no arithmetic, so every size gives bit-identical results.  (The
+ * paper auto-tunes its launch configuration by timing a predefined set on
+ * the first batch of each run, section "l0-regularization".)  sisso_l0_set_search_grid sets it (EINVAL
+ * outside 1..2048); sisso_l0_search_grid reads it (0 for NULL).
+ * sisso_l0_autotune times the candidates 256, 512, ..., 2048 on a full
+ * search of (D, k) (same argument rules as sisso_l0_search), keeps the
+ * fastest and writes it to *chosen (may be NULL).  With cache_path (may be
+ * NULL) it first looks up, and afterwards stores, the choice in a JSON file
+ * keyed by GPU architecture, D, S rounded up to a power of two, T and the
+ * precision mode; a cache hit runs nothing.  After a tuning run the handle
+ * holds the result of a search of (D, k), as after sisso_l0_search.
+ * Synchronises the stream; EINVAL if the cache cannot be written. */
+int32_t sisso_l0_set_search_grid(sisso_l0 *h, int32_t workgroups);
+int32_t sisso_l0_search_grid(const sisso_l0 *h);
+int32_t sisso_l0_autotune(sisso_l0 *h, int32_t D, int32_t k, const char *cache_path, int32_t *chosen);
+
 /* Synchronise the stream and copy the result of the last search to HOST
  * buffers: idx (k*D int32, row-major, ascending indices within a row), sse
  * (k doubles, SSE summed over tasks) and, unless NULL, coef (k*T*(D+1)

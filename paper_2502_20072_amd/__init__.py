@@ -93,6 +93,16 @@ class L0Search:
     def scored(self) -> int:
         return B.sisso_l0_scored(self.handle)
 
+    def autotune(self, D: int, k: int, cache_path: Optional[str] = None) -> int:
+        """Pick the fastest search grid for (D, k) (cached by shape); leaves the
+        handle with the result of a search of (D, k).  Returns the grid size."""
+        g = B.sisso_l0_autotune(self.handle, D, k, cache_path)
+        self.last_D, self.last_k = D, k
+        return g
+
+    def set_search_grid(self, workgroups: int) -> None:
+        B.sisso_l0_set_search_grid(self.handle, workgroups)
+
     def precision_report(self, nsample: int = 4096) -> dict:
         """Gram error on sampled entries vs FP64 from F, and the ranked-vs-exact
         SSE error of the last search's results; synchronises."""

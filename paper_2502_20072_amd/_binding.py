@@ -232,6 +232,31 @@ def sisso_l0_precision_report(h: int, nsample: int = 4096) -> dict:
                 slices=int(out[3]))
 
 
+def sisso_l0_set_search_grid(h: int, workgroups: int) -> None:
+    lib = load()
+    lib.sisso_l0_set_search_grid.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+    lib.sisso_l0_set_search_grid.restype = ctypes.c_int32
+    _check(lib.sisso_l0_set_search_grid(h, workgroups), h)
+
+
+def sisso_l0_search_grid(h: int) -> int:
+    lib = load()
+    lib.sisso_l0_search_grid.argtypes = [ctypes.c_void_p]
+    lib.sisso_l0_search_grid.restype = ctypes.c_int32
+    return int(lib.sisso_l0_search_grid(h))
+
+
+def sisso_l0_autotune(h: int, D: int, k: int, cache_path: Optional[str] = None) -> int:
+    lib = load()
+    lib.sisso_l0_autotune.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_char_p,
+                                      ctypes.POINTER(ctypes.c_int32)]
+    lib.sisso_l0_autotune.restype = ctypes.c_int32
+    out = ctypes.c_int32(0)
+    path = cache_path.encode() if cache_path else None
+    _check(lib.sisso_l0_autotune(h, D, k, path, ctypes.byref(out)), h)
+    return int(out.value)
+
+
 def _batch_sigs(lib):
     P = ctypes.POINTER
     lib.sisso_l0_batch_create.argtypes = [P(ctypes.c_void_p), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,

@@ -4,6 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
@@ -69,8 +70,8 @@ static Layout compute_layout(int64_t n_total, int64_t S, int T, int D_max, int k
     L.nsplit = (int)ns;
     L.KP = next_pow2(k_max + 16);
     if (L.KP < 64) L.KP = 64;
-    L.search_wgs = 1024;
-    L.nwaves = L.search_wgs * SEARCH_WAVES;
+    L.search_wgs = SEARCH_WGS_DEFAULT;
+    L.nwaves = SEARCH_WGS_MAX * SEARCH_WAVES;
     const int64_t nlists = L.nwaves;
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -281,6 +282,116 @@ extern "C" int32_t sisso_l0_search(sisso_l0 *h, int32_t D, int32_t k) { return d
 
 extern "C" int32_t sisso_l0_search_range(sisso_l0 *h, int32_t D, int32_t k, uint64_t r0, uint64_t r1) {
     return do_search(h, D, k, true, r0, r1);
+}
+
+// ---------------------------------------------------------------- autotuner
+// The persistent search grid is the one launch parameter whose best value
+// depends on the problem (items per workgroup vs. latency hiding) and that
+// changes no arithmetic: every grid size gives bit-identical results.
+
+extern "C" int32_t sisso_l0_set_search_grid(sisso_l0 *h, int32_t workgroups) {
+    if (!h) return SISSO_EINVAL;
+    h->err.clear();
+    if (workgroups < 1 || workgroups > SEARCH_WGS_MAX) return fail(h, SISSO_EINVAL, "grid size out of range");
+    h->ctx.search_wgs = workgroups;
+    return SISSO_OK;
+}
+
+extern "C" int32_t sisso_l0_search_grid(const sisso_l0 *h) { return h ? h->ctx.search_wgs : 0; }
+
+// Cache file: a JSON object with one entry per line,
+//   "<arch>|D=<D>|S=<S rounded up to a power of two>|T=<T>|P=<precision>": {"search_wgs": W, "ms": t},
+static std::map<std::string, std::pair<int, double>> read_cache(const char *path) {
+    std::map<std::string, std::pair<int, double>> m;
+    FILE *f = path ? fopen(path, "r") : nullptr;
+    if (!f) return m;
+    char line[512];
+    while (fgets(line, sizeof line, f)) {
+        const char *q0 = strchr(line, '"');
+        const char *q1 = q0 ? strchr(q0 + 1, '"') : nullptr;
+        const char *w = q1 ? strstr(q1, "\"search_wgs\":") : nullptr;
+        const char *t = q1 ? strstr(q1, "\"ms\":") : nullptr;
+        if (!w || !t) continue;
+        m[std::string(q0 + 1, q1)] = {atoi(w + 13), atof(t + 5)};
+    }
+    fclose(f);
+    return m;
+}
+
+static bool write_cache(const char *path, const std::map<std::string, std::pair<int, double>> &m) {
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = fopen(tmp.c_str(), "w");
+    if (!f) return false;
+    fputs("{\n", f);
+    size_t i = 0;
+    for (const auto &e : m)
+        fprintf(f, "\"%s\": {\"search_wgs\": %d, \"ms\": %.6f}%s\n", e.first.c_str(), e.second.first, e.second.second,
+                ++i < m.size() ? "," : "");
+    fputs("}\n", f);
+    const bool ok = fclose(f) == 0;
+    return ok && rename(tmp.c_str(), path) == 0;
+}
+
+extern "C" int32_t sisso_l0_autotune(sisso_l0 *h, int32_t D, int32_t k, const char *cache_path, int32_t *chosen) {
+    if (!h) return SISSO_EINVAL;
+    h->err.clear();
+    SearchCall sc;
+    uint64_t scored = 0;
+    int32_t rc = check_search(h, D, k, false, 0, 0, true, &sc, &scored);
+    if (rc != SISSO_OK) return rc;
+    hipDeviceProp_t prop;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return fail(h, SISSO_EDEVICE, "cannot query the device");
+    char key[256];
+    snprintf(key, sizeof key, "%s|D=%d|S=%d|T=%d|P=%d", prop.gcnArchName, D, next_pow2((int)h->desc.S), h->desc.T,
+             h->desc.precision);
+    auto cache = read_cache(cache_path);
+    auto it = cache.find(key);
+    if (it != cache.end() && it->second.first >= 1 && it->second.first <= SEARCH_WGS_MAX) {
+        h->ctx.search_wgs = it->second.first;
+        if (chosen) *chosen = h->ctx.search_wgs;
+        return SISSO_OK;
+    }
+    static const int cand[] = {256, 512, 768, 1024, 1280, 1536, 2048};
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(h, SISSO_EDEVICE, "hipEventCreate failed");
+    hipEvent_t *saved_ev = h->ctx.ev;
+    h->ctx.ev = nullptr;  // no phase events inside the timed launches
+    int best = h->ctx.search_wgs;
+    double best_ms = 1e300;
+    bool ok = true;
+    for (int w : cand) {
+        h->ctx.search_wgs = w;
+        if (launch_search(h->ctx, sc, h->stream)) { ok = false; break; }  // warm-up
+        float ms = 0.f;
+        if (hipEventRecord(e0, h->stream) != hipSuccess) { ok = false; break; }
+        for (int r = 0; r < 3; ++r)
+            if (launch_search(h->ctx, sc, h->stream)) { ok = false; break; }
+        if (!ok || hipEventRecord(e1, h->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { ok = false; break; }
+        if (ms / 3.0 < best_ms) {
+            best_ms = ms / 3.0;
+            best = w;
+        }
+    }
+    h->ctx.ev = saved_ev;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    h->ctx.search_wgs = best;
+    // the timed launches left a complete search of (D, k) behind
+    h->search_done = ok;
+    h->last_D = D;
+    h->last_k = k;
+    h->scored = scored;
+    if (!ok) return fail(h, SISSO_EDEVICE, "a timed search launch failed");
+    if (chosen) *chosen = best;
+    if (cache_path) {
+        cache[key] = {best, best_ms};
+        if (!write_cache(cache_path, cache)) return fail(h, SISSO_EINVAL, "cannot write the autotune cache");
+    }
+    return SISSO_OK;
 }
 
 extern "C" int32_t sisso_l0_topk(sisso_l0 *h, int32_t k, int32_t *idx, double *sse, double *coef) {

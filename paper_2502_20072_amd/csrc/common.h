@@ -15,6 +15,8 @@ constexpr int GRAM_TILE = 128;         // Gram output tile (rows = cols)
 constexpr int GRAM_KC = 16;            // samples per LDS stage of the Gram
 constexpr int SEARCH_WG = 256;         // threads per search workgroup (4 waves)
 constexpr int SEARCH_WAVES = SEARCH_WG / WAVE;
+constexpr int SEARCH_WGS_MAX = 2048;   // largest persistent search grid (lists are sized for it)
+constexpr int SEARCH_WGS_DEFAULT = 1024;
 constexpr int JBLK = 64;               // (D-1)-th indices per search work item (one per lane)
 constexpr int SUBP = 4;                // sub-prefixes sharing one Gram load (single task)
 constexpr int PRE_M = 16;              // features the threshold pre-pass starts from

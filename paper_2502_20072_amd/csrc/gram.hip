@@ -33,6 +33,7 @@ __global__ __launch_bounds__(256) void stats_y_kernel(const double *__restrict__
     const int64_t r0 = off[t], r1 = off[t + 1];
     double s = 0.0;
     bool bad = false;
+#pragma unroll 4
     for (int64_t i = r0 + lane; i < r1; i += 64) {
         double v = y[i];
         bad |= !isfinite(v);
@@ -41,6 +42,7 @@ __global__ __launch_bounds__(256) void stats_y_kernel(const double *__restrict__
     s = wave_sum(s);
     const double m = s / (double)(r1 - r0);
     double ss = 0.0;
+#pragma unroll 4
     for (int64_t i = r0 + lane; i < r1; i += 64) {
         double d = y[i] - m;
         ss += d * d;
@@ -71,6 +73,7 @@ __global__ __launch_bounds__(256) void stats_x_kernel(const double *__restrict__
     const double *col = F + j * n_total;
     double s = 0.0;
     bool bad = false;
+#pragma unroll 4
     for (int64_t i = r0 + lane; i < r1; i += 64) {
         double v = col[i];
         bad |= !isfinite(v);
@@ -80,6 +83,7 @@ __global__ __launch_bounds__(256) void stats_x_kernel(const double *__restrict__
     const double m = s / (double)(r1 - r0);
     const double ym = ybar[t];
     double ss = 0.0, sy = 0.0, sr = 0.0;
+#pragma unroll 4
     for (int64_t i = r0 + lane; i < r1; i += 64) {
         const double v = col[i];
         const double d = v - m;
@@ -113,7 +117,11 @@ __global__ __launch_bounds__(256) void stats_x_kernel(const double *__restrict__
 // lane j + 16k, result D[i][j] in lane j + 16*(i%4), register i/4.
 typedef double double4_t __attribute__((ext_vector_type(4)));
 
-constexpr int LDS_STRIDE = GRAM_TILE + 16;  // 144 doubles: rows k, k+1 land on opposite bank halves
+// LDS holds the chunk feature-major, [feature][sample] with a row of KC + 1
+// doubles: the loader's stores (16 consecutive samples of a feature) are
+// contiguous, and the MFMA operand reads (16 features at one sample) fall on
+// distinct banks (row stride 34 dwords).
+constexpr int LDS_STRIDE = GRAM_KC + 1;
 
 // One wave per SIMD is all this launch needs (about one workgroup per CU), so
 // the register budget is the whole file: no spills around the prefetch.
@@ -122,8 +130,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
                                                    int T, const double *__restrict__ mu,
                                                    int ntile, int nsplit,
                                                    double *__restrict__ part) {
-    __shared__ double As[GRAM_KC][LDS_STRIDE];
-    __shared__ double Bs[GRAM_KC][LDS_STRIDE];
+    __shared__ double As[GRAM_TILE][LDS_STRIDE];
+    __shared__ double Bs[GRAM_TILE][LDS_STRIDE];
 
     // blockIdx.x -> (split, task, tile pair) ; tile pairs enumerate bi <= bj row by row
     int64_t b = blockIdx.x;
@@ -196,8 +204,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         }
 #pragma unroll
         for (int r = 0; r < GRAM_TILE / 16; ++r) {
-            As[kk][f0 + 16 * r] = (row < r1 && ina[r]) ? sa[r] - muA[r] : 0.0;
-            Bs[kk][f0 + 16 * r] = (row < r1 && inb[r]) ? sb[r] - muB[r] : 0.0;
+            As[f0 + 16 * r][kk] = (row < r1 && ina[r]) ? sa[r] - muA[r] : 0.0;
+            Bs[f0 + 16 * r][kk] = (row < r1 && inb[r]) ? sb[r] - muB[r] : 0.0;
         }
     }
     __syncthreads();
@@ -217,9 +225,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
             const int krow = ks * 4 + (lane >> 4);
             double a[4], bv[4];
 #pragma unroll
-            for (int m = 0; m < 4; ++m) a[m] = As[krow][wr + m * 16 + (lane & 15)];
+            for (int m = 0; m < 4; ++m) a[m] = As[wr + m * 16 + (lane & 15)][krow];
 #pragma unroll
-            for (int m = 0; m < 4; ++m) bv[m] = Bs[krow][wc + m * 16 + (lane & 15)];
+            for (int m = 0; m < 4; ++m) bv[m] = Bs[wc + m * 16 + (lane & 15)][krow];
 #pragma unroll
             for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -230,8 +238,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         if (more) {
 #pragma unroll
             for (int r = 0; r < GRAM_TILE / 16; ++r) {
-                As[kk][f0 + 16 * r] = (row < r1 && ina[r]) ? sa[r] - muA[r] : 0.0;
-                Bs[kk][f0 + 16 * r] = (row < r1 && inb[r]) ? sb[r] - muB[r] : 0.0;
+                As[f0 + 16 * r][kk] = (row < r1 && ina[r]) ? sa[r] - muA[r] : 0.0;
+                Bs[f0 + 16 * r][kk] = (row < r1 && inb[r]) ? sb[r] - muB[r] : 0.0;
             }
         }
         __syncthreads();
@@ -273,20 +281,38 @@ __global__ __launch_bounds__(256) void gram_finish_kernel(const double *__restri
     }
     const int64_t tk = ti + pr;
     const double *ist = inv_s + (int64_t)t * S;
-    for (int e = threadIdx.x; e < GT * GT; e += 256) {
+    // each thread owns 16 elements; the split partials are summed split by
+    // split with all 16 loads of a split in flight (indices clamped in range,
+    // out-of-range elements masked afterwards)
+    constexpr int PER = GT * GT / 256;
+    int64_t src[PER];
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+        const int e = threadIdx.x + 256 * m;
+        const int li = e >> 6, lk = e & 63;
+        int64_t i = ti * GT + li, k = tk * GT + lk;
+        i = i < S ? i : S - 1;
+        k = k < S ? k : S - 1;
+        const int64_t a = (ti == tk && i > k) ? k : i, cc = (ti == tk && i > k) ? i : k;  // canonical (upper)
+        src[m] = a * S + cc;
+    }
+    double acc[PER];
+#pragma unroll
+    for (int m = 0; m < PER; ++m) acc[m] = 0.0;
+    for (int sp = 0; sp < nsplit; ++sp) {
+        const double *P = part + ((int64_t)sp * T + t) * S * S;
+#pragma unroll
+        for (int m = 0; m < PER; ++m) acc[m] += P[src[m]];
+    }
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+        const int e = threadIdx.x + 256 * m;
         const int li = e >> 6, lk = e & 63;
         const int64_t i = ti * GT + li, k = tk * GT + lk;
         double v = 0.0;
         if (i < S && k < S) {
-            if (i == k) {
-                v = ist[i] > 0.0 ? 1.0 : 0.0;
-            } else {
-                // canonical element: upper triangle within a diagonal tile
-                const int64_t a = (ti == tk && i > k) ? k : i, c = (ti == tk && i > k) ? i : k;
-                double acc = 0.0;
-                for (int sp = 0; sp < nsplit; ++sp) acc += part[(((int64_t)sp * T + t) * S + a) * S + c];
-                v = acc * (ist[a] * ist[c]);
-            }
+            const int64_t a = src[m] / S, cc = src[m] % S;
+            v = i == k ? (ist[i] > 0.0 ? 1.0 : 0.0) : acc[m] * (ist[a] * ist[cc]);
         }
         G[((((ti * nt + tk) << 12) + (li << 6) + lk)) * TP + t] = v;
         tr[lk][li] = v;

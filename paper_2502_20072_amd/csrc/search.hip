@@ -47,6 +47,9 @@ namespace sl0 {
 constexpr int MAXD = SISSO_MAX_D;
 constexpr double INF = __builtin_huge_val();
 constexpr double THETA_SLACK = 1e-9;  // relative slack of the filter bound
+#ifndef SEARCH_JG
+#define SEARCH_JG 8  // G rows per prefetch group (two groups in flight)
+#endif
 
 __device__ inline bool key_less(double s1, uint64_t r1, double s2, uint64_t r2) {
     return s1 < s2 || (s1 == s2 && r1 < r2);
@@ -71,6 +74,12 @@ __device__ inline int64_t uni(int64_t v) {
 }
 __device__ inline uint64_t uni(uint64_t v) { return (uint64_t)uni((int64_t)v); }
 __device__ inline double uni(double v) { return __longlong_as_double(uni((int64_t)__double_as_longlong(v))); }
+
+__device__ inline int next_pow2_dev(int x) {
+    int p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
 
 __device__ inline double Gat(const Ctx &c, int64_t i, int64_t k, int t) {
     return c.G[gidx(i, k, c.Gnt, c.TP, t)];
@@ -194,7 +203,9 @@ __global__ void search_init_kernel(Ctx c, int D, int R, int JB) {
         for (int64_t b = 0; b < nblk; ++b) {
             int64_t N = JB * (b + 1);
             if (N > c.S - 1) N = c.S - 1;
-            const uint64_t nsub = q >= 0 ? binom(N - 1, q) : 0;
+            // C(N - 1, q) in closed form (q = D - 2 <= 2)
+            const uint64_t m1 = (uint64_t)(N - 1);
+            const uint64_t nsub = q == 0 ? 1 : q == 1 ? m1 : (m1 * (m1 - 1)) / 2;
             acc += (nsub + R - 1) / R;
             c.cum[b + 1] = acc;
         }
@@ -205,207 +216,174 @@ __global__ void search_init_kernel(Ctx c, int D, int R, int JB) {
 // The search starts from an upper bound theta0 of the KP-th best SSE, so
 // that almost no tuple reaches the exact path.  It is built from a small,
 // structured set of real tuples: the best (D-1)-subsets of the PRE_M most
-// relevant features, each extended by every feature.  Selections below run
-// as per-thread sorted lists in registers and wave-level argmin rounds over
-// LDS (shuffles only), so no phase waits on a chain of global loads.
+// relevant features, each extended by every feature.  Any set of real
+// tuples gives a valid bound (below), so the selections may be heuristic;
+// they run as block-wide bitonic sorts in LDS, one thread per candidate.
+constexpr int PRE_WG = 1024;      // threads of the pre-pass workgroups
+constexpr int PRE_SORT = 4096;    // largest sorted candidate set
+constexpr int PRE_KEEP = PRE_SORT / PRE_WG;  // candidates a thread keeps when S > PRE_SORT
 
-// Keep the L smallest (v, id) pairs of a thread's stream, sorted ascending.
-template <int L>
-struct LocalTop {
-    double v[L];
-    int id[L];
-    __device__ void init() {
-#pragma unroll
-        for (int i = 0; i < L; ++i) {
-            v[i] = INF;
-            id[i] = -1;
+// Ascending sort of N (power of two) (key, id) pairs in LDS by (key, id).
+__device__ void block_sort(double *key, int *id, int N) {
+    for (int k = 2; k <= N; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < N; i += blockDim.x) {
+                const int ixj = i ^ j;
+                if (ixj > i) {
+                    const bool up = (i & k) == 0;
+                    const double a = key[i], b = key[ixj];
+                    const int ia = id[i], ib = id[ixj];
+                    const bool after = a > b || (a == b && ia > ib);
+                    if (after == up) {
+                        key[i] = b;
+                        key[ixj] = a;
+                        id[i] = ib;
+                        id[ixj] = ia;
+                    }
+                }
+            }
+            __syncthreads();
         }
+}
+
+// Fill key/id[0..N) with the candidates v(x) for x in [0, n): directly when
+// n <= PRE_SORT, else each thread keeps its PRE_KEEP smallest.  Returns N.
+template <class F>
+__device__ int gather_candidates(double *key, int *id, int64_t n, F v) {
+    const int tid = threadIdx.x;
+    if (n <= PRE_SORT) {
+        const int N = next_pow2_dev((int)n);
+        for (int x = tid; x < N; x += PRE_WG) {
+            key[x] = x < n ? v(x) : INF;
+            id[x] = x;
+        }
+        return N;
     }
-    __device__ void offer(double x, int i) {
-        if (!(x < v[L - 1] || (x == v[L - 1] && (unsigned)i < (unsigned)id[L - 1]))) return;
-        double cv = x;
-        int ci = i;
+    double kv[PRE_KEEP];
+    int ki[PRE_KEEP];
 #pragma unroll
-        for (int m = 0; m < L; ++m) {
-            const bool less = cv < v[m] || (cv == v[m] && (unsigned)ci < (unsigned)id[m]);
-            const double tv = v[m];
-            const int ti = id[m];
-            v[m] = less ? cv : tv;
-            id[m] = less ? ci : ti;
+    for (int m = 0; m < PRE_KEEP; ++m) {
+        kv[m] = INF;
+        ki[m] = 0x7fffffff;
+    }
+    for (int64_t x = tid; x < n; x += PRE_WG) {
+        double cv = v(x);
+        int ci = (int)x;
+#pragma unroll
+        for (int m = 0; m < PRE_KEEP; ++m) {
+            const bool less = cv < kv[m] || (cv == kv[m] && ci < ki[m]);
+            const double tv = kv[m];
+            const int ti = ki[m];
+            kv[m] = less ? cv : tv;
+            ki[m] = less ? ci : ti;
             cv = less ? tv : cv;
             ci = less ? ti : ci;
         }
     }
-};
-
-// One wave: the L smallest (v, id) among n entries of an LDS array, by L
-// rounds of wave argmin (chosen entries are overwritten with +inf).  Results
-// in out_v/out_id (lane 0 writes); returns how many finite ones were found.
-__device__ int wave_smallest(double *v, int *id, int n, int L, double *out_v, int *out_id) {
-    const int lane = threadIdx.x & 63;
-    int found = 0;
-    for (int it = 0; it < L; ++it) {
-        double bv = INF;
-        int bi = -1, bpos = -1;
-        for (int e = lane; e < n; e += 64) {
-            const double x = v[e];
-            const int xi = id[e];
-            if (x < bv || (x == bv && (unsigned)xi < (unsigned)bi)) {
-                bv = x;
-                bi = xi;
-                bpos = e;
-            }
-        }
-        for (int o = 32; o > 0; o >>= 1) {
-            const double ov = __shfl_xor(bv, o);
-            const int oi = __shfl_xor(bi, o);
-            const int op = __shfl_xor(bpos, o);
-            if (ov < bv || (ov == bv && (unsigned)oi < (unsigned)bi)) {
-                bv = ov;
-                bi = oi;
-                bpos = op;
-            }
-        }
-        if (!(bv < INF)) break;
-        if (lane == 0) {
-            out_v[it] = bv;
-            out_id[it] = bi;
-            v[bpos] = INF;
-        }
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        __builtin_amdgcn_wave_barrier();
-        ++found;
+#pragma unroll
+    for (int m = 0; m < PRE_KEEP; ++m) {
+        key[tid * PRE_KEEP + m] = kv[m];
+        id[tid * PRE_KEEP + m] = ki[m];
     }
-    return found;
+    return PRE_SORT;
 }
 
 // pre_select: relevance of feature j = sum over tasks of b_tj^2 (its D=1
 // explained sum of squares); the PRE_M most relevant full-rank features;
 // every (D-1)-subset of them scored; the PRE_Q best subsets become prefixes.
-__global__ __launch_bounds__(256) void pre_select_kernel(Ctx c, int D) {
-    __shared__ double lv[256 * PRE_M];
-    __shared__ int li[256 * PRE_M];
-    __shared__ double wv[SEARCH_WAVES * PRE_M];
-    __shared__ int wi[SEARCH_WAVES * PRE_M];
+__global__ __launch_bounds__(PRE_WG) void pre_select_kernel(Ctx c, int D) {
+    __shared__ double key[PRE_SORT];
+    __shared__ int id[PRE_SORT];
     __shared__ int sel[PRE_M];
     __shared__ int s_m;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x;
     const int q = D - 1;
-    // 1. per-thread top-PRE_M of -relevance
-    {
-        LocalTop<PRE_M> top;
-        top.init();
-        for (int64_t j = tid; j < c.S; j += 256) {
-            double r = 0.0;
-            bool ok = true;
-            for (int t = 0; t < c.T; ++t) {
-                ok &= Gat(c, j, j, t) == 1.0;
-                const double b = c.bhat[j * c.TP + t];
-                r += b * b;
-            }
-            if (ok) top.offer(-r, (int)j);
+    // 1. most relevant full-rank features first
+    int N = gather_candidates(key, id, c.S, [&](int64_t j) {
+        double r = 0.0;
+        bool ok = true;
+        for (int t = 0; t < c.T; ++t) {
+            ok &= Gat(c, j, j, t) == 1.0;
+            const double b = c.bhat[j * c.TP + t];
+            r += b * b;
         }
-#pragma unroll
-        for (int m = 0; m < PRE_M; ++m) {
-            lv[tid * PRE_M + m] = top.v[m];
-            li[tid * PRE_M + m] = top.id[m];
-        }
-    }
+        return ok ? -r : INF;
+    });
     __syncthreads();
-    // 2. each wave reduces its 64 lists, then wave 0 merges the 4 results
-    const int nw = wave_smallest(lv + wave * 64 * PRE_M, li + wave * 64 * PRE_M, 64 * PRE_M, PRE_M,
-                                 wv + wave * PRE_M, wi + wave * PRE_M);
-    if (lane == 0)
-        for (int m = nw; m < PRE_M; ++m) {
-            wv[wave * PRE_M + m] = INF;
-            wi[wave * PRE_M + m] = -1;
-        }
-    __syncthreads();
-    __shared__ double fv[PRE_M];
-    __shared__ int fi[PRE_M];
-    if (wave == 0) {
-        const int M = wave_smallest(wv, wi, SEARCH_WAVES * PRE_M, PRE_M, fv, fi);
-        if (lane == 0) {
-            // selected features in increasing index order
-            for (int a = 0; a < M; ++a) {
-                int b = a;
-                for (int x = a + 1; x < M; ++x)
-                    if (fi[x] < fi[b]) b = x;
-                const int t = fi[a];
-                fi[a] = fi[b];
-                fi[b] = t;
-                sel[a] = fi[a];
+    block_sort(key, id, N);
+    if (tid == 0) {
+        int M = 0;
+        while (M < PRE_M && M < N && key[M] < INF) ++M;
+        // selected features in increasing index order
+        for (int a = 0; a < M; ++a) sel[a] = id[a];
+        for (int a = 1; a < M; ++a)
+            for (int b2 = a; b2 > 0 && sel[b2 - 1] > sel[b2]; --b2) {
+                const int t = sel[b2];
+                sel[b2] = sel[b2 - 1];
+                sel[b2 - 1] = t;
             }
-            s_m = M;
-        }
+        s_m = M;
+        *c.pre_count = 0;
     }
     __syncthreads();
     const int M = s_m;
     if (M < q) return;
-    // 3. score every q-subset of the selection (<= C(16, 3) = 560 of them)
-    const uint64_t nsub = binom(M, q);
-    for (int e = tid; e < 1024; e += 256) {
-        lv[e] = INF;
-        li[e] = -1;
-    }
-    __syncthreads();
-    for (uint64_t e = tid; e < nsub && e < 1024; e += 256) {
-        int32_t loc[MAXD], tup[MAXD];
-        colex_unrank_small(e, q, M, loc);
-        for (int m = 0; m < q; ++m) tup[m] = sel[loc[m]];
-        lv[e] = ne_sse(c, q, tup);
-        li[e] = (int)e;
-    }
-    __syncthreads();
-    // 4. the PRE_Q best subsets (SSE, then subset rank)
-    __shared__ double bv[PRE_Q];
-    __shared__ int bi[PRE_Q];
-    if (wave == 0) {
-        const int Q = wave_smallest(lv, li, 1024, PRE_Q, bv, bi);
-        if (lane == 0) {
-            for (int it = 0; it < Q; ++it) {
-                int32_t loc[MAXD];
-                colex_unrank_small((uint64_t)bi[it], q, M, loc);
-                for (int m = 0; m < q; ++m) c.pre_prefix[it * MAXD + m] = sel[loc[m]];
-            }
-            *c.pre_count = Q;
+    // 2. score every q-subset of the selection (<= C(16, 3) = 560 of them)
+    const int nsub = (int)binom(M, q);
+    N = next_pow2_dev(nsub);
+    for (int e = tid; e < N; e += PRE_WG) {
+        double v = INF;
+        if (e < nsub) {
+            int32_t loc[MAXD], tup[MAXD];
+            colex_unrank_small((uint64_t)e, q, M, loc);
+            for (int m = 0; m < q; ++m) tup[m] = sel[loc[m]];
+            v = ne_sse(c, q, tup);
         }
+        key[e] = v;
+        id[e] = e;
+    }
+    __syncthreads();
+    block_sort(key, id, N);
+    // 3. the PRE_Q best subsets (SSE, then subset rank)
+    if (tid == 0) {
+        int Q = 0;
+        while (Q < PRE_Q && Q < N && key[Q] < INF) ++Q;
+        for (int it = 0; it < Q; ++it) {
+            int32_t loc[MAXD];
+            colex_unrank_small((uint64_t)id[it], q, M, loc);
+            for (int m = 0; m < q; ++m) c.pre_prefix[it * MAXD + m] = sel[loc[m]];
+        }
+        *c.pre_count = Q;
     }
 }
 
 // pre_extend: block qq scores every tuple prefix_qq + {k} that does not
 // contain an earlier chosen prefix (so the tuples of different blocks are
 // distinct) and lies in the searched rank range, and records the L-th
-// smallest SSE.  Q*L >= KP distinct tuples at or below max_q bound_q make
-// that maximum an upper bound of the KP-th best SSE of the search.
-__global__ __launch_bounds__(256) void pre_extend_kernel(Ctx c, int D, int ranged, uint64_t r0,
-                                                         uint64_t r1, int L) {
-    constexpr int LM = KP_MAX / PRE_Q;  // largest L
-    __shared__ double lv[256 * 16];
-    __shared__ int li[256 * 16];
-    __shared__ double wv[SEARCH_WAVES * LM];
-    __shared__ int wi[SEARCH_WAVES * LM];
+// smallest SSE among the candidates it kept.  Those are L distinct real
+// tuples at or below that value, so Q*L >= KP of them at or below the
+// maximum over blocks make that maximum an upper bound of the KP-th best
+// SSE of the search.
+__global__ __launch_bounds__(PRE_WG) void pre_extend_kernel(Ctx c, int D, int ranged, uint64_t r0,
+                                                            uint64_t r1, int L) {
+    __shared__ double key[PRE_SORT];
+    __shared__ int id[PRE_SORT];
     const int qq = blockIdx.x;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x;
     const int Q = *c.pre_count;
-    if (qq >= Q || L > LM) {
+    if (qq >= Q || L > PRE_SORT) {
         if (tid == 0) c.pre_bound[qq] = INF;
         return;
     }
     const int q = D - 1;
     int32_t P[MAXD];
     for (int m = 0; m < q; ++m) P[m] = c.pre_prefix[qq * MAXD + m];
-    // per-thread 16 smallest; the block's L smallest are among the union as
-    // long as L <= 16 per thread is not exceeded by one thread's share, so
-    // each thread keeps min(L, 16) and L <= 16 * 256 always holds
-    LocalTop<16> top;
-    top.init();
-    for (int64_t k = tid; k < c.S; k += 256) {
+    const int N = gather_candidates(key, id, c.S, [&](int64_t k) {
         int32_t tup[MAXD];
         bool inP = false;
         int n = 0;
         for (int m = 0; m < q; ++m) inP |= (P[m] == k);
-        if (inP) continue;
+        if (inP) return INF;
         bool placed = false;
         for (int m = 0; m < q; ++m) {
             if (!placed && k < P[m]) {
@@ -415,47 +393,23 @@ __global__ __launch_bounds__(256) void pre_extend_kernel(Ctx c, int D, int range
             tup[n++] = P[m];
         }
         if (!placed) tup[n++] = (int32_t)k;
-        bool dup = false;
-        for (int o = 0; o < qq && !dup; ++o) {
+        for (int o = 0; o < qq; ++o) {
             int hit = 0;
             for (int m = 0; m < q; ++m) {
                 const int32_t v = c.pre_prefix[o * MAXD + m];
                 for (int u = 0; u < D; ++u) hit += (tup[u] == v);
             }
-            dup = (hit == q);
+            if (hit == q) return INF;
         }
-        if (dup) continue;
         if (ranged) {
             const uint64_t rk = lex_rank(BinomTab{c.btab, c.S}, c.S, D, tup);
-            if (rk < r0 || rk >= r1) continue;
+            if (rk < r0 || rk >= r1) return INF;
         }
-        top.offer(ne_sse(c, D, tup), (int)k);
-    }
-#pragma unroll
-    for (int m = 0; m < 16; ++m) {
-        lv[tid * 16 + m] = top.v[m];
-        li[tid * 16 + m] = top.id[m];
-    }
+        return ne_sse(c, D, tup);
+    });
     __syncthreads();
-    const int Lw = L < 16 ? L : 16;
-    // a thread kept only its 16 best; if one thread's share could hold more
-    // than 16 of the block's L best, the bound is not certified
-    const bool exact = (L <= 16) || ((c.S + 255) / 256 <= 16);
-    const int nw = wave_smallest(lv + wave * 64 * 16, li + wave * 64 * 16, 64 * 16, L, wv + wave * LM,
-                                 wi + wave * LM);
-    if (lane == 0)
-        for (int m = nw; m < LM; ++m) {  // every slot wave 0 scans is defined
-            wv[wave * LM + m] = INF;
-            wi[wave * LM + m] = -1;
-        }
-    __syncthreads();
-    __shared__ double fv[LM];
-    __shared__ int fi[LM];
-    if (wave == 0) {
-        const int n = wave_smallest(wv, wi, SEARCH_WAVES * LM, L, fv, fi);
-        if (lane == 0) c.pre_bound[qq] = (n == L && exact) ? fv[L - 1] : INF;
-    }
-    (void)Lw;
+    block_sort(key, id, N);
+    if (tid == 0) c.pre_bound[qq] = (L <= N && key[L - 1] < INF) ? key[L - 1] : INF;
 }
 
 __device__ double theta0_from_prepass(const Ctx &c, int L, int KP) {
@@ -819,7 +773,16 @@ __global__ __launch_bounds__(256) void search_kernel(Ctx c, SearchArgs a) {
             // the j sweep, versioned on whether lanes need the k > j / k < S masks
             auto sweep = [&](auto checkc) {
                 constexpr bool CHECK = decltype(checkc)::value;
-                auto body = [&](int jj, double g, bool live) {
+                // records of one step: (P', j) for every sub-prefix (one task)
+                typedef double RecSet[NR][q + 3];
+                auto load_rv = [&](RecSet &rv, int jj) {
+                    const double *rj = recs + jj * (NR * RECW);
+#pragma unroll
+                    for (int r = 0; r < NR; ++r)
+#pragma unroll
+                        for (int x = 0; x < q + 3; ++x) rv[r][x] = rj[r * RECW + x];
+                };
+                auto body = [&](int jj, double g, bool live, const RecSet &rvs) {
                     unsigned long long m = 0;
                     if (MT) {
                         // a j whose record is invalid in some task has p = NaN
@@ -841,23 +804,14 @@ __global__ __launch_bounds__(256) void search_kernel(Ctx c, SearchArgs a) {
                         for (int o = 1; o < TL; o <<= 1) sum += __shfl_xor(sum, o);
                         m = __ballot(sum <= theta_f && tl == 0);
                     } else {
-                        // all record reads of this step are issued before any use,
-                        // so their LDS latencies overlap
-                        const double *rj = recs + jj * (NR * RECW);
-                        double rv[NR][q + 3];
-#pragma unroll
-                        for (int r = 0; r < NR; ++r)
-#pragma unroll
-                            for (int x = 0; x < q + 3; ++x) rv[r][x] = rj[r * RECW + x];
-                        __asm__ volatile("" ::: "memory");
 #pragma unroll
                         for (int r = 0; r < NR; ++r) {
                             double u = g;
 #pragma unroll
-                            for (int x = 0; x < q; ++x) u = fma(-rv[r][x], wq[r][x], u);
-                            const double d = fma(-rv[r][q], u * u, dq[r]);
-                            const double z = fma(-rv[r][q + 1], u, zq[r]);
-                            m |= __ballot(z * z >= rv[r][q + 2] * d);
+                            for (int x = 0; x < q; ++x) u = fma(-rvs[r][x], wq[r][x], u);
+                            const double d = fma(-rvs[r][q], u * u, dq[r]);
+                            const double z = fma(-rvs[r][q + 1], u, zq[r]);
+                            m |= __ballot(z * z >= rvs[r][q + 2] * d);
                         }
                     }
                     if (CHECK) m &= __ballot(kin && kr > jj);
@@ -873,7 +827,7 @@ __global__ __launch_bounds__(256) void search_kernel(Ctx c, SearchArgs a) {
                 // rows are fetched a group of JG ahead into the other of two
                 // register sets, so JG loads per wave are in flight while a
                 // group is scored
-                constexpr int JG = 8;
+                constexpr int JG = SEARCH_JG;
                 double ga[JG], gb[JG];
                 // a uniform 64-bit base plus a 32-bit byte offset per load
                 // (uniform row part + per-lane column part)
@@ -893,8 +847,14 @@ __global__ __launch_bounds__(256) void search_kernel(Ctx c, SearchArgs a) {
                 auto score = [&](const double (&src)[JG], int jg) {
 #pragma unroll
                     for (int x = 0; x < JG; ++x) {
-                        const int jj = jg + x;
-                        body(jj <= nrow ? jj : nrow, src[x], jj <= nrow);
+                        const int jj = jg + x <= nrow ? jg + x : nrow;
+                        RecSet rv;
+                        if (!MT) {
+                            // all record reads of the step are issued before any use
+                            load_rv(rv, jj);
+                            __asm__ volatile("" ::: "memory");
+                        }
+                        body(jj, src[x], jg + x <= nrow, rv);
                     }
                 };
                 // drain the loads of the chunk set-up first, so that only the
@@ -1111,6 +1071,7 @@ __global__ __launch_bounds__(256) void rescore_kernel(Ctx c, int D) {
         for (int m = 0; m < D; ++m) mu[m] = c.mu[(int64_t)t * c.S + tup[m]];
         double acc[NACC];
         for (int i = 0; i < NACC; ++i) acc[i] = 0.0;
+#pragma unroll 4
         for (int64_t i = r0 + tid; i < r1; i += 256) {
             double x[MAXD];
             for (int m = 0; m < D; ++m) x[m] = c.F[(int64_t)tup[m] * c.n_total + i] - mu[m];
@@ -1175,6 +1136,7 @@ __global__ __launch_bounds__(256) void rescore_kernel(Ctx c, int D) {
         double beta[MAXD];
         for (int m = 0; m < D; ++m) beta[m] = s_beta[m];
         double ss = 0.0;
+#pragma unroll 4
         for (int64_t i = r0 + tid; i < r1; i += 256) {
             double e = c.y[i] - ym;
             for (int m = 0; m < D; ++m) e -= beta[m] * (c.F[(int64_t)tup[m] * c.n_total + i] - mu[m]);
@@ -1216,6 +1178,7 @@ __global__ __launch_bounds__(1024) void final_kernel(Ctx c, int D, int k, int KP
         const uint64_t ri = fr[i];
         const bool vi = si < INF;
         int pos = 0;
+#pragma unroll 8
         for (int j = 0; j < KP; ++j) {
             const double sj = fs[j];
             const bool vj = sj < INF;
@@ -1299,8 +1262,8 @@ int launch_search(const Ctx &c, const SearchCall &sc, hipStream_t st) {
     } else {
         phase_begin(c, SISSO_PHASE_PREPASS, st);
         hipLaunchKernelGGL(search_init_kernel, dim3(init_blocks), dim3(256), 0, st, c, D, a.R, a.JB);
-        hipLaunchKernelGGL(pre_select_kernel, dim3(1), dim3(256), 0, st, c, D);
-        hipLaunchKernelGGL(pre_extend_kernel, dim3(PRE_Q), dim3(256), 0, st, c, D, sc.ranged,
+        hipLaunchKernelGGL(pre_select_kernel, dim3(1), dim3(PRE_WG), 0, st, c, D);
+        hipLaunchKernelGGL(pre_extend_kernel, dim3(PRE_Q), dim3(PRE_WG), 0, st, c, D, sc.ranged,
                            sc.r0, sc.r1, a.L);
         phase_end(c, SISSO_PHASE_PREPASS, st);
         phase_begin(c, SISSO_PHASE_SEARCH, st);

@@ -101,3 +101,33 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(B, "_lib", None)
     with pytest.raises(RuntimeError, match="no fallback"):
         B.load()
+
+
+def test_tuning_and_report_entry_points_reject_null_handle():
+    lib = B.load()
+    lib.sisso_l0_set_search_grid.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+    lib.sisso_l0_set_search_grid.restype = ctypes.c_int32
+    lib.sisso_l0_search_grid.argtypes = [ctypes.c_void_p]
+    lib.sisso_l0_search_grid.restype = ctypes.c_int32
+    lib.sisso_l0_autotune.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_char_p,
+                                      ctypes.POINTER(ctypes.c_int32)]
+    lib.sisso_l0_autotune.restype = ctypes.c_int32
+    lib.sisso_l0_precision_report.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
+    lib.sisso_l0_precision_report.restype = ctypes.c_int32
+    assert lib.sisso_l0_set_search_grid(None, 256) == B.SISSO_EINVAL
+    assert lib.sisso_l0_search_grid(None) == 0
+    assert lib.sisso_l0_autotune(None, 3, 10, None, None) == B.SISSO_EINVAL
+    out = (ctypes.c_double * 4)()
+    assert lib.sisso_l0_precision_report(None, 16, out) == B.SISSO_EINVAL
+
+
+def test_precision_modes_size_the_workspace():
+    def ws(prec, n=5000, S=300):
+        d = B.make_desc(0, 0, np.array([0, n], dtype=np.int64), n, S, 2, 10, precision=prec)
+        return B.sisso_l0_workspace_bytes(d)
+    fp64, bf16 = ws(B.SISSO_PREC_FP64), ws(B.SISSO_PREC_BF16_COMP)
+    # three BF16 slices of every padded column plus one exponent per 256-sample chunk
+    n_chunks = (5000 + 255) // 256 + 1
+    assert bf16 - fp64 >= 3 * 300 * n_chunks * 256 * 2 + 300 * n_chunks * 4
+    assert ws(B.SISSO_PREC_FP16_COMP) == 0      # reserved mode, not built
+    assert ws(7) == 0
