@@ -145,6 +145,35 @@ const char *sisso_l0_batch_last_error(void);
  * GPU work has finished). */
 int32_t sisso_l0_search_batch(sisso_l0 *const *hs, int32_t P, int32_t D, int32_t k);
 
+/* Prefix-list evaluation (the exact half of a learned proposal; see
+ * include/sisso_mlp.h).  prefixes: DEVICE int32 [n][m], each row strictly
+ * increasing indices in [0, S).  Every tuple P + {j} (j not in P) is scored
+ * exactly like the exhaustive search scores it (normal equations on the
+ * correlation matrices, sorted-index Cholesky, the same rank rule), so a
+ * tuple reached from several prefixes gets one SSE.  Asynchronous; ESTATE
+ * before sisso_gram; EINVAL for bad sizes or null pointers.
+ *  - sisso_l0_prefix_best: best[p] (DEVICE double [n]) = min over j of
+ *    SSE(P + {j}), +inf if no extension is full rank, NaN for a malformed
+ *    row.  1 <= m <= SISSO_MAX_D - 1 (ENOTSUP above).  Exhaustive over the
+ *    extensions, so a list of all m-subsets gives per-prefix minima of an
+ *    exhaustive (m+1)-search.
+ *  - sisso_l0_prefix_features: feat (DEVICE float [n][8]) = R^2 of P's own
+ *    fit, max/min/mean squared correlation with y of P's features, max/mean
+ *    |G| among them, R^2 minus the best single squared correlation, 1/m.
+ *    Malformed rows give NaN.  1 <= m <= SISSO_MAX_D.
+ *  - sisso_l0_search_list: the k best distinct D-tuples among all extensions
+ *    of the list (D = m + 1, same rules as sisso_l0_search on D and k),
+ *    exactly re-scored and read with sisso_l0_topk; malformed rows are
+ *    skipped.  sisso_l0_scored reports n (S - D + 1). */
+int32_t sisso_l0_prefix_best(sisso_l0 *h, int32_t m, const int32_t *prefixes, int64_t n, double *best);
+int32_t sisso_l0_prefix_features(sisso_l0 *h, int32_t m, const int32_t *prefixes, int64_t n, float *feat);
+int32_t sisso_l0_search_list(sisso_l0 *h, int32_t D, int32_t k, const int32_t *prefixes, int64_t n);
+/* Features (as sisso_l0_prefix_features) of the m-subsets of {0..S-1}
+ * (1 <= m <= 3) with colexicographic ranks r0 .. r0 + n - 1, i.e. ordered
+ * by largest element, then by the rest in the same order; feat: DEVICE
+ * float [n][8].  EINVAL if the range exceeds C(S, m). */
+int32_t sisso_l0_prefix_features_range(sisso_l0 *h, int32_t m, uint64_t r0, int64_t n, float *feat);
+
 /* Launch tuning.  The persistent search kernel runs on a grid of
  * workgroups (default 1024) whose best size depends on the problem; it
  * changes no arithmetic, so every size gives bit-identical results.  (The

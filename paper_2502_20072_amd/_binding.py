@@ -302,3 +302,107 @@ def sisso_l0_search_batch(handles, D: int, k: int) -> None:
     _batch_sigs(lib)
     arr = (ctypes.c_void_p * len(handles))(*handles)
     _batch_check(lib.sisso_l0_search_batch(arr, len(handles), D, k))
+
+
+# ------------------------------------------------ prefix lists and the MLP
+MLP_IN = 8
+MLP_HIDDEN = 128
+MLP_NPARAM = MLP_IN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN + 1
+PROP_NF = 8
+
+_sigs_done = False
+
+
+def _prop_sigs(lib):
+    global _sigs_done
+    if _sigs_done:
+        return
+    P, V, I32, I64, U64, SZ = ctypes.POINTER, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_size_t
+    for name, args in [("sisso_l0_prefix_best", [V, I32, V, I64, V]),
+                       ("sisso_l0_prefix_features", [V, I32, V, I64, V]),
+                       ("sisso_l0_prefix_features_range", [V, I32, U64, I64, V]),
+                       ("sisso_l0_search_list", [V, I32, I32, V, I64]),
+                       ("sisso_mlp_forward", [V, V, I64, V, V, SZ, V]),
+                       ("sisso_mlp_backward", [V, V, V, I64, V, V, V, SZ, V]),
+                       ("sisso_mlp_adam", [V, V, V, V, I32, ctypes.c_float, V]),
+                       ("sisso_mlp_infer_bf16", [V, V, I64, V, V]),
+                       ("sisso_select_top", [V, I64, I64, V, I64, P(I64), V, SZ, V]),
+                       ("sisso_colex_unrank", [I32, V, I64, V, V])]:
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = I32
+    lib.sisso_mlp_workspace_bytes.argtypes = [I64]
+    lib.sisso_mlp_workspace_bytes.restype = SZ
+    lib.sisso_select_workspace_bytes.argtypes = []
+    lib.sisso_select_workspace_bytes.restype = SZ
+    _sigs_done = True
+
+
+def _plib():
+    lib = load()
+    _prop_sigs(lib)
+    return lib
+
+
+def _ptr(t) -> int:
+    return int(t.data_ptr())
+
+
+def _raw_check(rc: int, what: str):
+    if rc != SISSO_OK:
+        raise SissoError(rc, f"{what} failed ({rc})")
+
+
+def sisso_l0_prefix_best(h: int, m: int, prefixes, best) -> None:
+    _check(_plib().sisso_l0_prefix_best(h, m, _ptr(prefixes), prefixes.shape[0], _ptr(best)), h)
+
+
+def sisso_l0_prefix_features(h: int, m: int, prefixes, feat) -> None:
+    _check(_plib().sisso_l0_prefix_features(h, m, _ptr(prefixes), prefixes.shape[0], _ptr(feat)), h)
+
+
+def sisso_l0_prefix_features_range(h: int, m: int, r0: int, n: int, feat) -> None:
+    _check(_plib().sisso_l0_prefix_features_range(h, m, r0, n, _ptr(feat)), h)
+
+
+def sisso_l0_search_list(h: int, D: int, k: int, prefixes) -> None:
+    _check(_plib().sisso_l0_search_list(h, D, k, _ptr(prefixes), prefixes.shape[0]), h)
+
+
+def sisso_mlp_workspace_bytes(n: int) -> int:
+    return int(_plib().sisso_mlp_workspace_bytes(n))
+
+
+def sisso_mlp_forward(params, x, out, ws, stream: int) -> None:
+    _raw_check(_plib().sisso_mlp_forward(_ptr(params), _ptr(x), x.shape[0], _ptr(out), _ptr(ws), ws.numel(), stream),
+               "sisso_mlp_forward")
+
+
+def sisso_mlp_backward(params, x, target, grad, loss, ws, stream: int) -> None:
+    _raw_check(_plib().sisso_mlp_backward(_ptr(params), _ptr(x), _ptr(target), x.shape[0], _ptr(grad), _ptr(loss),
+                                          _ptr(ws), ws.numel(), stream), "sisso_mlp_backward")
+
+
+def sisso_mlp_adam(params, grad, m, v, step: int, lr: float, stream: int) -> None:
+    _raw_check(_plib().sisso_mlp_adam(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), step, lr, stream), "sisso_mlp_adam")
+
+
+def sisso_mlp_infer_bf16(params, x, out, stream: int) -> None:
+    _raw_check(_plib().sisso_mlp_infer_bf16(_ptr(params), _ptr(x), x.shape[0], _ptr(out), stream),
+               "sisso_mlp_infer_bf16")
+
+
+def sisso_select_workspace_bytes() -> int:
+    return int(_plib().sisso_select_workspace_bytes())
+
+
+def sisso_select_top(scores, K: int, out, ws, stream: int) -> int:
+    cnt = ctypes.c_int64(0)
+    _raw_check(_plib().sisso_select_top(_ptr(scores), scores.shape[0], K, _ptr(out), out.shape[0], ctypes.byref(cnt),
+                                        _ptr(ws), ws.numel(), stream), "sisso_select_top")
+    return int(cnt.value)
+
+
+def sisso_colex_unrank(m: int, ranks, prefixes, stream: int) -> None:
+    _raw_check(_plib().sisso_colex_unrank(m, _ptr(ranks), ranks.shape[0], _ptr(prefixes), stream),
+               "sisso_colex_unrank")

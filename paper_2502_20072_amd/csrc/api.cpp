@@ -284,6 +284,72 @@ extern "C" int32_t sisso_l0_search_range(sisso_l0 *h, int32_t D, int32_t k, uint
     return do_search(h, D, k, true, r0, r1);
 }
 
+// ------------------------------------------------------ prefix-list calls
+static int32_t check_prefixes(sisso_l0 *h, int32_t m, const void *pre, int64_t n) {
+    if (!h) return SISSO_EINVAL;
+    h->err.clear();
+    if (!h->gram_done) return fail(h, SISSO_ESTATE, "sisso_gram must run first");
+    if (n < 0 || (n > 0 && !pre)) return fail(h, SISSO_EINVAL, "null prefix list or negative count");
+    if (m < 1 || m > h->desc.S) return fail(h, SISSO_EINVAL, "need 1 <= prefix length <= S");
+    return SISSO_OK;
+}
+
+extern "C" int32_t sisso_l0_prefix_best(sisso_l0 *h, int32_t m, const int32_t *prefixes, int64_t n, double *best) {
+    int32_t rc = check_prefixes(h, m, prefixes, n);
+    if (rc != SISSO_OK) return rc;
+    if (m + 1 > SISSO_MAX_D) return fail(h, SISSO_ENOTSUP, "prefix length + 1 exceeds SISSO_MAX_D");
+    if (n > 0 && !best) return fail(h, SISSO_EINVAL, "null output");
+    for (int t = 0; t < h->desc.T; ++t)
+        if (h->offsets[t + 1] - h->offsets[t] < m + 3) return fail(h, SISSO_EINVAL, "a task has too few rows");
+    if (n == 0) return SISSO_OK;
+    if (launch_prefix_best(h->ctx, m, prefixes, n, best, h->stream))
+        return fail(h, SISSO_EDEVICE, hipGetErrorString(hipGetLastError()));
+    return SISSO_OK;
+}
+
+extern "C" int32_t sisso_l0_prefix_features(sisso_l0 *h, int32_t m, const int32_t *prefixes, int64_t n, float *feat) {
+    int32_t rc = check_prefixes(h, m, prefixes, n);
+    if (rc != SISSO_OK) return rc;
+    if (m > SISSO_MAX_D) return fail(h, SISSO_ENOTSUP, "prefix length exceeds SISSO_MAX_D");
+    if (n > 0 && !feat) return fail(h, SISSO_EINVAL, "null output");
+    if (n == 0) return SISSO_OK;
+    if (launch_prefix_features(h->ctx, m, prefixes, n, feat, h->stream))
+        return fail(h, SISSO_EDEVICE, hipGetErrorString(hipGetLastError()));
+    return SISSO_OK;
+}
+
+extern "C" int32_t sisso_l0_prefix_features_range(sisso_l0 *h, int32_t m, uint64_t r0, int64_t n, float *feat) {
+    if (!h) return SISSO_EINVAL;
+    h->err.clear();
+    if (!h->gram_done) return fail(h, SISSO_ESTATE, "sisso_gram must run first");
+    if (m < 1 || m > 3 || m > h->desc.S) return fail(h, SISSO_EINVAL, "need 1 <= m <= 3 and m <= S");
+    if (n < 0 || (n > 0 && !feat)) return fail(h, SISSO_EINVAL, "null output or negative count");
+    const uint64_t total = binom(h->desc.S, m);
+    if (r0 > total || (uint64_t)n > total - r0) return fail(h, SISSO_EINVAL, "rank range exceeds C(S, m)");
+    if (n == 0) return SISSO_OK;
+    if (launch_prefix_features_range(h->ctx, m, r0, n, feat, h->stream))
+        return fail(h, SISSO_EDEVICE, hipGetErrorString(hipGetLastError()));
+    return SISSO_OK;
+}
+
+extern "C" int32_t sisso_l0_search_list(sisso_l0 *h, int32_t D, int32_t k, const int32_t *prefixes, int64_t n) {
+    int32_t rc = check_prefixes(h, D - 1, prefixes, n);
+    if (rc != SISSO_OK) return rc;
+    SearchCall sc;
+    uint64_t scored = 0;
+    rc = check_search(h, D, k, false, 0, 0, true, &sc, &scored);
+    if (rc != SISSO_OK) return rc;
+    if (D < 2) return fail(h, SISSO_EINVAL, "a prefix list needs D >= 2");
+    if (launch_list_search(h->ctx, D, k, prefixes, n, h->stream))
+        return fail(h, SISSO_EDEVICE, hipGetErrorString(hipGetLastError()));
+    for (int ph = SISSO_PHASE_PREPASS; ph <= SISSO_PHASE_FINAL; ++ph) h->ran[ph] = h->prof;
+    h->search_done = true;
+    h->last_D = D;
+    h->last_k = k;
+    h->scored = (uint64_t)n * (uint64_t)(h->desc.S - D + 1);
+    return SISSO_OK;
+}
+
 // ---------------------------------------------------------------- autotuner
 // The persistent search grid is the one launch parameter whose best value
 // depends on the problem (items per workgroup vs. latency hiding) and that

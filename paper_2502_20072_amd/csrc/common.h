@@ -23,6 +23,7 @@ constexpr int PRE_M = 16;              // features the threshold pre-pass starts
 constexpr int PRE_Q = 8;               // best prefixes the pre-pass extends by every feature
 constexpr int KP_MAX = 512;            // longest per-wave candidate list
 constexpr int LP_XC = 256;             // precision form: samples per slice-exponent chunk
+constexpr int PROP_NF = 8;             // learned proposal: features per prefix
 
 // ---------------------------------------------------------------- binomials
 // C(n, r) exactly in 64-bit arithmetic, saturating at UINT64_MAX (never
@@ -166,6 +167,16 @@ __host__ __device__ inline int64_t gidx(int64_t i, int64_t k, int64_t nt, int TP
 __host__ __device__ inline void colex_unrank_small(uint64_t r, int q, int64_t N, int32_t *t) {
     if (q == 1) {
         t[0] = (int32_t)r;
+        return;
+    }
+    if (q == 3) {
+        // largest c with c (c - 1) (c - 2) / 6 <= r, then the pair below it
+        int64_t c = (int64_t)cbrt(6.0 * (double)r) + 2;
+        auto c3 = [](int64_t x) { return x < 3 ? (uint64_t)0 : (uint64_t)(x * (x - 1) / 2) * (uint64_t)(x - 2) / 3; };
+        while (c > 2 && c3(c) > r) --c;
+        while (c3(c + 1) <= r) ++c;
+        t[2] = (int32_t)c;
+        colex_unrank_small(r - c3(c), 2, c, t);
         return;
     }
     if (q == 2) {

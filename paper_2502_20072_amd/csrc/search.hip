@@ -149,6 +149,7 @@ __device__ void list_insert(double *Ls, uint64_t *Lr, int KP, double s, uint64_t
         pos += __popcll(__ballot(key_less(Ls[e], Lr[e], s, r)));
     }
     if (pos >= KP) return;
+    if (Ls[pos] == s && Lr[pos] == r) return;  // the same tuple, offered twice (list search)
     double vs[KP_MAX / 64];
     uint64_t vr[KP_MAX / 64];
 #pragma unroll
@@ -933,6 +934,185 @@ __global__ __launch_bounds__(256) void search_d1_kernel(Ctx c, SearchArgs a) {
     }
 }
 
+// ------------------------------------------------- prefix-list evaluation
+// Exact evaluation driven by a list of (D-1)-prefixes: every tuple P + {k}
+// (k not in P) is scored by ne_sse on its sorted indices, so a tuple reached
+// from several prefixes of the list gets bitwise the same SSE and key.
+
+// Sorted tuple P + {k} (P sorted, k not in P); returns false if k is in P.
+template <int M>
+__device__ inline bool extend_sorted(const int32_t *P, int32_t k, int32_t *tup) {
+    int n = 0;
+    bool placed = false, dup = false;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        dup |= P[m] == k;
+        if (!placed && k < P[m]) {
+            tup[n++] = k;
+            placed = true;
+        }
+        tup[n++] = P[m];
+    }
+    if (!placed) tup[n] = k;
+    return !dup;
+}
+
+// Reads prefix p (M indices) and checks it: strictly increasing, in [0, S).
+template <int M>
+__device__ inline bool load_prefix(const Ctx &c, const int32_t *pre, int64_t p, int32_t *P) {
+    bool ok = true;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        P[m] = pre[p * M + m];
+        ok &= P[m] >= 0 && P[m] < c.S && (m == 0 || P[m] > P[m - 1]);
+    }
+    return ok;
+}
+
+// best[p] = min over k not in P of SSE(P + {k}); +inf if no extension is
+// full rank, NaN for a malformed prefix.  One wavefront per prefix.
+template <int M>
+__global__ __launch_bounds__(256) void prefix_best_kernel(Ctx c, const int32_t *__restrict__ pre, int64_t n,
+                                                          double *__restrict__ best) {
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = (int64_t)gridDim.x * 4;
+    for (int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); p < n; p += nw) {
+        int32_t P[M];
+        const bool ok = load_prefix<M>(c, pre, p, P);
+        double mn = INF;
+        if (ok)
+            for (int64_t k = lane; k < c.S; k += 64) {
+                int32_t tup[M + 1];
+                if (extend_sorted<M>(P, (int32_t)k, tup)) mn = fmin(mn, ne_sse_t<M + 1>(c, tup));
+            }
+        for (int o = 32; o >= 1; o >>= 1) mn = fmin(mn, __shfl_xor(mn, o));
+        if (lane == 0) best[p] = ok ? mn : __builtin_nan("");
+    }
+}
+
+// Top-k candidates over the extensions of a prefix list: persistent waves
+// take prefixes in turn, lanes run over k, and each wave keeps its sorted
+// list as in the exhaustive search (bound: own KP-th entry and the
+// device-wide bound).  The lists feed the same merge, re-score and final
+// ordering (merge removes tuples that several prefixes produced).
+template <int M>
+__global__ __launch_bounds__(256) void list_search_kernel(Ctx c, const int32_t *__restrict__ pre, int64_t n) {
+    extern __shared__ double smem[];
+    const int KP = c.KP;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double *Ls = smem + (size_t)wave * KP * 2;
+    uint64_t *Lr = reinterpret_cast<uint64_t *>(Ls + KP);
+    for (int m = lane; m < KP; m += 64) {
+        Ls[m] = INF;
+        Lr[m] = ~0ull;
+    }
+    double theta_pub = INF;
+    const int64_t gw = (int64_t)blockIdx.x * SEARCH_WAVES + wave;
+    const int64_t nw = (int64_t)gridDim.x * SEARCH_WAVES;
+    for (int64_t p = gw; p < n; p += nw) {
+        int32_t P[M];
+        if (!load_prefix<M>(c, pre, p, P)) continue;
+        for (int64_t kb = 0; kb < c.S; kb += 64) {
+            const int64_t k = kb + lane;
+            double sse = INF;
+            uint64_t key = ~0ull;
+            int32_t tup[M + 1];
+            if (k < c.S && extend_sorted<M>(P, (int32_t)k, tup)) {
+                sse = ne_sse_t<M + 1>(c, tup);
+                key = pack_tuple(tup, M + 1);
+            }
+            const double th = fmin(Ls[KP - 1], theta_load(c.theta_bits));
+            unsigned long long m = __ballot(sse < INF && sse <= th);
+            if (m && lane == 0) atomicAdd(c.cand_counter, (unsigned)__popcll(m));
+            while (m) {
+                const int src = __ffsll((long long)m) - 1;
+                m &= m - 1;
+                list_insert(Ls, Lr, KP, __shfl(sse, src), (uint64_t)__shfl((long long)key, src));
+            }
+            const double tw = Ls[KP - 1];
+            if (tw < theta_pub) {
+                theta_pub = tw;
+                if (lane == 0) theta_publish(c.theta_bits, tw);
+            }
+        }
+    }
+    for (int m = lane; m < KP; m += 64) {
+        c.list_sse[gw * KP + m] = Ls[m];
+        c.list_rank[gw * KP + m] = Lr[m];
+    }
+}
+
+// Per-prefix features for the learned proposal (FP32, PROP_NF per prefix),
+// dimension-agnostic so that a model trained on one prefix length applies
+// to another: with r_i^2 = b_i^2 / c (squared correlation with y) and the
+// prefix's own fit R^2 = 1 - SSE(P) / c (sums over tasks):
+//   R^2, max r_i^2, min r_i^2, mean r_i^2, max |G_ij|, mean |G_ij|,
+//   R^2 - max r_i^2 (gain over the best single feature), 1 / M.
+// One thread per prefix.
+template <int M>
+__device__ void prefix_features(const Ctx &c, const int32_t *P, float *o) {
+    double ctot = 0.0;
+    for (int t = 0; t < c.T; ++t) ctot += c.cyy[t];
+    const double ic = ctot > 0.0 ? 1.0 / ctot : 0.0;
+    double r2max = 0.0, r2min = INF, r2sum = 0.0, gmax = 0.0, gsum = 0.0;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        double e = 0.0;
+        for (int t = 0; t < c.T; ++t) {
+            const double b = c.bhat[(int64_t)P[m] * c.TP + t];
+            e += b * b;
+        }
+        e *= ic;
+        r2max = fmax(r2max, e);
+        r2min = fmin(r2min, e);
+        r2sum += e;
+#pragma unroll
+        for (int l = 0; l < m; ++l) {
+            double g = 0.0;
+            for (int t = 0; t < c.T; ++t) g = fmax(g, fabs(Gat(c, P[m], P[l], t)));
+            gmax = fmax(gmax, g);
+            gsum += g;
+        }
+    }
+    const double sse = ne_sse_t<M>(c, P);
+    const double R2 = sse < INF ? 1.0 - sse * ic : 0.0;
+    o[0] = (float)R2;
+    o[1] = (float)r2max;
+    o[2] = (float)r2min;
+    o[3] = (float)(r2sum / M);
+    o[4] = (float)gmax;
+    o[5] = (float)(M > 1 ? gsum / (M * (M - 1) / 2) : 0.0);
+    o[6] = (float)(R2 - r2max);
+    o[7] = (float)(1.0 / M);
+}
+
+// Features of the prefixes of a list (one thread each).
+template <int M>
+__global__ __launch_bounds__(256) void prefix_features_kernel(Ctx c, const int32_t *__restrict__ pre, int64_t n,
+                                                              float *__restrict__ out) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    int32_t P[M];
+    float *o = out + p * PROP_NF;
+    if (!load_prefix<M>(c, pre, p, P)) {
+        for (int f = 0; f < PROP_NF; ++f) o[f] = __builtin_nanf("");
+        return;
+    }
+    prefix_features<M>(c, P, o);
+}
+
+// Features of the M-subsets of {0..S-1} with colexicographic ranks
+// r0 .. r0 + n - 1 (no prefix array needed for a full sweep).
+template <int M>
+__global__ __launch_bounds__(256) void prefix_features_range_kernel(Ctx c, uint64_t r0, int64_t n,
+                                                                    float *__restrict__ out) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    int32_t P[M];
+    colex_unrank_small(r0 + (uint64_t)p, M, c.S, P);
+    prefix_features<M>(c, P, out + p * PROP_NF);
+}
+
 // ----------------------------------------------------------------- merge
 // One workgroup: gather every list entry at or below the final bound, then
 // select the KP smallest (SSE, rank) keys with bitonic sorts in LDS, a
@@ -1000,7 +1180,26 @@ __global__ __launch_bounds__(MERGE_THREADS) void merge_compact_kernel(Ctx c, int
 // merge_select: one workgroup selects the KP smallest (SSE, key) pairs of
 // the candidates with bitonic sorts in LDS, carrying a running top-KP across
 // chunks when there are many.
-__global__ __launch_bounds__(MERGE_THREADS) void merge_select_kernel(Ctx c, int KP, int L, int use_pre) {
+// Marks the later copy of every adjacent equal (SSE, key) pair as empty and
+// re-sorts (a prefix-list search can offer one tuple from several prefixes,
+// always with bitwise the same SSE, so copies are adjacent after a sort).
+__device__ void drop_adjacent_duplicates(double *ks, uint64_t *kr, int N) {
+    bool dup[MERGE_CAP / MERGE_THREADS];
+    int nd = 0;
+    for (int i = threadIdx.x, u = 0; i < N; i += MERGE_THREADS, ++u) {
+        dup[u] = i > 0 && ks[i] < INF && ks[i] == ks[i - 1] && kr[i] == kr[i - 1];
+        nd += dup[u];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x, u = 0; i < N; i += MERGE_THREADS, ++u)
+        if (dup[u]) {
+            ks[i] = INF;
+            kr[i] = ~0ull;
+        }
+    if (__syncthreads_or(nd)) bitonic_sort_lds(ks, kr, N);
+}
+
+__global__ __launch_bounds__(MERGE_THREADS) void merge_select_kernel(Ctx c, int KP, int L, int use_pre, int dedupe) {
     __shared__ double ks[MERGE_CAP];
     __shared__ uint64_t kr[MERGE_CAP];
     const int tid = threadIdx.x;
@@ -1033,6 +1232,7 @@ __global__ __launch_bounds__(MERGE_THREADS) void merge_select_kernel(Ctx c, int 
         }
         __syncthreads();
         bitonic_sort_lds(ks, kr, N);
+        if (dedupe) drop_adjacent_duplicates(ks, kr, N);
         if (base + chunk >= total) break;
     }
     for (int i = tid; i < KP; i += MERGE_THREADS) {
@@ -1220,11 +1420,11 @@ static void launch_one(const Ctx &c, const SearchArgs &a, size_t lds, hipStream_
     hipLaunchKernelGGL((search_kernel<D, MT>), dim3(c.search_wgs), dim3(SEARCH_WG), lds, st, c, a);
 }
 
-static void launch_merge(const Ctx &c, int nlists, int L, int use_pre, hipStream_t st) {
+static void launch_merge(const Ctx &c, int nlists, int L, int use_pre, hipStream_t st, int dedupe = 0) {
     const int per = MERGE_THREADS / 64;
     hipLaunchKernelGGL(merge_compact_kernel, dim3((nlists + per - 1) / per), dim3(MERGE_THREADS), 0, st, c, nlists,
                        c.KP, L, use_pre);
-    hipLaunchKernelGGL(merge_select_kernel, dim3(1), dim3(MERGE_THREADS), 0, st, c, c.KP, L, use_pre);
+    hipLaunchKernelGGL(merge_select_kernel, dim3(1), dim3(MERGE_THREADS), 0, st, c, c.KP, L, use_pre, dedupe);
 }
 
 int launch_search(const Ctx &c, const SearchCall &sc, hipStream_t st) {
@@ -1284,6 +1484,70 @@ int launch_search(const Ctx &c, const SearchCall &sc, hipStream_t st) {
     phase_end(c, SISSO_PHASE_RESCORE, st);
     phase_begin(c, SISSO_PHASE_FINAL, st);
     hipLaunchKernelGGL(final_kernel, dim3(1), dim3(1024), 0, st, c, D, sc.k, c.KP);
+    phase_end(c, SISSO_PHASE_FINAL, st);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+
+int launch_prefix_best(const Ctx &c, int M, const int32_t *pre, int64_t n, double *best, hipStream_t st) {
+    const unsigned wgs = (unsigned)(n < 4096 ? (n + 3) / 4 : 1024);
+    switch (M) {
+        case 1: hipLaunchKernelGGL((prefix_best_kernel<1>), dim3(wgs), dim3(256), 0, st, c, pre, n, best); break;
+        case 2: hipLaunchKernelGGL((prefix_best_kernel<2>), dim3(wgs), dim3(256), 0, st, c, pre, n, best); break;
+        case 3: hipLaunchKernelGGL((prefix_best_kernel<3>), dim3(wgs), dim3(256), 0, st, c, pre, n, best); break;
+        default: return -1;
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_prefix_features(const Ctx &c, int M, const int32_t *pre, int64_t n, float *out, hipStream_t st) {
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    switch (M) {
+        case 1: hipLaunchKernelGGL((prefix_features_kernel<1>), dim3(blocks), dim3(256), 0, st, c, pre, n, out); break;
+        case 2: hipLaunchKernelGGL((prefix_features_kernel<2>), dim3(blocks), dim3(256), 0, st, c, pre, n, out); break;
+        case 3: hipLaunchKernelGGL((prefix_features_kernel<3>), dim3(blocks), dim3(256), 0, st, c, pre, n, out); break;
+        case 4: hipLaunchKernelGGL((prefix_features_kernel<4>), dim3(blocks), dim3(256), 0, st, c, pre, n, out); break;
+        default: return -1;
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_prefix_features_range(const Ctx &c, int M, uint64_t r0, int64_t n, float *out, hipStream_t st) {
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    switch (M) {
+        case 1: hipLaunchKernelGGL((prefix_features_range_kernel<1>), dim3(blocks), dim3(256), 0, st, c, r0, n, out); break;
+        case 2: hipLaunchKernelGGL((prefix_features_range_kernel<2>), dim3(blocks), dim3(256), 0, st, c, r0, n, out); break;
+        case 3: hipLaunchKernelGGL((prefix_features_range_kernel<3>), dim3(blocks), dim3(256), 0, st, c, r0, n, out); break;
+        default: return -1;
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_list_search(const Ctx &c, int D, int k, const int32_t *pre, int64_t n, hipStream_t st) {
+    const unsigned init_blocks = (unsigned)(((SISSO_MAX_D + 1) * (c.S + 1) + 255) / 256);
+    phase_begin(c, SISSO_PHASE_PREPASS, st);
+    hipLaunchKernelGGL(search_init_kernel, dim3(init_blocks), dim3(256), 0, st, c, 2, 1, JBLK);
+    phase_end(c, SISSO_PHASE_PREPASS, st);
+    int64_t wgs = (n + SEARCH_WAVES - 1) / SEARCH_WAVES;
+    if (wgs > c.search_wgs) wgs = c.search_wgs;
+    if (wgs < 1) wgs = 1;
+    const size_t lds = (size_t)SEARCH_WAVES * c.KP * 2 * sizeof(double);
+    phase_begin(c, SISSO_PHASE_SEARCH, st);
+    switch (D - 1) {
+        case 1: hipLaunchKernelGGL((list_search_kernel<1>), dim3((unsigned)wgs), dim3(SEARCH_WG), lds, st, c, pre, n); break;
+        case 2: hipLaunchKernelGGL((list_search_kernel<2>), dim3((unsigned)wgs), dim3(SEARCH_WG), lds, st, c, pre, n); break;
+        case 3: hipLaunchKernelGGL((list_search_kernel<3>), dim3((unsigned)wgs), dim3(SEARCH_WG), lds, st, c, pre, n); break;
+        default: return -1;
+    }
+    phase_end(c, SISSO_PHASE_SEARCH, st);
+    phase_begin(c, SISSO_PHASE_MERGE, st);
+    launch_merge(c, (int)wgs * SEARCH_WAVES, 1, 0, st, 1);
+    phase_end(c, SISSO_PHASE_MERGE, st);
+    phase_begin(c, SISSO_PHASE_RESCORE, st);
+    hipLaunchKernelGGL(rescore_kernel, dim3(c.KP), dim3(256), 0, st, c, D);
+    phase_end(c, SISSO_PHASE_RESCORE, st);
+    phase_begin(c, SISSO_PHASE_FINAL, st);
+    hipLaunchKernelGGL(final_kernel, dim3(1), dim3(1024), 0, st, c, D, k, c.KP);
     phase_end(c, SISSO_PHASE_FINAL, st);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }

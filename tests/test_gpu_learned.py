@@ -1,0 +1,205 @@
+"""Learned proposal: the network kernels against the FP64 reference, the
+prefix-list kernels against the CPU oracle, and the proposal against
+exhaustive search (the judge of recall)."""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp_ref as R
+from synth import make_problem
+from tests.parity import compare_topk
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _t(a, dtype=None):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0") if dtype is None else \
+        torch.from_numpy(np.ascontiguousarray(a, dtype=dtype)).to("cuda:0")
+
+
+def _st():
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def test_mlp_forward_backward_adam_match_reference():
+    import torch
+    from paper_2502_20072_amd import _binding as B
+    rng = np.random.default_rng(11)
+    flat = rng.normal(0, 0.15, R.NPARAM)
+    n = 300
+    X = rng.normal(size=(n, R.IN))
+    Y = rng.normal(size=n)
+    _say("mlp forward/backward n=300")
+    P, Xd, Yd = _t(flat, np.float32), _t(X, np.float32), _t(Y, np.float32)
+    ws = torch.empty(B.sisso_mlp_workspace_bytes(n), dtype=torch.uint8, device="cuda:0")
+    out = torch.empty(n, dtype=torch.float32, device="cuda:0")
+    grad = torch.empty(R.NPARAM, dtype=torch.float32, device="cuda:0")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda:0")
+    B.sisso_mlp_forward(P, Xd, out, ws, _st())
+    B.sisso_mlp_backward(P, Xd, Yd, grad, loss, ws, _st())
+    # reference on the FP32-rounded inputs
+    f32 = lambda a: np.asarray(a, dtype=np.float32).astype(np.float64)
+    ref_out, _ = R.forward(f32(flat), f32(X))
+    ref_loss, ref_g = R.loss_and_grad(f32(flat), f32(X), f32(Y))
+    o = out.cpu().numpy()
+    np.testing.assert_allclose(o, ref_out, rtol=0, atol=2e-5 * np.max(np.abs(ref_out)))
+    assert abs(loss.item() - ref_loss) <= 1e-4 * ref_loss
+    g = grad.cpu().numpy()
+    np.testing.assert_allclose(g, ref_g, rtol=0, atol=2e-5 * np.max(np.abs(ref_g)))
+    # deterministic (ordered reductions)
+    g2 = torch.empty_like(grad)
+    B.sisso_mlp_backward(P, Xd, Yd, g2, loss, ws, _st())
+    assert torch.equal(grad, g2)
+    # one Adam step
+    m, v = torch.zeros_like(P), torch.zeros_like(P)
+    B.sisso_mlp_adam(P, grad, m, v, 1, 1e-3, _st())
+    ref_p, ref_m, _ = R.adam(f32(flat), g.astype(np.float64), np.zeros(R.NPARAM), np.zeros(R.NPARAM), 1, 1e-3)
+    np.testing.assert_allclose(P.cpu().numpy(), ref_p, rtol=0, atol=2e-6)
+
+
+def test_bf16_inference_close_to_fp64():
+    from paper_2502_20072_amd import _binding as B
+    import torch
+    rng = np.random.default_rng(12)
+    flat = rng.normal(0, 0.1, R.NPARAM)
+    for n in (1, 63, 64, 1000):
+        X = rng.uniform(0, 1, size=(n, R.IN))
+        _say(f"bf16 inference n={n}")
+        out = torch.empty(n, dtype=torch.float32, device="cuda:0")
+        B.sisso_mlp_infer_bf16(_t(flat, np.float32), _t(X, np.float32), out, _st())
+        ref, (_, _, h1, _, h2) = R.forward(flat, X)
+        # BF16 rounding of W2 and h1 (8 significant bits): bound by the
+        # magnitude of the terms, not of the sum
+        scale = (np.abs(h1) @ np.abs(R.unpack(flat)["W2"]) * 1.0) @ np.abs(R.unpack(flat)["W3"])
+        err = np.abs(out.cpu().numpy() - ref)
+        assert np.all(err <= 2 * 2.0 ** -8 * scale + 1e-5), (err.max(), scale.max())
+
+
+def test_colex_unrank_and_select_top():
+    import torch
+    from paper_2502_20072_amd import _binding as B
+    from paper_2502_20072_amd.learned import all_prefixes
+    for m, S in ((1, 9), (2, 30), (3, 25)):
+        pre = all_prefixes(S, m).cpu().numpy()
+        ref = sorted(itertools.combinations(range(S), m), key=lambda t: tuple(reversed(t)))
+        assert [tuple(r) for r in pre] == ref
+    rng = np.random.default_rng(13)
+    sc = rng.normal(size=200000).astype(np.float32)
+    sc[::1000] = np.nan
+    K = 3000
+    d = _t(sc)
+    out = torch.empty(2 * K + 4096, dtype=torch.int64, device="cuda:0")
+    ws = torch.empty(B.sisso_select_workspace_bytes(), dtype=torch.uint8, device="cuda:0")
+    cnt = B.sisso_select_top(d, K, out, ws, _st())
+    got = set(out[:cnt].cpu().numpy().tolist())
+    order = np.argsort(-np.nan_to_num(sc, nan=-np.inf), kind="stable")
+    assert cnt >= K and set(order[:K].tolist()) <= got
+    kth = sc[order[K - 1]]
+    assert all(np.isfinite(sc[i]) and sc[i] >= kth - 2.0 ** -14 * abs(kth) for i in got)
+    assert cnt <= K + 200
+
+
+def _small(seed, S, n, D, T=1):
+    tasks = dict(T=T, lo=n // (2 * T), hi=2 * n // T) if T > 1 else None
+    return make_problem(n=n, S=S, D=D, k=10, seed=seed, beta=(1.5, -0.8, 0.6, -0.4)[:D], sigma=0.1, tasks=tasks)
+
+
+@pytest.mark.parametrize("m,T", [(1, 1), (2, 1), (2, 2), (3, 1)])
+def test_prefix_best_and_features_match_oracle(m, T):
+    import torch
+    from paper_2502_20072_amd import L0Search
+    from paper_2502_20072_amd import _binding as B
+    p = _small(700 + m + 10 * T, S=16, n=120, D=m + 1, T=T)
+    _say(f"prefix best m={m} T={T} S=16")
+    s = L0Search(p.F, p.y, p.task_offsets, D_max=m + 1, k_max=5)
+    s.gram()
+    subsets = list(itertools.combinations(range(p.S), m))
+    rng = np.random.default_rng(m)
+    pick = [subsets[i] for i in rng.choice(len(subsets), size=min(40, len(subsets)), replace=False)]
+    pre = _t(np.array(pick, dtype=np.int32))
+    best = torch.empty(len(pick), dtype=torch.float64, device="cuda:0")
+    feat = torch.empty((len(pick), 8), dtype=torch.float32, device="cuda:0")
+    B.sisso_l0_prefix_best(s.handle, m, pre, best)
+    B.sisso_l0_prefix_features(s.handle, m, pre, feat)
+    best, feat = best.cpu().numpy(), feat.cpu().numpy()
+    s.close()
+    ctot = sum(float(((p.y[a:b] - p.y[a:b].mean()) ** 2).sum())
+               for a, b in zip(p.task_offsets[:-1], p.task_offsets[1:]))
+    for P, bv, fv in zip(pick, best, feat):
+        ref = min(oracle.tuple_sse(p.F, p.y, tuple(sorted(P + (j,))), p.task_offsets)
+                  for j in range(p.S) if j not in P)
+        assert abs(bv - ref) <= 1e-9 * ref, (P, bv, ref)
+        # features against their definitions
+        r2 = np.array([sum(np.corrcoef(p.F[i, a:b], p.y[a:b])[0, 1] ** 2 * ((p.y[a:b] - p.y[a:b].mean()) ** 2).sum()
+                           for a, b in zip(p.task_offsets[:-1], p.task_offsets[1:])) / ctot for i in P])
+        own = 1.0 - oracle.tuple_sse(p.F, p.y, P, p.task_offsets) / ctot
+        G = [max(abs(np.corrcoef(p.F[i, a:b], p.F[j, a:b])[0, 1])
+                 for a, b in zip(p.task_offsets[:-1], p.task_offsets[1:])) for i, j in itertools.combinations(P, 2)]
+        want = [own, r2.max(), r2.min(), r2.mean(), max(G) if G else 0.0, np.mean(G) if G else 0.0,
+                own - r2.max(), 1.0 / m]
+        np.testing.assert_allclose(fv, want, rtol=1e-4, atol=1e-6)
+
+
+def test_search_list_matches_oracle_and_dedupes():
+    import torch
+    from paper_2502_20072_amd import L0Search
+    from paper_2502_20072_amd import _binding as B
+    p = _small(720, S=18, n=150, D=3)
+    _say("search list S=18 D=3")
+    rng = np.random.default_rng(3)
+    pairs = list(itertools.combinations(range(p.S), 2))
+    pick = [pairs[i] for i in rng.choice(len(pairs), size=25, replace=False)]
+    pick += pick[:3]                       # repeated prefixes: repeated tuples
+    s = L0Search(p.F, p.y, p.task_offsets, D_max=3, k_max=30)
+    s.gram()
+    B.sisso_l0_search_list(s.handle, 3, 30, _t(np.array(pick, dtype=np.int32)))
+    s.last_D, s.last_k = 3, 30
+    gi, gs, gc = s.topk()
+    s.close()
+    cand = sorted({tuple(sorted(P + (j,))) for P in pick for j in range(p.S) if j not in P})
+    scored = sorted((oracle.tuple_sse(p.F, p.y, t, p.task_offsets), t) for t in cand)
+    scored = [(v, t) for v, t in scored if np.isfinite(v)][:30]
+    oi = np.array([t for _, t in scored], dtype=np.int32)
+    osse = np.array([v for v, _ in scored])
+    assert len({tuple(t) for t in gi}) == len(gi)
+    compare_topk(p, 3, 30, gi, gs, oi, osse, gcoef=gc)
+
+
+def test_learned_proposal_recall_small():
+    """Train on exhaustive D=2 labels of small problems (pairs -> best
+    triple), propose triples for D=3 problems at a 5% budget, and compare
+    with the exhaustive top-k (itself checked against the oracle)."""
+    import torch
+    from paper_2502_20072_amd import L0Search
+    from paper_2502_20072_amd.learned import ProposalNet, training_set, propose_and_search, r2_scorer, recall
+    train = [make_problem(n=200, S=40, D=3, k=10, seed=9000 + i, beta=(1.5, -0.8, 0.6), sigma=0.1) for i in range(24)]
+    _say("learned proposal: training on 24 problems (S=40, pairs)")
+    X, Y = training_set(train, 2)
+    net = ProposalNet(seed=1)
+    hist = net.fit(X, Y, epochs=15, batch=2048, lr=3e-3)
+    assert hist[-1] < 0.5 * hist[0], hist
+    rec_net, rec_r2 = [], []
+    for seed in (9101, 9102):
+        p = make_problem(n=300, S=70, D=3, k=20, seed=seed, beta=(1.5, -0.8, 0.6), sigma=0.1)
+        s = L0Search(p.F, p.y, p.task_offsets, D_max=3, k_max=20)
+        s.gram().search(3, 20)
+        ei, es, _ = s.topk()
+        oi, osse, _ = oracle.topk(p.F, p.y, 3, 20)
+        compare_topk(p, 3, 20, ei, es, oi, osse)
+        propose_and_search(s, 3, 20, net.predict, budget_frac=0.05)
+        li, ls, _ = s.topk()
+        rec_net.append(recall(li, ei))
+        propose_and_search(s, 3, 20, r2_scorer, budget_frac=0.05)
+        rec_r2.append(recall(s.topk()[0], ei))
+        s.close()
+    _say(f"recall@20 net {rec_net} r2-only {rec_r2}")
+    assert min(rec_net) >= 0.9
