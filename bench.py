@@ -80,6 +80,10 @@ def main() -> int:
                     help="Gram precision form (the search and the re-score are FP64 either way)")
     ap.add_argument("--tune-cache", default=os.environ.get("SISSO_AUTOTUNE_CACHE"),
                     help="JSON cache of the search-grid autotuner (default: tune every run)")
+    ap.add_argument("--form", choices=("exhaustive", "learned"), default="exhaustive",
+                    help="learned: train the proposal network (untimed), then time proposal + exact "
+                         "evaluation against exhaustive search on the same GPU")
+    ap.add_argument("--budget", type=float, default=0.01, help="learned form: fraction of C(S, D) evaluated")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the search shards by "
@@ -99,6 +103,8 @@ def main() -> int:
 
     p = make_config(args.workload)
     D, k = p.D, p.k
+    if args.form == "learned":
+        return bench_learned(args, p)
     ntup = math.comb(p.S, D)
     dev = torch.device("cuda:0")
     print(f"bench: workload={args.workload} n={p.n} S={p.S} T={p.T} D={D} k={k} "
@@ -179,6 +185,82 @@ def main() -> int:
     s.close()
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(p, D, k, args.cpu_seconds)
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+def bench_learned(args, p) -> int:
+    """Learned proposal vs exhaustive search at the workload's D (one GPU).
+
+    Training (not timed): 150 seeded problems with S=200 (every pair, labelled
+    by its best extension: exhaustive D=3 grouped by pair) and 50 with S=60
+    (every triple, exhaustive D=4), n=500, generated like the workload.
+    Timed: the exhaustive search of all C(S, D) tuples, and the proposal
+    (features of every (D-1)-prefix, BF16 network inference, top selection,
+    exact search of the kept prefixes' extensions), each after the Gram.
+    recall@k: |proposal top-k n exhaustive top-k| / k.
+    """
+    import numpy as np
+    import torch
+
+    from synth import make_problem
+    from paper_2502_20072_amd import L0Search
+    from paper_2502_20072_amd.learned import ProposalNet, training_set, propose_and_search, r2_scorer, recall
+
+    D, k = p.D, p.k
+    beta = (1.5, -0.8, 0.6)
+    t0 = time.perf_counter()
+    tr2 = [make_problem(n=500, S=200, D=3, k=10, seed=5000 + i, beta=beta, sigma=0.05) for i in range(150)]
+    tr3 = [make_problem(n=500, S=60, D=4, k=10, seed=5150 + i, beta=beta + (-0.4,), sigma=0.05) for i in range(50)]
+    X2, Y2 = training_set(tr2, 2)
+    X3, Y3 = training_set(tr3, 3)
+    X, Y = torch.cat([X2, X3]), torch.cat([Y2, Y3])
+    net = ProposalNet(seed=0)
+    hist = net.fit(X, Y, epochs=6, batch=8192, lr=2e-3)
+    train_s = time.perf_counter() - t0
+    print(f"bench: trained on {X.shape[0]} prefixes in {train_s:.1f} s, loss {hist[0]:.4f} -> {hist[-1]:.4f}",
+          file=sys.stderr, flush=True)
+
+    s = L0Search(p.F, p.y, p.task_offsets, D_max=D, k_max=k, device="cuda:0")
+    s.gram()
+    s.autotune(D, k, args.tune_cache)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        ev[0].record()
+        for _ in range(reps):
+            fn()
+        ev[1].record()
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]) / reps
+
+    t_exh = timed(lambda: s.search(D, k), max(1, args.steps // 4))
+    ei, es, _ = s.topk()
+    info = {}
+
+    def prop():
+        info.update(propose_and_search(s, D, k, net.predict, budget_frac=args.budget))
+    t_prop = timed(prop, max(1, args.steps // 4))
+    li, ls, _ = s.topk()
+    rec = recall(li, ei)
+    propose_and_search(s, D, k, r2_scorer, budget_frac=args.budget)
+    rec_r2 = recall(s.topk()[0], ei)
+    s.close()
+    ntup = math.comb(p.S, D)
+    res = {
+        "metric": f"l0 tuples/sec at D={D} (learned proposal, exact FP64 evaluation; recall@{k} vs exhaustive)",
+        "value": ntup / (t_prop * 1e-3), "unit": "tuples/s (covered)", "n_gpus": 1, "steps": max(1, args.steps // 4),
+        "warmup": 1, "ms_per_step": t_prop, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 (network: fp32 train, bf16 infer)", "data": "synthetic",
+        "config": {"workload": args.workload, "n": p.n, "S": p.S, "D": D, "k": k, "budget": args.budget,
+                   "form": "learned proposal", **info},
+        f"recall_at_{k}": rec, f"recall_at_{k}_r2_only": rec_r2,
+        "exhaustive_ms": t_exh, "proposal_ms": t_prop, "speedup_vs_exhaustive": t_exh / t_prop,
+        "train": {"prefixes": int(X.shape[0]), "seconds": train_s, "loss_first_epoch": hist[0],
+                  "loss_last_epoch": hist[-1]},
+    }
     print(json.dumps(res), flush=True)
     return 0
 

@@ -52,8 +52,9 @@ int32_t sisso_mlp_backward(const float *params, const float *x, const float *tar
  * 1-based step count) on params with first/second moments m, v. */
 int32_t sisso_mlp_adam(float *params, const float *grad, float *m, float *v, int32_t step, float lr, void *stream);
 
-/* Inference of n samples with the hidden layer on BF16 MFMA (weights and
- * first-layer activations rounded to BF16, FP32 accumulation): out[n]. */
+/* Inference of n samples with both hidden layers on BF16 MFMA (inputs,
+ * W1, W2 and the first layer's activations rounded to BF16, FP32
+ * accumulation, output layer in FP32): out[n]. */
 int32_t sisso_mlp_infer_bf16(const float *params, const float *x, int64_t n, float *out, void *stream);
 
 /* Top-K selection over n scores (larger is better): writes to out[] the

@@ -195,62 +195,105 @@ __global__ void mlp_adam_kernel(float *__restrict__ P, const float *__restrict__
 }
 
 // ---------------------------------------------------- BF16 MFMA inference
-// Block: 64 samples, 4 waves of 16.  The hidden layer runs on
-// v_mfma_f32_16x16x32_bf16 (A: h1 of 16 samples, lane i + 16 (k/8) holds
-// h1[i][k..k+7] of a 32-wide K-step; B: W2 from LDS, transposed so a lane
-// reads 8 consecutive k of one output column; D[i][j] in lane j + 16 (i/4),
-// register i % 4).  Input and output layers run in FP32.
+// Block: 4 waves, persistent over groups of 64 samples (16 per wave).  Both
+// hidden layers run on v_mfma_f32_16x16x32_bf16 (A[i][k] in lane i + 16
+// (k / 8), element k % 8; B[k][j] in lane j + 16 (k / 8); D[i][j] in lane
+// j + 16 (i / 4), register i % 4), the output layer in FP32.
+//  - layer 1 is computed transposed, h1^T = W1^T x^T (inputs padded from 8
+//    to the MFMA's 32), so each lane receives 4 consecutive hidden units of
+//    one sample from each 16-row block;
+//  - layer 2 takes those as its A operand directly: in K-step s, element e
+//    of lane i + 16 g is hidden unit hid(s, g, e) = 32 s + 4 g + e (e < 4) or
+//    32 s + 16 + 4 g + (e - 4) (e >= 4), and W2 is staged in LDS in the same
+//    unit order, so the contraction is over all 128 units exactly once.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
-constexpr int WT = H + 8;  // LDS row stride of the transposed W2 (BF16 elements)
+constexpr int WT = H + 8;  // LDS row stride of the staged W2 (BF16 elements)
+
+__device__ inline int hid_of(int s, int g, int e) { return 32 * s + (e < 4 ? 4 * g + e : 16 + 4 * g + (e - 4)); }
 
 __global__ __launch_bounds__(256) void mlp_infer_bf16_kernel(const float *__restrict__ P, const float *__restrict__ x,
                                                              int64_t n, float *__restrict__ out) {
-    __shared__ __attribute__((aligned(16))) __bf16 w2t[H][WT];
+    __shared__ __attribute__((aligned(16))) __bf16 w2t[H][WT];  // [output j][MFMA k order]
     for (int e = threadIdx.x; e < H * H; e += 256) {
-        const int k = e / H, j = e % H;  // coalesced reads of W2[k][j]
-        w2t[j][k] = (__bf16)P[OW2 + e];
+        const int j = e / H, kk = e % H;  // kk = 32 s + 8 g + el
+        const int s = kk >> 5, g = (kk >> 3) & 3, el = kk & 7;
+        w2t[j][kk] = (__bf16)P[OW2 + hid_of(s, g, el) * H + j];
     }
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t i0 = (int64_t)blockIdx.x * 64 + wave * 16;
-    const int64_t ia = i0 + (lane & 15);  // sample of this lane's A rows
-    float xi[IN];
-#pragma unroll
-    for (int a = 0; a < IN; ++a) xi[a] = ia < n ? x[ia * IN + a] : 0.f;
-    bf16x8 A[H / 32];
+    const int g = lane >> 4, r16 = lane & 15;
+    // layer-1 operands that do not change with the samples: W1^T blocks
+    // (rows = hidden units, k = inputs; only lanes of k-group 0 hold inputs)
+    // and the bias as the accumulator's start value
+    bf16x8 A1[H / 32][2];
+    f32x4 B1init[H / 32][2];
 #pragma unroll
     for (int s = 0; s < H / 32; ++s)
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int k = 32 * s + 8 * (lane >> 4) + e;
-            float z = P[OB1 + k];
+        for (int hf = 0; hf < 2; ++hf) {
+            const int row = 32 * s + 16 * hf + r16;
 #pragma unroll
-            for (int a = 0; a < IN; ++a) z = fmaf(xi[a], P[OW1 + a * H + k], z);
-            A[s][e] = (__bf16)fmaxf(z, 0.f);
+            for (int e = 0; e < 8; ++e) A1[s][hf][e] = (__bf16)(g == 0 && e < IN ? P[OW1 + e * H + row] : 0.f);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) B1init[s][hf][r] = P[OB1 + 32 * s + 16 * hf + 4 * g + r];
         }
-    float part[4] = {0.f, 0.f, 0.f, 0.f};
+    float b2r[H / 16], w3r[H / 16];
 #pragma unroll
     for (int cb = 0; cb < H / 16; ++cb) {
-        const int j = 16 * cb + (lane & 15);
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int s = 0; s < H / 32; ++s) {
-            const bf16x8 B = *reinterpret_cast<const bf16x8 *>(&w2t[j][32 * s + 8 * (lane >> 4)]);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[s], B, acc, 0, 0, 0);
-        }
-        const float b2 = P[OB2 + j], w3 = P[OW3 + j];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) part[r] = fmaf(fmaxf(acc[r] + b2, 0.f), w3, part[r]);
+        b2r[cb] = P[OB2 + 16 * cb + r16];
+        w3r[cb] = P[OW3 + 16 * cb + r16];
     }
+    const float b3 = P[OB3];
+    for (int64_t g0 = (int64_t)blockIdx.x * 64; g0 < n; g0 += (int64_t)gridDim.x * 64) {
+        const int64_t i0 = g0 + wave * 16;
+        // x^T as the B operand: lanes of k-group 0 hold the 8 inputs of sample r16
+        bf16x8 Bx;
+        {
+            const int64_t i = i0 + r16;
+            float4 lo = {0.f, 0.f, 0.f, 0.f}, hi = {0.f, 0.f, 0.f, 0.f};
+            if (g == 0 && i < n) {
+                lo = reinterpret_cast<const float4 *>(x + i * IN)[0];
+                hi = reinterpret_cast<const float4 *>(x + i * IN)[1];
+            }
+            Bx[0] = (__bf16)lo.x; Bx[1] = (__bf16)lo.y; Bx[2] = (__bf16)lo.z; Bx[3] = (__bf16)lo.w;
+            Bx[4] = (__bf16)hi.x; Bx[5] = (__bf16)hi.y; Bx[6] = (__bf16)hi.z; Bx[7] = (__bf16)hi.w;
+        }
+        bf16x8 A2[H / 32];
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-        for (int m = 8; m >= 1; m >>= 1) part[r] += __shfl_xor(part[r], m);  // over the 16 columns of a lane row
-    if ((lane & 15) == 0) {
+        for (int s = 0; s < H / 32; ++s)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int64_t i = i0 + 4 * (lane >> 4) + r;
-            if (i < n) out[i] = part[r] + P[OB3];
+            for (int hf = 0; hf < 2; ++hf) {
+                f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1[s][hf], Bx, B1init[s][hf], 0, 0, 0);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) A2[s][4 * hf + r] = (__bf16)fmaxf(acc[r], 0.f);
+            }
+        // eight independent accumulators, K-steps outermost, so consecutive
+        // MFMAs do not wait on each other
+        f32x4 acc[H / 16];
+#pragma unroll
+        for (int cb = 0; cb < H / 16; ++cb) acc[cb] = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < H / 32; ++s)
+#pragma unroll
+            for (int cb = 0; cb < H / 16; ++cb) {
+                const bf16x8 Bw = *reinterpret_cast<const bf16x8 *>(&w2t[16 * cb + r16][32 * s + 8 * g]);
+                acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A2[s], Bw, acc[cb], 0, 0, 0);
+            }
+        float part[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int cb = 0; cb < H / 16; ++cb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) part[r] = fmaf(fmaxf(acc[cb][r] + b2r[cb], 0.f), w3r[cb], part[r]);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            for (int m = 8; m >= 1; m >>= 1) part[r] += __shfl_xor(part[r], m);  // over the 16 columns of a row
+        if (r16 == 0) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t i = i0 + 4 * g + r;
+                if (i < n) out[i] = part[r] + b3;
+            }
         }
     }
 }
@@ -316,12 +359,19 @@ __global__ void sel_threshold_kernel(const unsigned int *__restrict__ hist, int6
 __global__ void sel_compact_kernel(const float *__restrict__ sc, int64_t n, SelState *__restrict__ st,
                                    uint64_t *__restrict__ out, int64_t cap) {
     const uint32_t thr = st->thr;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const float f = sc[i];
-        if (f == f && okey(f) >= thr) {
-            const unsigned long long at = atomicAdd(&st->count, 1ull);
-            if ((int64_t)at < cap) out[at] = (uint64_t)i;
-        }
+    const int lane = threadIdx.x & 63;
+    // one atomic per wave: the selected lanes take consecutive slots
+    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < n; i0 += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = i0 + threadIdx.x;
+        const float f = i < n ? sc[i] : __builtin_nanf("");
+        const bool take = f == f && okey(f) >= thr;
+        const unsigned long long m = __ballot(take);
+        if (!m) continue;
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(&st->count, (unsigned long long)__popcll(m));
+        base = __shfl(base, 0);
+        const unsigned long long at = base + __popcll(m & ((1ull << lane) - 1ull));
+        if (take && (int64_t)at < cap) out[at] = (uint64_t)i;
     }
 }
 
@@ -387,8 +437,9 @@ extern "C" int32_t sisso_mlp_adam(float *params, const float *grad, float *m, fl
 
 extern "C" int32_t sisso_mlp_infer_bf16(const float *params, const float *x, int64_t n, float *out, void *stream) {
     if (!params || !x || !out || n < 1) return SISSO_EINVAL;
-    hipLaunchKernelGGL(mlp_infer_bf16_kernel, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, (hipStream_t)stream,
-                       params, x, n, out);
+    const int64_t groups = (n + 63) / 64;
+    hipLaunchKernelGGL(mlp_infer_bf16_kernel, dim3((unsigned)(groups < 1024 ? groups : 1024)), dim3(256), 0,
+                       (hipStream_t)stream, params, x, n, out);
     return launched();
 }
 

@@ -91,6 +91,35 @@ __device__ inline double Gat(const Ctx &c, int64_t i, int64_t k, int t) {
 // pivot is <= RANK_EPS in some task.  Used by the threshold pre-pass.  All
 // entries a task needs are loaded before any arithmetic, so the loads of one
 // call overlap instead of forming a chain.
+// SSE of one task from its tuple's correlation block g (lower triangle,
+// sorted-index order), b and c = |y_c|^2; clears ok on a pivot <= RANK_EPS.
+template <int D>
+__device__ inline double ne_sse_core(const double (&g)[D][D], const double (&bv)[D], double cyy, bool &ok) {
+    double L[D][D], z[D];
+    double p = cyy;
+#pragma unroll
+    for (int m = 0; m < D; ++m) {
+#pragma unroll
+        for (int j = 0; j < m; ++j) {
+            double s = g[m][j];
+#pragma unroll
+            for (int l = 0; l < j; ++l) s -= L[m][l] * L[j][l];
+            L[m][j] = s / L[j][j];
+        }
+        double d = g[m][m];
+#pragma unroll
+        for (int l = 0; l < m; ++l) d -= L[m][l] * L[m][l];
+        ok &= d > RANK_EPS;
+        L[m][m] = sqrt(fmax(d, RANK_EPS));
+        double zm = bv[m];
+#pragma unroll
+        for (int l = 0; l < m; ++l) zm -= L[m][l] * z[l];
+        z[m] = zm / L[m][m];
+        p -= z[m] * z[m];
+    }
+    return p;
+}
+
 template <int D>
 __device__ double ne_sse_t(const Ctx &c, const int32_t *tup) {
     double total = 0.0;
@@ -103,29 +132,7 @@ __device__ double ne_sse_t(const Ctx &c, const int32_t *tup) {
             for (int j = 0; j <= m; ++j) g[m][j] = Gat(c, tup[m], tup[j], t);
             bv[m] = c.bhat[(int64_t)tup[m] * c.TP + t];
         }
-        double L[D][D], z[D];
-        double p = c.cyy[t];
-#pragma unroll
-        for (int m = 0; m < D; ++m) {
-#pragma unroll
-            for (int j = 0; j < m; ++j) {
-                double s = g[m][j];
-#pragma unroll
-                for (int l = 0; l < j; ++l) s -= L[m][l] * L[j][l];
-                L[m][j] = s / L[j][j];
-            }
-            double d = g[m][m];
-#pragma unroll
-            for (int l = 0; l < m; ++l) d -= L[m][l] * L[m][l];
-            ok &= d > RANK_EPS;
-            L[m][m] = sqrt(fmax(d, RANK_EPS));
-            double zm = bv[m];
-#pragma unroll
-            for (int l = 0; l < m; ++l) zm -= L[m][l] * z[l];
-            z[m] = zm / L[m][m];
-            p -= z[m] * z[m];
-        }
-        total += p;
+        total += ne_sse_core<D>(g, bv, c.cyy[t], ok);
     }
     return ok ? total : INF;
 }
@@ -176,6 +183,30 @@ __device__ void list_insert(double *Ls, uint64_t *Lr, int KP, double s, uint64_t
     }
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     __builtin_amdgcn_wave_barrier();
+}
+
+// Sorts a wave's LDS list of KP (power of two) entries by (SSE, key).
+__device__ void wave_sort_list(double *Ls, uint64_t *Lr, int KP) {
+    const int lane = threadIdx.x & 63;
+    for (int k = 2; k <= KP; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = lane; i < KP; i += 64) {
+                const int ixj = i ^ j;
+                if (ixj > i) {
+                    const bool up = (i & k) == 0;
+                    const double a = Ls[i], b = Ls[ixj];
+                    const uint64_t ra = Lr[i], rb = Lr[ixj];
+                    if (key_less(b, rb, a, ra) == up) {
+                        Ls[i] = b;
+                        Ls[ixj] = a;
+                        Lr[i] = rb;
+                        Lr[ixj] = ra;
+                    }
+                }
+            }
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            __builtin_amdgcn_wave_barrier();
+        }
 }
 
 // ------------------------------------------------------------ init kernel
@@ -481,7 +512,7 @@ __device__ inline double slow_path(const Ctx &c, const SearchArgs &a, double *Ls
                                          const double *recs, const double *subf, const int32_t *sub,
                                          const unsigned long long *smask, int64_t j, int jj, int64_t k,
                                          bool kin, bool flagged, int myt, int TL, double theta_f,
-                                         double theta_pub) {
+                                         double theta_pub, unsigned &offered) {
     constexpr int q = D - 2;
     constexpr int QA = q > 0 ? q : 1;
     constexpr int RECW = q + 4;
@@ -526,7 +557,7 @@ __device__ inline double slow_path(const Ctx &c, const SearchArgs &a, double *Ls
             }
         }
         unsigned long long m = __ballot(take);
-        if (m && lane == 0) atomicAdd(c.cand_counter, (unsigned)__popcll(m));
+        offered += (unsigned)__popcll(m);
         while (m) {
             const int src = __ffsll((long long)m) - 1;
             m &= m - 1;
@@ -575,6 +606,7 @@ __global__ __launch_bounds__(256) void search_kernel(Ctx c, SearchArgs a) {
         Lr[m] = ~0ull;
     }
     double theta_pub = INF;  // last value this wave published
+    unsigned offered = 0;    // tuples offered to the list (diagnostics; one atomic per wave)
     const double theta0 = theta0_from_prepass(c, a.L, KP);
 
     const int TL = MT ? a.TL : 1;         // lanes per last index
@@ -880,11 +912,12 @@ __global__ __launch_bounds__(256) void search_kernel(Ctx c, SearchArgs a) {
                 const int jj = qj[e];
                 const unsigned long long lm = qmask[e];
                 theta_pub = slow_path<D, NR, MT>(c, a, Ls, Lr, recs, subf, &s_sub[0][0], s_mask, j0 + jj, jj, k,
-                                                 kin, (lm >> lane) & 1ull, myt, TL, theta_f, theta_pub);
+                                                 kin, (lm >> lane) & 1ull, myt, TL, theta_f, theta_pub, offered);
             }
         }
         __syncthreads();
     }
+    if (lane == 0 && offered) atomicAdd(c.cand_counter, offered);
     // write this wave's list
     const int64_t gw = (int64_t)blockIdx.x * SEARCH_WAVES + wave;
     for (int m = lane; m < KP; m += 64) {
@@ -1007,23 +1040,132 @@ __global__ __launch_bounds__(256) void list_search_kernel(Ctx c, const int32_t *
         Lr[m] = ~0ull;
     }
     double theta_pub = INF;
+    int fill = 0;  // entries appended while the list is filling (sorted once full)
+    unsigned offered = 0;  // tuples offered to the list (diagnostics; one atomic per wave)
     const int64_t gw = (int64_t)blockIdx.x * SEARCH_WAVES + wave;
     const int64_t nw = (int64_t)gridDim.x * SEARCH_WAVES;
     for (int64_t p = gw; p < n; p += nw) {
         int32_t P[M];
         if (!load_prefix<M>(c, pre, p, P)) continue;
+        // one task: the prefix's own factor (uniform) turns each extension
+        // into an incremental filter (w = L^-1 G[P,k], d = G[k,k] - |w|^2,
+        // SSE ~ p - zeta^2 / d); only extensions that pass it (or whose pivot
+        // is too small to judge) are scored canonically
+        double L[M][M], z[M], pp = 0.0;
+        double gP[M][M], bP[M];  // the prefix's own correlation block and b (one task)
+        bool pok = false;
+        if (c.T == 1) {
+            pp = c.cyy[0];
+            pok = true;
+#pragma unroll
+            for (int a = 0; a < M; ++a) {
+                bP[a] = c.bhat[(int64_t)P[a] * c.TP];
+#pragma unroll
+                for (int b2 = 0; b2 <= a; ++b2) gP[a][b2] = Gat(c, P[a], P[b2], 0);
+            }
+#pragma unroll
+            for (int a = 0; a < M; ++a) {
+#pragma unroll
+                for (int b2 = 0; b2 < a; ++b2) {
+                    double v = gP[a][b2];
+#pragma unroll
+                    for (int l = 0; l < b2; ++l) v -= L[a][l] * L[b2][l];
+                    L[a][b2] = v / L[b2][b2];
+                }
+                double d = gP[a][a];
+#pragma unroll
+                for (int l = 0; l < a; ++l) d -= L[a][l] * L[a][l];
+                pok &= d > RANK_EPS;
+                L[a][a] = sqrt(fmax(d, RANK_EPS));
+                double zz = bP[a];
+#pragma unroll
+                for (int l = 0; l < a; ++l) zz -= L[a][l] * z[l];
+                z[a] = zz / L[a][a];
+                pp -= z[a] * z[a];
+            }
+        }
+        // the device-wide bound is read once per prefix (a memory round trip)
+        const double th_dev = theta_load(c.theta_bits);
         for (int64_t kb = 0; kb < c.S; kb += 64) {
             const int64_t k = kb + lane;
             double sse = INF;
             uint64_t key = ~0ull;
             int32_t tup[M + 1];
-            if (k < c.S && extend_sorted<M>(P, (int32_t)k, tup)) {
+            const double th = fmin(Ls[KP - 1], th_dev);
+            bool score = k < c.S && extend_sorted<M>(P, (int32_t)k, tup);
+            if (score && c.T == 1) {
+                const int64_t kc = k;
+                double gk[M];
+#pragma unroll
+                for (int a = 0; a < M; ++a) gk[a] = Gat(c, P[a], kc, 0);
+                const double gkk = Gat(c, kc, kc, 0), bk = c.bhat[kc * c.TP];
+                if (pok) {
+                    double w[M], ww = 0.0, wz = 0.0;
+#pragma unroll
+                    for (int a = 0; a < M; ++a) {
+                        double v = gk[a];
+#pragma unroll
+                        for (int l = 0; l < a; ++l) v -= L[a][l] * w[l];
+                        w[a] = v / L[a][a];
+                        ww += w[a] * w[a];
+                        wz += w[a] * z[a];
+                    }
+                    const double d = gkk - ww;
+                    const double zeta = bk - wz;
+                    const double inc = d > 1e3 * RANK_EPS ? pp - zeta * zeta / d : -INF;
+                    score = inc <= (th < INF ? th * (1.0 + 1e-8) + 1e-12 * c.cyy[0] : INF);
+                }
+                // (a tiny pivot in the prefix's own order says nothing certain about
+                // the tuple's sorted order: such extensions are scored canonically)
+                if (score) {
+                    // canonical: the tuple's block in sorted-index order, from the
+                    // values already loaded (G is bitwise symmetric)
+                    int pos = 0;
+#pragma unroll
+                    for (int a = 0; a < M; ++a) pos += P[a] < kc;
+                    double g4[M + 1][M + 1], b4[M + 1];
+#pragma unroll
+                    for (int u = 0; u <= M; ++u) {
+                        const int au = u < pos ? u : u - 1;  // prefix slot of tuple slot u (u != pos)
+                        b4[u] = u == pos ? bk : bP[au];
+#pragma unroll
+                        for (int v2 = 0; v2 <= u; ++v2) {
+                            const int av = v2 < pos ? v2 : v2 - 1;
+                            double val;
+                            if (u == pos && v2 == pos) val = gkk;
+                            else if (u == pos) val = gk[av];
+                            else if (v2 == pos) val = gk[au];
+                            else val = gP[au][av];
+                            g4[u][v2] = val;
+                        }
+                    }
+                    bool ok = true;
+                    const double v = ne_sse_core<M + 1>(g4, b4, c.cyy[0], ok);
+                    sse = ok ? v : INF;
+                    key = pack_tuple(tup, M + 1);
+                }
+            } else if (score) {
                 sse = ne_sse_t<M + 1>(c, tup);
                 key = pack_tuple(tup, M + 1);
             }
-            const double th = fmin(Ls[KP - 1], theta_load(c.theta_bits));
             unsigned long long m = __ballot(sse < INF && sse <= th);
-            if (m && lane == 0) atomicAdd(c.cand_counter, (unsigned)__popcll(m));
+            offered += (unsigned)__popcll(m);
+            if (fill < KP && m) {
+                // the list is not full: append (one slot per passing lane), and
+                // sort once it is
+                const int rank = __popcll(m & ((1ull << lane) - 1ull));
+                const int nfit = min(__popcll(m), KP - fill);
+                const bool mine = ((m >> lane) & 1ull) && rank < nfit;
+                if (mine) {
+                    Ls[fill + rank] = sse;
+                    Lr[fill + rank] = key;
+                }
+                __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                __builtin_amdgcn_wave_barrier();
+                m &= ~__ballot(mine);
+                fill += nfit;
+                if (fill == KP) wave_sort_list(Ls, Lr, KP);
+            }
             while (m) {
                 const int src = __ffsll((long long)m) - 1;
                 m &= m - 1;
@@ -1036,6 +1178,8 @@ __global__ __launch_bounds__(256) void list_search_kernel(Ctx c, const int32_t *
             }
         }
     }
+    if (fill < KP) wave_sort_list(Ls, Lr, KP);  // unused slots hold +inf and sort last
+    if (lane == 0 && offered) atomicAdd(c.cand_counter, offered);
     for (int m = lane; m < KP; m += 64) {
         c.list_sse[gw * KP + m] = Ls[m];
         c.list_rank[gw * KP + m] = Lr[m];

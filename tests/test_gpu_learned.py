@@ -76,12 +76,15 @@ def test_bf16_inference_close_to_fp64():
         _say(f"bf16 inference n={n}")
         out = torch.empty(n, dtype=torch.float32, device="cuda:0")
         B.sisso_mlp_infer_bf16(_t(flat, np.float32), _t(X, np.float32), out, _st())
-        ref, (_, _, h1, _, h2) = R.forward(flat, X)
-        # BF16 rounding of W2 and h1 (8 significant bits): bound by the
-        # magnitude of the terms, not of the sum
-        scale = (np.abs(h1) @ np.abs(R.unpack(flat)["W2"]) * 1.0) @ np.abs(R.unpack(flat)["W3"])
+        ref, _ = R.forward(flat, X)
+        # BF16 rounding (8 significant bits, relative error <= 2^-8) of x, W1,
+        # h1 and W2: with M the same network evaluated on absolute values
+        # (no cancellation, relu never cutting), |error| <= 4 * 2^-8 * M
+        pa = R.unpack(flat)
+        h1m = np.abs(X) @ np.abs(pa["W1"]) + np.abs(pa["b1"])
+        M = (h1m @ np.abs(pa["W2"]) + np.abs(pa["b2"])) @ np.abs(pa["W3"])
         err = np.abs(out.cpu().numpy() - ref)
-        assert np.all(err <= 2 * 2.0 ** -8 * scale + 1e-5), (err.max(), scale.max())
+        assert np.all(err <= 4 * 2.0 ** -8 * M + 1e-5), (err.max(), M.max())
 
 
 def test_colex_unrank_and_select_top():
@@ -203,3 +206,28 @@ def test_learned_proposal_recall_small():
         s.close()
     _say(f"recall@20 net {rec_net} r2-only {rec_r2}")
     assert min(rec_net) >= 0.9
+
+
+def test_c5_exhaustive_sampled_parity():
+    """The judge of recall at the learned-proposal shape (n=2000, S=600, D=4,
+    k=100): every returned SSE is the oracle's, the planted tuple is first,
+    and no sampled tuple beats the k-th result (5.3e9 tuples are beyond the
+    oracle)."""
+    from synth import make_config
+    from paper_2502_20072_amd import L0Search
+    p = make_config("learned_s600_d4")
+    _say("c5 exhaustive D=4 n=2000 S=600")
+    s = L0Search(p.F, p.y, p.task_offsets, D_max=4, k_max=100)
+    s.gram().search(4, 100)
+    gi, gs, _ = s.topk(with_coef=False)
+    s.close()
+    assert tuple(int(v) for v in gi[0]) == tuple(sorted(int(v) for v in p.planted))
+    for t, v in zip(gi, gs):
+        ref = oracle.tuple_sse(p.F, p.y, tuple(int(x) for x in t))
+        assert abs(v - ref) <= 1e-10 * ref
+    rng = np.random.default_rng(17)
+    top = {tuple(int(x) for x in t) for t in gi}
+    for _ in range(300):
+        t = tuple(sorted(int(x) for x in rng.choice(p.S, size=4, replace=False)))
+        if t not in top:
+            assert oracle.tuple_sse(p.F, p.y, t) >= gs[-1] * (1 - 1e-9)
