@@ -98,6 +98,8 @@ static Layout compute_layout(int64_t n_total, int64_t S, int T, int D_max, int k
     L.pre = take(64 + (size_t)(S / 4 + 8) * sizeof(uint64_t) + PRE_Q * SISSO_MAX_D * sizeof(int32_t) +
                  64 + (size_t)PRE_Q * S * d + PRE_Q * d + 1024 +
                  (size_t)(SISSO_MAX_D + 1) * (S + 1) * sizeof(uint64_t) + 256);
+    L.rec3_bytes = (D_max >= 3 && T == 1) ? (size_t)((S + 3) / 4) * S * 16 * d : 0;
+    L.rec3 = take(L.rec3_bytes);
     L.lists = take((size_t)nlists * L.KP * 2 * d + (size_t)nlists * L.KP * 2 * d);
     L.merged = take((size_t)L.KP * 2 * d);
     L.rescored = take((size_t)L.KP * d);
@@ -164,6 +166,7 @@ static void carve(sisso_l0 *h) {
     c.pre_sse = (double *)p;
     p += align256((size_t)PRE_Q * c.S * sizeof(double));
     c.btab = (uint64_t *)p;
+    c.rec3 = L.rec3_bytes ? (double *)(base + L.rec3) : nullptr;
     const int64_t nl = L.nwaves;
     char *q = base + L.lists;
     c.list_sse = (double *)q;

@@ -31,6 +31,7 @@ struct Ctx {
     int32_t *pre_count;              // pre-pass: number of chosen prefixes
     double *pre_sse;                 // pre-pass: extension scores [PRE_Q][S]
     double *pre_bound;               // pre-pass: per-prefix L-th best [PRE_Q]
+    double *rec3;                    // D = 3, one task: pair records [ceil(S/4)][S][4][4] (null if absent)
     double *list_sse;                // per-wave lists [nwaves][KP]
     uint64_t *list_rank;
     double *cand_sse;                // merge: compacted candidates [nwaves * KP]

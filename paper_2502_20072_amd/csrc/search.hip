@@ -214,7 +214,9 @@ __device__ void wave_sort_list(double *Ls, uint64_t *Lr, int KP) {
 // of work items per j-block: block jb covers j in [JB*jb, N_jb) with
 // N_jb = min(JB*(jb+1), S-1); its sub-prefixes are the q-combinations of
 // {0..N_jb-2}, grouped R at a time.
-__global__ void search_init_kernel(Ctx c, int D, int R, int JB) {
+__device__ void s3_tile_table(const Ctx &c);
+
+__global__ void search_init_kernel(Ctx c, int D, int R, int JB, int s3) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e < (int64_t)(SISSO_MAX_D + 1) * (c.S + 1)) {
         const int r = (int)(e / (c.S + 1));
@@ -228,6 +230,10 @@ __global__ void search_init_kernel(Ctx c, int D, int R, int JB) {
         *c.pre_count = 0;
         *c.merge_count = 0;
         c.stats[1] = 0;
+        if (s3) {
+            s3_tile_table(c);
+            return;
+        }
         const int q = D - 2;
         const int64_t nblk = (c.S - 1 + JB - 1) / JB;
         uint64_t acc = 0;
@@ -926,6 +932,339 @@ __global__ __launch_bounds__(256) void search_kernel(Ctx c, SearchArgs a) {
     }
 }
 
+// ------------------------------------------- D = 3, one task: record table
+// With one task and D = 3 the Cholesky row of every pair (i1, j) is built
+// once per search into a table (rec3_kernel), and the sweep reads the rows
+// of four consecutive i1 for one j with scalar loads: lanes run over the
+// last index k, so a record is the same for every lane and enters the FP64
+// instructions as a scalar operand, at no LDS or vector-memory cost.  Each
+// lane handles two adjacent k (one 16-byte load of G[j][k..k+1] serves
+// 2 x 4 tuples).  A work tile is (group of four i1, S3_JR rows j, S3_KC
+// columns k); tiles are dealt to single waves round-robin, so no wave waits
+// on another.  Per tuple the arithmetic is the same as search_kernel's
+// single-task path: u = g - v w', d = d' - alpha u^2, zeta = zeta' - zs u,
+// pass iff zeta^2 >= (p - theta) d.
+constexpr int S3_NR = 4;              // i1 per tile (a group)
+constexpr int S3_KC = 128;            // k per tile: two adjacent per lane
+#ifndef S3_JR
+#define S3_JR 32                      // j rows per tile (divides 64)
+#endif
+#ifndef S3_JG
+#define S3_JG 2                       // G rows per prefetch group (two groups in flight)
+#endif
+
+// record of (i1, j), i1 = S3_NR g + r:
+//   rec[((g S + j) S3_NR + r) 4 + {0, 1, 2, 3}] = {v, 1/d_j, z_j / s_j, p}
+// with v = G[i1][j], d_j = 1 - v^2, s_j = sqrt(d_j), z_j = (b_j - v b_i1) / s_j,
+// p = c - b_i1^2 - z_j^2 (the SSE of the pair); p = NaN (fails every
+// comparison) unless i1 < j, column i1 is live and d_j > RANK_EPS.
+__global__ __launch_bounds__(256) void rec3_kernel(Ctx c, double *__restrict__ rec) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t S = c.S;
+    const int64_t ng = (S + S3_NR - 1) / S3_NR;
+    if (e >= ng * S * S3_NR) return;
+    const int r = (int)(e % S3_NR);
+    const int64_t gj = e / S3_NR;
+    const int64_t j = gj % S;
+    const int64_t i1 = (gj / S) * S3_NR + r;
+    double v = 0.0, al = 0.0, zs = 0.0, p = __builtin_nan("");
+    if (i1 < j && Gat(c, i1, i1, 0) > RANK_EPS) {
+        const double zp = c.bhat[i1 * c.TP];
+        const double pp = c.cyy[0] - zp * zp;
+        const double g = Gat(c, i1, j, 0);
+        const double d = Gat(c, j, j, 0) - g * g;
+        if (d > RANK_EPS) {
+            const double sj = sqrt(d);
+            const double zn = (c.bhat[j * c.TP] - g * zp) / sj;
+            v = g;
+            al = 1.0 / d;
+            zs = zn / sj;
+            p = pp - zn * zn;
+        }
+    }
+    double *o = rec + e * 4;
+    o[0] = v;
+    o[1] = al;
+    o[2] = zs;
+    o[3] = p;
+}
+
+// Tiles of j-block jb (j in [S3_JR jb, S3_JR jb + S3_JR) and j <= S - 2):
+// column chunks kc >= kc0 (the chunk reaches past the block's first j) times
+// groups g < ng (the group's first i1 lies below the block's last j).
+__host__ __device__ inline void s3_block(int64_t S, int64_t jb, int64_t &kc0, int64_t &ng) {
+    const int64_t j0 = jb * S3_JR;
+    int64_t jmax = j0 + S3_JR - 1;
+    if (jmax > S - 2) jmax = S - 2;
+    kc0 = (j0 + 1) / S3_KC;
+    ng = jmax >= 1 ? (jmax - 1) / S3_NR + 1 : 0;
+}
+__host__ __device__ inline int64_t s3_nblocks(int64_t S) { return S >= 3 ? (S - 2) / S3_JR + 1 : 0; }
+__host__ __device__ inline int64_t s3_nchunks(int64_t S) { return (S + S3_KC - 1) / S3_KC; }
+
+// tcum[jb] = tiles of the blocks before jb (tcum[nblocks] = all tiles)
+__device__ void s3_tile_table(const Ctx &c) {
+    const int64_t nb = s3_nblocks(c.S), nkc = s3_nchunks(c.S);
+    uint64_t acc = 0;
+    c.cum[0] = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+        int64_t kc0, ng;
+        s3_block(c.S, b, kc0, ng);
+        acc += (uint64_t)((nkc - kc0) * ng);
+        c.cum[b + 1] = acc;
+    }
+    c.stats[1] = acc;
+}
+
+uint64_t s3_tiles_host(int64_t S) {
+    const int64_t nb = s3_nblocks(S), nkc = s3_nchunks(S);
+    uint64_t acc = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+        int64_t kc0, ng;
+        s3_block(S, b, kc0, ng);
+        acc += (uint64_t)((nkc - kc0) * ng);
+    }
+    return acc;
+}
+
+#ifndef S3_WPE
+#define S3_WPE 4                      // waves per SIMD the register budget is sized for
+#endif
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S3_WPE))) void search3_kernel(Ctx c, SearchArgs a, const double *__restrict__ rec,
+                                                      const uint64_t *__restrict__ tcum) {
+    extern __shared__ double smem[];
+    __shared__ unsigned long long s_q[SEARCH_WAVES][S3_JR][2];
+    __shared__ int s_qj[SEARCH_WAVES][S3_JR];
+    const int KP = a.KP;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    double *Ls = smem + (size_t)wave * KP * 2;
+    uint64_t *Lr = reinterpret_cast<uint64_t *>(Ls + KP);
+    for (int m = lane; m < KP; m += 64) {
+        Ls[m] = INF;
+        Lr[m] = ~0ull;
+    }
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_wave_barrier();
+    double theta_pub = INF;
+    unsigned offered = 0;
+    const double theta0 = theta0_from_prepass(c, a.L, KP);
+    const int64_t S = c.S;
+    const int64_t nb = s3_nblocks(S);
+    const uint64_t ntiles = tcum[nb];
+    const int64_t nt = c.Gnt;
+    const double *__restrict__ Gb = c.G;
+    const int TP = c.TP;
+
+    // tiles are dealt round-robin over the waves: their costs are nearly
+    // equal, and a shared counter would serialise on one address
+    for (uint64_t t = (uint64_t)blockIdx.x * SEARCH_WAVES + wave;; t += (uint64_t)gridDim.x * SEARCH_WAVES) {
+        if (t >= ntiles) break;
+        // tile -> (j-block, column chunk, group)
+        int64_t lo = 0, hi = nb - 1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (tcum[mid] <= t) lo = mid; else hi = mid - 1;
+        }
+        const int64_t jb = lo;
+        int64_t kc0, ng;
+        s3_block(S, jb, kc0, ng);
+        // column chunk fastest: the four waves of a workgroup usually take
+        // four chunks of one (block, group) and share its records in the
+        // scalar cache
+        const int64_t nkb = s3_nchunks(S) - kc0;
+        const int64_t rem = (int64_t)(t - tcum[jb]);
+        const int64_t kcx = kc0 + rem % nkb;
+        const int64_t g = rem / nkb;
+        const int64_t j0 = jb * S3_JR;
+        const int64_t jlo = j0 > S3_NR * g + 1 ? j0 : S3_NR * g + 1;
+        const int64_t jhi = (j0 + S3_JR - 1 < S - 2) ? j0 + S3_JR - 1 : S - 2;
+        const int nrow = (int)(jhi - jlo);  // steps 0..nrow
+        const int64_t kb = kcx * S3_KC;
+        const int64_t k0 = kb + 2 * lane, k1 = k0 + 1;
+        const bool kv0 = k0 < S, kv1 = k1 < S;
+        // even column < S: the pair (kk, kk + 1) lies inside the padded tile row
+        const int64_t kk = kv0 ? k0 : ((S - 1) & ~(int64_t)1);
+        const bool diag = kb <= jhi;
+
+        double th = fmin(theta0, theta_load(c.theta_bits));
+        th = fmin(th, Ls[KP - 1]);
+        const double theta_f = th < INF ? th * (1.0 + THETA_SLACK) : INF;
+
+        // k-dependent part of each i1's solve, for both columns of the lane
+        double w[S3_NR][2], dq[S3_NR][2], zq[S3_NR][2];
+        {
+            // G[k][k] is 1 for a live column and 0 for a constant one; the
+            // contiguous 1/|x - mean| row says which (0 = constant)
+            const int64_t kd1 = kv1 ? k1 : kk;
+            const double gd0 = c.inv_s[kk] > 0.0 ? 1.0 : 0.0;
+            const double gd1 = c.inv_s[kd1] > 0.0 ? 1.0 : 0.0;
+            const double b0 = c.bhat[kk * TP], b1 = c.bhat[kd1 * TP];
+#pragma unroll
+            for (int r = 0; r < S3_NR; ++r) {
+                int64_t i1 = S3_NR * g + r;
+                if (i1 > S - 1) i1 = S - 1;
+                const double zp = c.bhat[i1 * TP];
+                const double2 wv = *reinterpret_cast<const double2 *>(Gb + gidx(i1, kk, nt, 1, 0));
+                w[r][0] = wv.x;
+                w[r][1] = wv.y;
+                // a lane past S or on a constant column never passes
+                dq[r][0] = (kv0 && gd0 > RANK_EPS) ? gd0 - wv.x * wv.x : __builtin_nan("");
+                dq[r][1] = (kv1 && gd1 > RANK_EPS) ? gd1 - wv.y * wv.y : __builtin_nan("");
+                zq[r][0] = b0 - wv.x * zp;
+                zq[r][1] = b1 - wv.y * zp;
+            }
+        }
+        // G[j][kk..kk+1] for the block's rows: j >> 6 is the same for the whole
+        // block (S3_JR divides 64), so one uniform tile-row base plus a 32-bit
+        // per-lane byte offset (column part + row j & 63) addresses every step
+        const char *__restrict__ gtile =
+            reinterpret_cast<const char *>(Gb + (((j0 >> 6) * nt) << 12));
+        const uint32_t voff = (uint32_t)((((kk >> 6) << 12) + (kk & 63) + ((jlo & 63) << 6)) * 8);
+        // records of row jlo + x are 128 bytes at recj + 128 x (uniform)
+        const char *__restrict__ recj = reinterpret_cast<const char *>(rec + (size_t)(g * S + jlo) * (S3_NR * 4));
+        int nq = 0;
+        auto sweep = [&](auto diagc) {
+            constexpr bool DIAG = decltype(diagc)::value;
+            constexpr int JG = S3_JG;
+            double2 ga[JG], gb[JG];
+            auto fetch = [&](double2 (&dst)[JG], int jg) {
+#pragma unroll
+                for (int x = 0; x < JG; ++x) {
+                    const uint32_t jr = (uint32_t)(jg + x < nrow ? jg + x : nrow);
+                    dst[x] = *reinterpret_cast<const double2 *>(gtile + (voff + jr * 512u));
+                }
+            };
+            // records of one step are two halves of 64 bytes (i1 = 4g, 4g+1 and
+            // 4g+2, 4g+3); each half is loaded while the other is scored.  Scalar
+            // loads may return out of order, so the half in flight is waited for
+            // (lgkmcnt(0)) before the next one is issued.
+            auto load_half = [&](double (&rv)[8], int jr, int h) {
+                const double *rp = reinterpret_cast<const double *>(recj + (size_t)jr * 128 + h * 64);
+#pragma unroll
+                for (int e = 0; e < 8; ++e) rv[e] = rp[e];
+            };
+            auto score_half = [&](const double (&rv)[8], const double2 gv, int h, unsigned long long &m0,
+                                  unsigned long long &m1) {
+#pragma unroll
+                for (int rr = 0; rr < 2; ++rr) {
+                    const int r = 2 * h + rr;
+                    const double pi = rv[4 * rr + 3] - theta_f;
+                    {
+                        const double u = fma(-rv[4 * rr], w[r][0], gv.x);
+                        const double d = fma(-rv[4 * rr + 1], u * u, dq[r][0]);
+                        const double z = fma(-rv[4 * rr + 2], u, zq[r][0]);
+                        m0 |= __ballot(z * z >= pi * d);
+                    }
+                    {
+                        const double u = fma(-rv[4 * rr], w[r][1], gv.y);
+                        const double d = fma(-rv[4 * rr + 1], u * u, dq[r][1]);
+                        const double z = fma(-rv[4 * rr + 2], u, zq[r][1]);
+                        m1 |= __ballot(z * z >= pi * d);
+                    }
+                }
+            };
+            double ra[8], rb[8];
+            load_half(ra, 0, 0);
+            auto score = [&](const double2 (&src)[JG], int jg) {
+#pragma unroll
+                for (int x = 0; x < JG; ++x) {
+                    const int jr = jg + x;
+                    const int jc = jr <= nrow ? jr : nrow;
+                    unsigned long long m0 = 0, m1 = 0;
+                    __builtin_amdgcn_s_waitcnt(0xC07F);
+                    load_half(rb, jc, 1);
+                    __builtin_amdgcn_sched_barrier(0);
+                    score_half(ra, src[x], 0, m0, m1);
+                    __builtin_amdgcn_s_waitcnt(0xC07F);
+                    load_half(ra, jr + 1 <= nrow ? jr + 1 : nrow, 0);
+                    __builtin_amdgcn_sched_barrier(0);
+                    score_half(rb, src[x], 1, m0, m1);
+                    if (DIAG) {
+                        const int64_t j = jlo + jr;
+                        m0 &= __ballot(k0 > j);
+                        m1 &= __ballot(k1 > j);
+                    }
+                    if (jr > nrow) m0 = m1 = 0;
+                    if (m0 | m1) {
+                        if (lane == 0) {
+                            s_q[wave][nq][0] = m0;
+                            s_q[wave][nq][1] = m1;
+                            s_qj[wave][nq] = jr;
+                        }
+                        ++nq;
+                    }
+                }
+            };
+            __builtin_amdgcn_s_waitcnt(0x0F70);
+            fetch(ga, 0);
+            for (int jg = 0;; jg += 2 * JG) {
+                fetch(gb, jg + JG);
+                score(ga, jg);
+                fetch(ga, jg + 2 * JG);
+                score(gb, jg + JG);
+                if (jg + 2 * JG > nrow) break;
+            }
+        };
+        if (diag) sweep(std::true_type{});
+        else sweep(std::false_type{});
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_wave_barrier();
+
+        // exact scoring of the flagged steps (rare): the same terms, a true
+        // division, the rank test and the current bound
+        for (int e = 0; e < nq; ++e) {
+            const int jr = s_qj[wave][e];
+            const int64_t j = jlo + jr;
+            const unsigned long long fm[2] = {s_q[wave][e][0], s_q[wave][e][1]};
+            const double *rp = reinterpret_cast<const double *>(recj + (size_t)jr * 128);
+            const double2 gv = *reinterpret_cast<const double2 *>(gtile + (voff + (uint32_t)jr * 512u));
+            for (int r = 0; r < S3_NR; ++r) {
+                const double v = rp[4 * r], al = rp[4 * r + 1], zs = rp[4 * r + 2], p = rp[4 * r + 3];
+                for (int sl = 0; sl < 2; ++sl) {
+                    const double gg = sl ? gv.y : gv.x;
+                    const int64_t k = sl ? k1 : k0;
+                    const double u = fma(-v, w[r][sl], gg);
+                    const double d = fma(-al, u * u, dq[r][sl]);
+                    const double z = fma(-zs, u, zq[r][sl]);
+                    const double es = (d > RANK_EPS) ? p - z * z / d : INF;
+                    const double thc = fmin(theta_f, Ls[KP - 1]);
+                    bool take = ((fm[sl] >> lane) & 1ull) && k < S && k > j && es <= thc;
+                    uint64_t rk = 0;
+                    if (take) {
+                        const int32_t tup[3] = {(int32_t)(S3_NR * g + r), (int32_t)j, (int32_t)k};
+                        rk = pack_tuple(tup, 3);
+                        if (a.ranged) {
+                            const uint64_t lr = lex_rank(BinomTab{c.btab, c.S}, c.S, 3, tup);
+                            if (lr < a.r0 || lr >= a.r1) take = false;
+                        }
+                    }
+                    unsigned long long m = __ballot(take);
+                    offered += (unsigned)__popcll(m);
+                    while (m) {
+                        const int src = __ffsll((long long)m) - 1;
+                        m &= m - 1;
+                        const double cs = __shfl(es, src);
+                        const uint64_t cr = (uint64_t)__shfl((long long)rk, src);
+                        list_insert(Ls, Lr, KP, cs, cr);
+                    }
+                }
+            }
+        }
+        const double tw = Ls[KP - 1];
+        if (tw < theta_pub) {
+            theta_pub = tw;
+            if (lane == 0) theta_publish(c.theta_bits, tw);
+        }
+    }
+    if (lane == 0 && offered) atomicAdd(c.cand_counter, offered);
+    const int64_t gw = (int64_t)blockIdx.x * SEARCH_WAVES + wave;
+    for (int m = lane; m < KP; m += 64) {
+        c.list_sse[gw * KP + m] = Ls[m];
+        c.list_rank[gw * KP + m] = Lr[m];
+    }
+}
+
 // D = 1: every feature is a tuple; SSE = sum_t (c_t - b_t^2) over full-rank columns.
 __global__ __launch_bounds__(256) void search_d1_kernel(Ctx c, SearchArgs a) {
     extern __shared__ double smem[];
@@ -1595,7 +1934,7 @@ int launch_search(const Ctx &c, const SearchCall &sc, hipStream_t st) {
         int wgs = (int)((c.S + SEARCH_WG - 1) / SEARCH_WG);
         if (wgs > c.search_wgs) wgs = c.search_wgs;
         phase_begin(c, SISSO_PHASE_PREPASS, st);
-        hipLaunchKernelGGL(search_init_kernel, dim3(init_blocks), dim3(256), 0, st, c, 2, 1, JBLK);
+        hipLaunchKernelGGL(search_init_kernel, dim3(init_blocks), dim3(256), 0, st, c, 2, 1, JBLK, 0);
         phase_end(c, SISSO_PHASE_PREPASS, st);
         phase_begin(c, SISSO_PHASE_SEARCH, st);
         hipLaunchKernelGGL(search_d1_kernel, dim3(wgs), dim3(SEARCH_WG), lds_lists, st, c, a);
@@ -1605,14 +1944,23 @@ int launch_search(const Ctx &c, const SearchCall &sc, hipStream_t st) {
         phase_end(c, SISSO_PHASE_MERGE, st);
     } else {
         phase_begin(c, SISSO_PHASE_PREPASS, st);
-        hipLaunchKernelGGL(search_init_kernel, dim3(init_blocks), dim3(256), 0, st, c, D, a.R, a.JB);
+        // one task, D = 3: record table + tile sweep (tile count within the 32-bit work counter)
+        const bool s3 = D == 3 && !MT && c.rec3 != nullptr && s3_tiles_host(c.S) < (1ull << 31);
+        hipLaunchKernelGGL(search_init_kernel, dim3(init_blocks), dim3(256), 0, st, c, D, a.R, a.JB, s3 ? 1 : 0);
+        if (s3) {
+            const int64_t nrec = (c.S + S3_NR - 1) / S3_NR * c.S * S3_NR;
+            hipLaunchKernelGGL(rec3_kernel, dim3((unsigned)((nrec + 255) / 256)), dim3(256), 0, st, c, c.rec3);
+        }
         hipLaunchKernelGGL(pre_select_kernel, dim3(1), dim3(PRE_WG), 0, st, c, D);
         hipLaunchKernelGGL(pre_extend_kernel, dim3(PRE_Q), dim3(PRE_WG), 0, st, c, D, sc.ranged,
                            sc.r0, sc.r1, a.L);
         phase_end(c, SISSO_PHASE_PREPASS, st);
         phase_begin(c, SISSO_PHASE_SEARCH, st);
         const size_t lds = lds_lists + (size_t)256 * RECW * sizeof(double) + (size_t)64 * SUBW * sizeof(double);
-        switch (D) {
+        if (s3)
+            hipLaunchKernelGGL(search3_kernel, dim3(c.search_wgs), dim3(SEARCH_WG), lds_lists, st, c, a,
+                               (const double *)c.rec3, (const uint64_t *)c.cum);
+        else switch (D) {
             case 2: MT ? launch_one<2, true>(c, a, lds, st) : launch_one<2, false>(c, a, lds, st); break;
             case 3: MT ? launch_one<3, true>(c, a, lds, st) : launch_one<3, false>(c, a, lds, st); break;
             case 4: MT ? launch_one<4, true>(c, a, lds, st) : launch_one<4, false>(c, a, lds, st); break;
@@ -1670,7 +2018,7 @@ int launch_prefix_features_range(const Ctx &c, int M, uint64_t r0, int64_t n, fl
 int launch_list_search(const Ctx &c, int D, int k, const int32_t *pre, int64_t n, hipStream_t st) {
     const unsigned init_blocks = (unsigned)(((SISSO_MAX_D + 1) * (c.S + 1) + 255) / 256);
     phase_begin(c, SISSO_PHASE_PREPASS, st);
-    hipLaunchKernelGGL(search_init_kernel, dim3(init_blocks), dim3(256), 0, st, c, 2, 1, JBLK);
+    hipLaunchKernelGGL(search_init_kernel, dim3(init_blocks), dim3(256), 0, st, c, 2, 1, JBLK, 0);
     phase_end(c, SISSO_PHASE_PREPASS, st);
     int64_t wgs = (n + SEARCH_WAVES - 1) / SEARCH_WAVES;
     if (wgs > c.search_wgs) wgs = c.search_wgs;
