@@ -28,9 +28,11 @@ struct sisso_l0 {
     hipEvent_t ev[2 * SISSO_NPHASE] = {};
     bool ran[SISSO_NPHASE] = {};
     bool prof = false;
+    char *stage = nullptr;  // pinned host copy of the result block (one transfer per readout)
     ~sisso_l0() {
         for (auto &e : ev)
             if (e) (void)hipEventDestroy(e);
+        if (stage) (void)hipHostFree(stage);
     }
 };
 
@@ -104,9 +106,15 @@ static Layout compute_layout(int64_t n_total, int64_t S, int T, int D_max, int k
     L.merged = take((size_t)L.KP * 2 * d);
     L.rescored = take((size_t)L.KP * d);
     L.coef = take((size_t)L.KP * T * (D_max + 1) * d);
-    L.res_idx = take((size_t)k_max * D_max * sizeof(int32_t));
-    L.res_sse = take((size_t)k_max * d);
-    L.res_coef = take((size_t)k_max * T * (D_max + 1) * d);
+    {
+        const size_t idx_bytes = ((size_t)k_max * D_max * sizeof(int32_t) + 7) & ~(size_t)7;
+        const size_t coef_bytes = (size_t)k_max * T * (D_max + 1) * d;
+        L.res_bytes = 16 + (size_t)k_max * d + idx_bytes + coef_bytes;
+        L.res = take(L.res_bytes);
+        L.res_sse = L.res + 16;
+        L.res_idx = L.res_sse + (size_t)k_max * d;
+        L.res_coef = L.res_idx + idx_bytes;
+    }
     L.total = o;
     return L;
 }
@@ -180,6 +188,7 @@ static void carve(sisso_l0 *h) {
     c.merged_rank = (uint64_t *)(base + L.merged + (size_t)L.KP * sizeof(double));
     c.resc_sse = (double *)(base + L.rescored);
     c.resc_coef = (double *)(base + L.coef);
+    c.res_flags = (uint32_t *)(base + L.res);
     c.res_idx = (int32_t *)(base + L.res_idx);
     c.res_sse = (double *)(base + L.res_sse);
     c.res_coef = (double *)(base + L.res_coef);
@@ -213,6 +222,11 @@ extern "C" int32_t sisso_l0_create(const sisso_l0_desc *d, sisso_l0 **out) {
     h->lay = compute_layout(d->n_total, d->S, d->T, d->D_max, d->k_max, precision_slices(d->precision));
     h->stream = (hipStream_t)d->stream;
     carve(h);
+    if (hipHostMalloc((void **)&h->stage, h->lay.res_bytes, hipHostMallocDefault) != hipSuccess) {
+        h->stage = nullptr;
+        delete h;
+        return fail(nullptr, SISSO_EDEVICE, "could not allocate the pinned result stage");
+    }
     // precision form: chunks of LP_XC samples per task (the count never
     // exceeds the bound the layout was sized with)
     std::vector<int32_t> cbase(d->T + 1, 0);
@@ -470,15 +484,19 @@ extern "C" int32_t sisso_l0_topk(sisso_l0 *h, int32_t k, int32_t *idx, double *s
     if (k < 1 || k > h->last_k) return fail(h, SISSO_ESTATE, "k exceeds the searched k");
     if (!idx || !sse) return fail(h, SISSO_EINVAL, "null idx or sse");
     const int D = h->last_D, T = h->desc.T;
-    uint32_t flags[4] = {0, 0, 0, 0};
-    hipError_t e = hipMemcpyAsync(idx, h->ctx.res_idx, (size_t)k * D * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(sse, h->ctx.res_sse, (size_t)k * sizeof(double), hipMemcpyDeviceToHost, h->stream);
-    if (e == hipSuccess && coef)
-        e = hipMemcpyAsync(coef, h->ctx.res_coef, (size_t)k * T * (D + 1) * sizeof(double), hipMemcpyDeviceToHost, h->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(flags, h->ctx.flags, sizeof(flags), hipMemcpyDeviceToHost, h->stream);
+    const Layout &L = h->lay;
+    // the final kernel leaves status words, SSEs, indices and coefficients in
+    // one block: a single transfer into the pinned stage, then host copies
+    const size_t bytes = coef ? L.res_bytes : L.res_coef - L.res;
+    hipError_t e = hipMemcpyAsync(h->stage, h->ctx.res_flags, bytes, hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return fail(h, SISSO_EDEVICE, hipGetErrorString(e));
+    uint32_t flags[4];
+    memcpy(flags, h->stage, sizeof(flags));
     if (flags[FLAG_NONFINITE]) return fail(h, SISSO_EINVAL, "F or y holds a non-finite value");
+    memcpy(sse, h->stage + (L.res_sse - L.res), (size_t)k * sizeof(double));
+    memcpy(idx, h->stage + (L.res_idx - L.res), (size_t)k * D * sizeof(int32_t));
+    if (coef) memcpy(coef, h->stage + (L.res_coef - L.res), (size_t)k * T * (D + 1) * sizeof(double));
     return SISSO_OK;
 }
 

@@ -214,9 +214,11 @@ struct Layout {
     size_t merged;     // merged candidates [KP] (sse, rank)
     size_t rescored;   // rescored candidates [KP] (sse, rank)
     size_t coef;       // double [KP][T][D_max+1]
-    size_t res_idx;    // int32 [k_max][D_max]
-    size_t res_sse;    // double [k_max]
-    size_t res_coef;   // double [k_max][T][D_max+1]
+    size_t res;        // result block, read back by one copy: status words uint32 [4], then
+    size_t res_sse;    //   double [k_max],
+    size_t res_idx;    //   int32 [k_max][D_max] (padded to 8 bytes),
+    size_t res_coef;   //   double [k_max][T][D_max+1]
+    size_t res_bytes;  // block size without / with the coefficients: res_coef - res, res_bytes
     size_t total;
     int TP;            // tasks padded to a power of two
     int nsplit;        // split-K factor of the Gram

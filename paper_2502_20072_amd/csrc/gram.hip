@@ -22,14 +22,17 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
+// One workgroup: clears the status words, then wave w handles tasks w,
+// w + 4, ... (so no other workgroup can set a status bit before the clear).
 __global__ __launch_bounds__(256) void stats_y_kernel(const double *__restrict__ y,
                                                       const int64_t *__restrict__ off, int T,
                                                       double *__restrict__ ybar,
                                                       double *__restrict__ cyy,
                                                       uint32_t *__restrict__ flags) {
     const int lane = threadIdx.x & 63;
-    const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (t >= T) return;
+    if (threadIdx.x < 64) flags[threadIdx.x] = 0u;
+    __syncthreads();
+    for (int t = threadIdx.x >> 6; t < T; t += 4) {
     const int64_t r0 = off[t], r1 = off[t + 1];
     double s = 0.0;
     bool bad = false;
@@ -52,6 +55,7 @@ __global__ __launch_bounds__(256) void stats_y_kernel(const double *__restrict__
     if (lane == 0) {
         ybar[t] = m;
         cyy[t] = ss;
+    }
     }
 }
 
@@ -267,13 +271,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 // mirrored elements are bitwise equal and both writes are coalesced.  The
 // diagonal is 1 for a non-constant column and 0 for a constant one; padding
 // rows/columns and padded tasks are written as zeros.
+constexpr int FIN_ROWS = 16;  // tile rows per finishing workgroup (divides 64)
 __global__ __launch_bounds__(256) void gram_finish_kernel(const double *__restrict__ part, int64_t S, int T,
                                                           int TP, int nsplit, const double *__restrict__ inv_s,
                                                           double *__restrict__ G, int64_t nt) {
-    __shared__ double tr[GT][GT + 1];
+    __shared__ double tr[GT][FIN_ROWS + 1];
     const int64_t npair = nt * (nt + 1) / 2;
-    const int t = (int)(blockIdx.x / npair);
-    int64_t pr = blockIdx.x % npair;
+    const int qr = (int)(blockIdx.x % (GT / FIN_ROWS));  // row band of the tile pair
+    const int64_t pb = blockIdx.x / (GT / FIN_ROWS);
+    const int t = (int)(pb / npair);
+    int64_t pr = pb % npair;
     int64_t ti = 0;
     while (pr >= nt - ti) {
         pr -= nt - ti;
@@ -281,15 +288,15 @@ __global__ __launch_bounds__(256) void gram_finish_kernel(const double *__restri
     }
     const int64_t tk = ti + pr;
     const double *ist = inv_s + (int64_t)t * S;
-    // each thread owns 16 elements; the split partials are summed split by
-    // split with all 16 loads of a split in flight (indices clamped in range,
-    // out-of-range elements masked afterwards)
-    constexpr int PER = GT * GT / 256;
+    // each thread owns PER elements of rows [FIN_ROWS qr, FIN_ROWS (qr + 1));
+    // the split partials are summed split by split, two splits of loads in
+    // flight (indices clamped in range, out-of-range elements masked after)
+    constexpr int PER = GT * FIN_ROWS / 256;
     int64_t src[PER];
 #pragma unroll
     for (int m = 0; m < PER; ++m) {
         const int e = threadIdx.x + 256 * m;
-        const int li = e >> 6, lk = e & 63;
+        const int li = FIN_ROWS * qr + (e >> 6), lk = e & 63;
         int64_t i = ti * GT + li, k = tk * GT + lk;
         i = i < S ? i : S - 1;
         k = k < S ? k : S - 1;
@@ -299,6 +306,7 @@ __global__ __launch_bounds__(256) void gram_finish_kernel(const double *__restri
     double acc[PER];
 #pragma unroll
     for (int m = 0; m < PER; ++m) acc[m] = 0.0;
+#pragma unroll 2
     for (int sp = 0; sp < nsplit; ++sp) {
         const double *P = part + ((int64_t)sp * T + t) * S * S;
 #pragma unroll
@@ -307,7 +315,7 @@ __global__ __launch_bounds__(256) void gram_finish_kernel(const double *__restri
 #pragma unroll
     for (int m = 0; m < PER; ++m) {
         const int e = threadIdx.x + 256 * m;
-        const int li = e >> 6, lk = e & 63;
+        const int li = FIN_ROWS * qr + (e >> 6), lk = e & 63;
         const int64_t i = ti * GT + li, k = tk * GT + lk;
         double v = 0.0;
         if (i < S && k < S) {
@@ -315,15 +323,17 @@ __global__ __launch_bounds__(256) void gram_finish_kernel(const double *__restri
             v = i == k ? (ist[i] > 0.0 ? 1.0 : 0.0) : acc[m] * (ist[a] * ist[cc]);
         }
         G[((((ti * nt + tk) << 12) + (li << 6) + lk)) * TP + t] = v;
-        tr[lk][li] = v;
+        tr[lk][li - FIN_ROWS * qr] = v;
         if (t == T - 1)
             for (int tp = T; tp < TP; ++tp) G[((((ti * nt + tk) << 12) + (li << 6) + lk)) * TP + tp] = 0.0;
     }
     if (ti == tk) return;
     __syncthreads();
-    for (int e = threadIdx.x; e < GT * GT; e += 256) {
-        const int li = e >> 6, lk = e & 63;  // row li of tile (tk, ti) = column li of tile (ti, tk)
-        G[((((tk * nt + ti) << 12) + (li << 6) + lk)) * TP + t] = tr[li][lk];
+    for (int e = threadIdx.x; e < GT * FIN_ROWS; e += 256) {
+        // row li of tile (tk, ti) = column li of tile (ti, tk): this band
+        // holds columns [FIN_ROWS qr, FIN_ROWS (qr + 1)) of every such row
+        const int li = e / FIN_ROWS, lk = FIN_ROWS * qr + e % FIN_ROWS;
+        G[((((tk * nt + ti) << 12) + (li << 6) + lk)) * TP + t] = tr[li][lk - FIN_ROWS * qr];
         if (t == T - 1)
             for (int tp = T; tp < TP; ++tp) G[((((tk * nt + ti) << 12) + (li << 6) + lk)) * TP + tp] = 0.0;
     }
@@ -344,15 +354,9 @@ int launch_untile(const Ctx &c, int t, double *dst, hipStream_t st) {
 }
 
 // ------------------------------------------------------------- launchers
-__global__ void clear_flags_kernel(uint32_t *flags) {
-    if (threadIdx.x < 64) flags[threadIdx.x] = 0u;
-}
-
 int launch_stats(const Ctx &c, hipStream_t st) {
     phase_begin(c, SISSO_PHASE_STATS, st);
-    hipLaunchKernelGGL(clear_flags_kernel, dim3(1), dim3(64), 0, st, c.flags);
-    hipLaunchKernelGGL(stats_y_kernel, dim3((c.T + 3) / 4), dim3(256), 0, st, c.y, c.off_dev, c.T,
-                       c.ybar, c.cyy, c.flags);
+    hipLaunchKernelGGL(stats_y_kernel, dim3(1), dim3(256), 0, st, c.y, c.off_dev, c.T, c.ybar, c.cyy, c.flags);
     const int64_t jobs = c.S * c.T;
     hipLaunchKernelGGL(stats_x_kernel, dim3((unsigned)((jobs + 3) / 4)), dim3(256), 0, st, c.F, c.y,
                        c.off_dev, c.n_total, c.S, c.T, c.TP, c.ybar, c.mu, c.inv_s, c.bhat, c.flags);
@@ -371,7 +375,7 @@ int launch_gram(const Ctx &c, hipStream_t st) {
                            c.off_dev, c.T, c.mu, ntile, c.nsplit, c.part);
     }
     const int64_t npair64 = c.Gnt * (c.Gnt + 1) / 2;
-    hipLaunchKernelGGL(gram_finish_kernel, dim3((unsigned)(npair64 * c.T)), dim3(256), 0, st, c.part, c.S, c.T,
+    hipLaunchKernelGGL(gram_finish_kernel, dim3((unsigned)(npair64 * c.T * (GT / FIN_ROWS))), dim3(256), 0, st, c.part, c.S, c.T,
                        c.TP, c.nsplit, c.inv_s, c.G, c.Gnt);
     phase_end(c, SISSO_PHASE_GRAM, st);
     return hipGetLastError() == hipSuccess ? 0 : -1;

@@ -40,6 +40,7 @@ struct Ctx {
     uint64_t *merged_rank;
     double *resc_sse;                // rescored [KP]
     double *resc_coef;               // [KP][T][D_max+1]
+    uint32_t *res_flags;             // final: copy of the status words [4], head of the result block
     int32_t *res_idx;                // final [k_max][D_max]
     double *res_sse;                 // [k_max]
     double *res_coef;                // [k_max][T][D_max+1]

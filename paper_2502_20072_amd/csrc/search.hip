@@ -216,8 +216,7 @@ __device__ void wave_sort_list(double *Ls, uint64_t *Lr, int KP) {
 // {0..N_jb-2}, grouped R at a time.
 __device__ void s3_tile_table(const Ctx &c);
 
-__global__ void search_init_kernel(Ctx c, int D, int R, int JB, int s3) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ void search_init_body(const Ctx &c, int64_t e, int D, int R, int JB, int s3) {
     if (e < (int64_t)(SISSO_MAX_D + 1) * (c.S + 1)) {
         const int r = (int)(e / (c.S + 1));
         const int64_t n = e % (c.S + 1);
@@ -248,6 +247,10 @@ __global__ void search_init_kernel(Ctx c, int D, int R, int JB, int s3) {
             c.cum[b + 1] = acc;
         }
     }
+}
+
+__global__ void search_init_kernel(Ctx c, int D, int R, int JB, int s3) {
+    search_init_body(c, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, D, R, JB, s3);
 }
 
 // ----------------------------------------------------- threshold pre-pass
@@ -958,8 +961,10 @@ constexpr int S3_KC = 128;            // k per tile: two adjacent per lane
 // with v = G[i1][j], d_j = 1 - v^2, s_j = sqrt(d_j), z_j = (b_j - v b_i1) / s_j,
 // p = c - b_i1^2 - z_j^2 (the SSE of the pair); p = NaN (fails every
 // comparison) unless i1 < j, column i1 is live and d_j > RANK_EPS.
+// (its grid also does the per-search initialisation of search_init_kernel)
 __global__ __launch_bounds__(256) void rec3_kernel(Ctx c, double *__restrict__ rec) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    search_init_body(c, e, 3, SUBP, JBLK, 1);
     const int64_t S = c.S;
     const int64_t ng = (S + S3_NR - 1) / S3_NR;
     if (e >= ng * S * S3_NR) return;
@@ -1846,6 +1851,8 @@ __global__ __launch_bounds__(256) void rescore_kernel(Ctx c, int D) {
 // ones last in candidate order) and write the k best.  The KP keys are staged
 // in LDS once, so each thread's count runs over LDS.
 __global__ __launch_bounds__(1024) void final_kernel(Ctx c, int D, int k, int KP) {
+    // status words travel with the results (one readout transfer)
+    if (threadIdx.x < 4) c.res_flags[threadIdx.x] = c.flags[threadIdx.x];
     __shared__ double fs[KP_MAX];
     __shared__ uint64_t fr[KP_MAX];
     __shared__ double ferr[1024 / 64];
@@ -1946,10 +1953,14 @@ int launch_search(const Ctx &c, const SearchCall &sc, hipStream_t st) {
         phase_begin(c, SISSO_PHASE_PREPASS, st);
         // one task, D = 3: record table + tile sweep (tile count within the 32-bit work counter)
         const bool s3 = D == 3 && !MT && c.rec3 != nullptr && s3_tiles_host(c.S) < (1ull << 31);
-        hipLaunchKernelGGL(search_init_kernel, dim3(init_blocks), dim3(256), 0, st, c, D, a.R, a.JB, s3 ? 1 : 0);
         if (s3) {
-            const int64_t nrec = (c.S + S3_NR - 1) / S3_NR * c.S * S3_NR;
+            // record table + initialisation in one launch (its grid covers the binomial table)
+            int64_t nrec = (c.S + S3_NR - 1) / S3_NR * c.S * S3_NR;
+            const int64_t ninit = (int64_t)init_blocks * 256;
+            if (nrec < ninit) nrec = ninit;
             hipLaunchKernelGGL(rec3_kernel, dim3((unsigned)((nrec + 255) / 256)), dim3(256), 0, st, c, c.rec3);
+        } else {
+            hipLaunchKernelGGL(search_init_kernel, dim3(init_blocks), dim3(256), 0, st, c, D, a.R, a.JB, 0);
         }
         hipLaunchKernelGGL(pre_select_kernel, dim3(1), dim3(PRE_WG), 0, st, c, D);
         hipLaunchKernelGGL(pre_extend_kernel, dim3(PRE_Q), dim3(PRE_WG), 0, st, c, D, sc.ranged,
