@@ -259,33 +259,11 @@ __global__ void search_init_kernel(Ctx c, int D, int R, int JB, int s3) {
 // structured set of real tuples: the best (D-1)-subsets of the PRE_M most
 // relevant features, each extended by every feature.  Any set of real
 // tuples gives a valid bound (below), so the selections may be heuristic;
-// they run as block-wide bitonic sorts in LDS, one thread per candidate.
+// they run as block-wide histogram thresholds, one thread per candidate.
 constexpr int PRE_WG = 1024;      // threads of the pre-pass workgroups
 constexpr int PRE_SORT = 4096;    // largest sorted candidate set
 constexpr int PRE_KEEP = PRE_SORT / PRE_WG;  // candidates a thread keeps when S > PRE_SORT
 
-// Ascending sort of N (power of two) (key, id) pairs in LDS by (key, id).
-__device__ void block_sort(double *key, int *id, int N) {
-    for (int k = 2; k <= N; k <<= 1)
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = threadIdx.x; i < N; i += blockDim.x) {
-                const int ixj = i ^ j;
-                if (ixj > i) {
-                    const bool up = (i & k) == 0;
-                    const double a = key[i], b = key[ixj];
-                    const int ia = id[i], ib = id[ixj];
-                    const bool after = a > b || (a == b && ia > ib);
-                    if (after == up) {
-                        key[i] = b;
-                        key[ixj] = a;
-                        id[i] = ib;
-                        id[ixj] = ia;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-}
 
 // Fill key/id[0..N) with the candidates v(x) for x in [0, n): directly when
 // n <= PRE_SORT, else each thread keeps its PRE_KEEP smallest.  Returns N.
@@ -329,18 +307,139 @@ __device__ int gather_candidates(double *key, int *id, int64_t n, F v) {
     return PRE_SORT;
 }
 
+// Selections of the pre-pass without sorting: a histogram of 1024 bins over
+// the order keys of the candidate values (IEEE doubles mapped to integers so
+// that integer order = value order) finds, in a few barrier steps, a
+// threshold t such that at least L candidates are <= t and t lies within one
+// bin of the L-th smallest value.
+constexpr int SEL_NB = PRE_WG;  // one histogram bin per thread
+struct SelScratch {
+    unsigned long long mn, mx;
+    unsigned cnt;
+    unsigned hist[SEL_NB];
+    unsigned wsum[PRE_WG / 64];
+    double res;
+    int npick;
+};
+
+__device__ inline uint64_t okey(double v) {
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+__device__ inline double okey_inv(uint64_t t) {
+    const uint64_t u = (t >> 63) ? (t & 0x7fffffffffffffffull) : ~t;
+    return __longlong_as_double((long long)u);
+}
+
+// Block-wide inclusive prefix sum of one value per thread (PRE_WG threads).
+__device__ inline unsigned block_scan(unsigned v, unsigned *wsum) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    unsigned incl = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    unsigned base = 0;
+    for (int w = 0; w < wave; ++w) base += wsum[w];
+    __syncthreads();
+    return incl + base;
+}
+
+// Threshold over key[0..n) (smaller is better, INF = not a candidate): a
+// value t, equal to a bin's upper edge or to the largest candidate, with at
+// least L candidates <= t; INF when fewer than L candidates exist.  Called
+// by all PRE_WG threads.
+__device__ double block_threshold(const double *key, int n, int L, SelScratch &sc) {
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        sc.mn = ~0ull;
+        sc.mx = 0;
+        sc.cnt = 0;
+    }
+    sc.hist[tid] = 0;
+    __syncthreads();
+    unsigned long long mn = ~0ull, mx = 0;
+    unsigned cnt = 0;
+    for (int x = tid; x < n; x += PRE_WG) {
+        const double v = key[x];
+        if (v < INF) {
+            const uint64_t u = okey(v);
+            mn = u < mn ? u : mn;
+            mx = u > mx ? u : mx;
+            ++cnt;
+        }
+    }
+    for (int o = 32; o >= 1; o >>= 1) {
+        const unsigned long long a = (unsigned long long)__shfl_xor((long long)mn, o);
+        const unsigned long long b = (unsigned long long)__shfl_xor((long long)mx, o);
+        mn = a < mn ? a : mn;
+        mx = b > mx ? b : mx;
+        cnt += __shfl_xor(cnt, o);
+    }
+    if ((tid & 63) == 0) {
+        atomicMin(&sc.mn, mn);
+        atomicMax(&sc.mx, mx);
+        atomicAdd(&sc.cnt, cnt);
+    }
+    __syncthreads();
+    if (L < 1 || sc.cnt < (unsigned)L) return INF;
+    const uint64_t lo = sc.mn, hi = sc.mx, span = hi - lo;
+    int sh = 0;
+    while ((span >> sh) >= (uint64_t)SEL_NB) ++sh;
+    for (int x = tid; x < n; x += PRE_WG) {
+        const double v = key[x];
+        if (v < INF) atomicAdd(&sc.hist[(okey(v) - lo) >> sh], 1u);
+    }
+    __syncthreads();
+    const unsigned h = sc.hist[tid];
+    const unsigned incl = block_scan(h, sc.wsum);
+    if (incl >= (unsigned)L && incl - h < (unsigned)L) {
+        // the bin holding the L-th smallest: every candidate of bins <= tid is
+        // <= its upper edge (the last occupied bin's edge is the maximum)
+        const uint64_t top = span >> sh;
+        const uint64_t edge = (uint64_t)tid + 1 > top ? hi : lo + (((uint64_t)tid + 1) << sh) - 1;
+        sc.res = okey_inv(edge);
+    }
+    __syncthreads();
+    return sc.res;
+}
+
+// The first (by position) up to M positions x < n with key[x] <= t, into
+// out[]; returns how many.  Called by all PRE_WG threads.
+__device__ int block_pick_first(const double *key, int n, double t, int M, int *out, SelScratch &sc) {
+    int taken = 0;
+    for (int base = 0; base < n && taken < M; base += PRE_WG) {
+        const int x = base + (int)threadIdx.x;
+        const bool f = x < n && key[x] < INF && key[x] <= t;
+        const unsigned incl = block_scan(f ? 1u : 0u, sc.wsum);
+        const int pos = taken + (int)incl - (f ? 1 : 0);
+        if (f && pos < M) out[pos] = x;
+        if (threadIdx.x == PRE_WG - 1) sc.npick = taken + (int)incl;
+        __syncthreads();
+        taken = sc.npick < M ? sc.npick : M;
+        __syncthreads();
+    }
+    return taken;
+}
+
 // pre_select: relevance of feature j = sum over tasks of b_tj^2 (its D=1
 // explained sum of squares); the PRE_M most relevant full-rank features;
 // every (D-1)-subset of them scored; the PRE_Q best subsets become prefixes.
-__global__ __launch_bounds__(PRE_WG) void pre_select_kernel(Ctx c, int D) {
+template <int D>
+__global__ __launch_bounds__(PRE_WG) void pre_select_kernel(Ctx c) {
     __shared__ double key[PRE_SORT];
     __shared__ int id[PRE_SORT];
+    __shared__ int pick[PRE_M > PRE_Q ? PRE_M : PRE_Q];
     __shared__ int sel[PRE_M];
-    __shared__ int s_m;
+    __shared__ SelScratch sc;
     const int tid = threadIdx.x;
-    const int q = D - 1;
-    // 1. most relevant full-rank features first
-    int N = gather_candidates(key, id, c.S, [&](int64_t j) {
+    constexpr int q = D - 1;
+    if (tid == 0) *c.pre_count = 0;
+    // 1. the PRE_M most relevant full-rank features (up to the last
+    //    histogram bin), in increasing index order
+    const int N = gather_candidates(key, id, c.S, [&](int64_t j) {
         double r = 0.0;
         bool ok = true;
         for (int t = 0; t < c.T; ++t) {
@@ -351,51 +450,38 @@ __global__ __launch_bounds__(PRE_WG) void pre_select_kernel(Ctx c, int D) {
         return ok ? -r : INF;
     });
     __syncthreads();
-    block_sort(key, id, N);
-    if (tid == 0) {
-        int M = 0;
-        while (M < PRE_M && M < N && key[M] < INF) ++M;
-        // selected features in increasing index order
-        for (int a = 0; a < M; ++a) sel[a] = id[a];
-        for (int a = 1; a < M; ++a)
-            for (int b2 = a; b2 > 0 && sel[b2 - 1] > sel[b2]; --b2) {
-                const int t = sel[b2];
-                sel[b2] = sel[b2 - 1];
-                sel[b2 - 1] = t;
-            }
-        s_m = M;
-        *c.pre_count = 0;
+    double th = block_threshold(key, N, PRE_M, sc);
+    if (!(th < INF)) th = __DBL_MAX__;  // fewer than PRE_M full-rank features: take them all
+    const int M = block_pick_first(key, N, th, PRE_M, pick, sc);
+    // increasing feature index (positions are indices unless S > PRE_SORT)
+    if (tid < M) {
+        const int f = id[pick[tid]];
+        int r = 0;
+        for (int b2 = 0; b2 < M; ++b2) r += id[pick[b2]] < f;
+        sel[r] = f;
     }
     __syncthreads();
-    const int M = s_m;
     if (M < q) return;
     // 2. score every q-subset of the selection (<= C(16, 3) = 560 of them)
     const int nsub = (int)binom(M, q);
-    N = next_pow2_dev(nsub);
-    for (int e = tid; e < N; e += PRE_WG) {
-        double v = INF;
-        if (e < nsub) {
-            int32_t loc[MAXD], tup[MAXD];
-            colex_unrank_small((uint64_t)e, q, M, loc);
-            for (int m = 0; m < q; ++m) tup[m] = sel[loc[m]];
-            v = ne_sse(c, q, tup);
-        }
-        key[e] = v;
-        id[e] = e;
+    for (int e = tid; e < nsub; e += PRE_WG) {
+        int32_t loc[MAXD], tup[MAXD];
+        colex_unrank_small((uint64_t)e, q, M, loc);
+        for (int m = 0; m < q; ++m) tup[m] = sel[loc[m]];
+        key[e] = ne_sse_t<(D > 1 ? D - 1 : 1)>(c, tup);
     }
     __syncthreads();
-    block_sort(key, id, N);
-    // 3. the PRE_Q best subsets (SSE, then subset rank)
-    if (tid == 0) {
-        int Q = 0;
-        while (Q < PRE_Q && Q < N && key[Q] < INF) ++Q;
-        for (int it = 0; it < Q; ++it) {
-            int32_t loc[MAXD];
-            colex_unrank_small((uint64_t)id[it], q, M, loc);
-            for (int m = 0; m < q; ++m) c.pre_prefix[it * MAXD + m] = sel[loc[m]];
-        }
-        *c.pre_count = Q;
+    // 3. PRE_Q of the best subsets (the first in subset order at or below
+    //    the threshold of the PRE_Q-th best)
+    double th2 = block_threshold(key, nsub, PRE_Q, sc);
+    if (!(th2 < INF)) th2 = __DBL_MAX__;
+    const int Q = block_pick_first(key, nsub, th2, PRE_Q, pick, sc);
+    if (tid < Q) {
+        int32_t loc[MAXD];
+        colex_unrank_small((uint64_t)pick[tid], q, M, loc);
+        for (int m = 0; m < q; ++m) c.pre_prefix[tid * MAXD + m] = sel[loc[m]];
     }
+    if (tid == 0) *c.pre_count = Q;
 }
 
 // pre_extend: block qq scores every tuple prefix_qq + {k} that does not
@@ -405,10 +491,12 @@ __global__ __launch_bounds__(PRE_WG) void pre_select_kernel(Ctx c, int D) {
 // tuples at or below that value, so Q*L >= KP of them at or below the
 // maximum over blocks make that maximum an upper bound of the KP-th best
 // SSE of the search.
-__global__ __launch_bounds__(PRE_WG) void pre_extend_kernel(Ctx c, int D, int ranged, uint64_t r0,
+template <int D>
+__global__ __launch_bounds__(PRE_WG) void pre_extend_kernel(Ctx c, int ranged, uint64_t r0,
                                                             uint64_t r1, int L) {
     __shared__ double key[PRE_SORT];
     __shared__ int id[PRE_SORT];
+    __shared__ SelScratch sc;
     const int qq = blockIdx.x;
     const int tid = threadIdx.x;
     const int Q = *c.pre_count;
@@ -446,11 +534,12 @@ __global__ __launch_bounds__(PRE_WG) void pre_extend_kernel(Ctx c, int D, int ra
             const uint64_t rk = lex_rank(BinomTab{c.btab, c.S}, c.S, D, tup);
             if (rk < r0 || rk >= r1) return INF;
         }
-        return ne_sse(c, D, tup);
+        return ne_sse_t<D>(c, tup);
     });
     __syncthreads();
-    block_sort(key, id, N);
-    if (tid == 0) c.pre_bound[qq] = (L <= N && key[L - 1] < INF) ? key[L - 1] : INF;
+    // at least L of the kept candidates (distinct real tuples) are <= the bound
+    const double bound = block_threshold(key, N, L, sc);
+    if (tid == 0) c.pre_bound[qq] = bound;
 }
 
 __device__ double theta0_from_prepass(const Ctx &c, int L, int KP) {
@@ -1734,10 +1823,11 @@ __global__ __launch_bounds__(MERGE_THREADS) void merge_select_kernel(Ctx c, int 
 // of the centred columns are accumulated straight from F in a fixed order,
 // solved by Cholesky (pivot-ratio rank test), and the SSE is taken as the
 // squared norm of the explicit residual y_c - X_c beta.
-__global__ __launch_bounds__(256) void rescore_kernel(Ctx c, int D) {
-    constexpr int NACC = MAXD * (MAXD + 1) / 2 + MAXD;
+template <int D>
+__global__ __launch_bounds__(256) void rescore_kernel(Ctx c) {
+    constexpr int NACC = D * (D + 1) / 2 + D;
     __shared__ double red[NACC][4];
-    __shared__ double s_beta[MAXD];
+    __shared__ double s_beta[D];
     __shared__ int s_ok;
     const int cand = blockIdx.x;
     const int tid = threadIdx.x;
@@ -1755,13 +1845,13 @@ __global__ __launch_bounds__(256) void rescore_kernel(Ctx c, int D) {
     for (int t = 0; t < c.T; ++t) {
         const int64_t r0 = c.off_dev[t], r1 = c.off_dev[t + 1];
         const double ym = c.ybar[t];
-        double mu[MAXD];
+        double mu[D];
         for (int m = 0; m < D; ++m) mu[m] = c.mu[(int64_t)t * c.S + tup[m]];
         double acc[NACC];
         for (int i = 0; i < NACC; ++i) acc[i] = 0.0;
 #pragma unroll 4
         for (int64_t i = r0 + tid; i < r1; i += 256) {
-            double x[MAXD];
+            double x[D];
             for (int m = 0; m < D; ++m) x[m] = c.F[(int64_t)tup[m] * c.n_total + i] - mu[m];
             const double yc = c.y[i] - ym;
             int e = 0;
@@ -1769,7 +1859,7 @@ __global__ __launch_bounds__(256) void rescore_kernel(Ctx c, int D) {
                 for (int l = 0; l <= m; ++l) acc[e++] += x[m] * x[l];
             for (int m = 0; m < D; ++m) acc[e++] += x[m] * yc;
         }
-        const int nacc = D * (D + 1) / 2 + D;
+        constexpr int nacc = NACC;
         // wave butterflies, then the 4 wave sums in a fixed order
         for (int i = 0; i < nacc; ++i) {
             double v = acc[i];
@@ -1780,7 +1870,7 @@ __global__ __launch_bounds__(256) void rescore_kernel(Ctx c, int D) {
         if (tid < nacc) red[tid][0] = ((red[tid][0] + red[tid][1]) + red[tid][2]) + red[tid][3];
         __syncthreads();
         if (tid == 0) {
-            double M[MAXD][MAXD], v[MAXD], L[MAXD][MAXD], z[MAXD];
+            double M[D][D], v[D], L[D][D], z[D];
             int e = 0;
             for (int m = 0; m < D; ++m)
                 for (int l = 0; l <= m; ++l) {
@@ -1821,7 +1911,7 @@ __global__ __launch_bounds__(256) void rescore_kernel(Ctx c, int D) {
             __syncthreads();
             break;
         }
-        double beta[MAXD];
+        double beta[D];
         for (int m = 0; m < D; ++m) beta[m] = s_beta[m];
         double ss = 0.0;
 #pragma unroll 4
@@ -1850,7 +1940,8 @@ __global__ __launch_bounds__(256) void rescore_kernel(Ctx c, int D) {
 // Order the re-scored candidates by (SSE, rank) (rank by counting; invalid
 // ones last in candidate order) and write the k best.  The KP keys are staged
 // in LDS once, so each thread's count runs over LDS.
-__global__ __launch_bounds__(1024) void final_kernel(Ctx c, int D, int k, int KP) {
+template <int D>
+__global__ __launch_bounds__(1024) void final_kernel(Ctx c, int k, int KP) {
     // status words travel with the results (one readout transfer)
     if (threadIdx.x < 4) c.res_flags[threadIdx.x] = c.flags[threadIdx.x];
     __shared__ double fs[KP_MAX];
@@ -1863,23 +1954,33 @@ __global__ __launch_bounds__(1024) void final_kernel(Ctx c, int D, int k, int KP
     }
     __syncthreads();
     double err = 0.0;  // largest relative gap between the ranked and the exact SSE of a result
-    for (int i = threadIdx.x; i < KP; i += blockDim.x) {
-        const double si = fs[i];
-        const uint64_t ri = fr[i];
+    // rank by counting: FIN_SPLIT neighbouring lanes share one candidate and
+    // count over interleaved slices of the others (short LDS chains), then
+    // add their counts with shuffles
+    constexpr int FIN_SPLIT = 8;
+    for (int i0 = 0; i0 < KP; i0 += 1024 / FIN_SPLIT) {
+        const int i = i0 + (int)(threadIdx.x / FIN_SPLIT);
+        const int part = (int)(threadIdx.x % FIN_SPLIT);
+        const bool have = i < KP;
+        const double si = have ? fs[i] : INF;
+        const uint64_t ri = have ? fr[i] : 0;
         const bool vi = si < INF;
         int pos = 0;
-#pragma unroll 8
-        for (int j = 0; j < KP; ++j) {
-            const double sj = fs[j];
-            const bool vj = sj < INF;
-            bool before;
-            if (vi && vj) before = key_less(sj, fr[j], si, ri);
-            else if (vj) before = true;
-            else if (vi) before = false;
-            else before = j < i;
-            pos += before;
+        if (have) {
+#pragma unroll 4
+            for (int j = part; j < KP; j += FIN_SPLIT) {
+                const double sj = fs[j];
+                const bool vj = sj < INF;
+                bool before;
+                if (vi && vj) before = key_less(sj, fr[j], si, ri);
+                else if (vj) before = true;
+                else if (vi) before = false;
+                else before = j < i;
+                pos += before;
+            }
         }
-        if (pos < k) {
+        for (int o = 1; o < FIN_SPLIT; o <<= 1) pos += __shfl_xor(pos, o);
+        if (have && part == 0 && pos < k) {
             if (vi) {
                 const double a = c.merged_sse[i];
                 err = fmax(err, si > 0.0 ? fabs(a - si) / si : fabs(a - si));
@@ -1905,6 +2006,33 @@ __global__ __launch_bounds__(1024) void final_kernel(Ctx c, int D, int k, int KP
 }
 
 // -------------------------------------------------------------- launcher
+// the small per-search kernels are compiled per D (short code, no runtime
+// dimension loops)
+static void launch_rescore_final(const Ctx &c, int D, int k, hipStream_t st) {
+    phase_begin(c, SISSO_PHASE_RESCORE, st);
+    switch (D) {
+        case 1: hipLaunchKernelGGL((rescore_kernel<1>), dim3(c.KP), dim3(256), 0, st, c); break;
+        case 2: hipLaunchKernelGGL((rescore_kernel<2>), dim3(c.KP), dim3(256), 0, st, c); break;
+        case 3: hipLaunchKernelGGL((rescore_kernel<3>), dim3(c.KP), dim3(256), 0, st, c); break;
+        default: hipLaunchKernelGGL((rescore_kernel<4>), dim3(c.KP), dim3(256), 0, st, c); break;
+    }
+    phase_end(c, SISSO_PHASE_RESCORE, st);
+    phase_begin(c, SISSO_PHASE_FINAL, st);
+    switch (D) {
+        case 1: hipLaunchKernelGGL((final_kernel<1>), dim3(1), dim3(1024), 0, st, c, k, c.KP); break;
+        case 2: hipLaunchKernelGGL((final_kernel<2>), dim3(1), dim3(1024), 0, st, c, k, c.KP); break;
+        case 3: hipLaunchKernelGGL((final_kernel<3>), dim3(1), dim3(1024), 0, st, c, k, c.KP); break;
+        default: hipLaunchKernelGGL((final_kernel<4>), dim3(1), dim3(1024), 0, st, c, k, c.KP); break;
+    }
+    phase_end(c, SISSO_PHASE_FINAL, st);
+}
+
+template <int D>
+static void launch_prepass(const Ctx &c, const SearchCall &sc, int L, hipStream_t st) {
+    hipLaunchKernelGGL((pre_select_kernel<D>), dim3(1), dim3(PRE_WG), 0, st, c);
+    hipLaunchKernelGGL((pre_extend_kernel<D>), dim3(PRE_Q), dim3(PRE_WG), 0, st, c, sc.ranged, sc.r0, sc.r1, L);
+}
+
 template <int D, bool MT>
 static void launch_one(const Ctx &c, const SearchArgs &a, size_t lds, hipStream_t st) {
     hipLaunchKernelGGL((search_kernel<D, MT>), dim3(c.search_wgs), dim3(SEARCH_WG), lds, st, c, a);
@@ -1962,9 +2090,11 @@ int launch_search(const Ctx &c, const SearchCall &sc, hipStream_t st) {
         } else {
             hipLaunchKernelGGL(search_init_kernel, dim3(init_blocks), dim3(256), 0, st, c, D, a.R, a.JB, 0);
         }
-        hipLaunchKernelGGL(pre_select_kernel, dim3(1), dim3(PRE_WG), 0, st, c, D);
-        hipLaunchKernelGGL(pre_extend_kernel, dim3(PRE_Q), dim3(PRE_WG), 0, st, c, D, sc.ranged,
-                           sc.r0, sc.r1, a.L);
+        switch (D) {
+            case 2: launch_prepass<2>(c, sc, a.L, st); break;
+            case 3: launch_prepass<3>(c, sc, a.L, st); break;
+            default: launch_prepass<4>(c, sc, a.L, st); break;
+        }
         phase_end(c, SISSO_PHASE_PREPASS, st);
         phase_begin(c, SISSO_PHASE_SEARCH, st);
         const size_t lds = lds_lists + (size_t)256 * RECW * sizeof(double) + (size_t)64 * SUBW * sizeof(double);
@@ -1982,12 +2112,7 @@ int launch_search(const Ctx &c, const SearchCall &sc, hipStream_t st) {
         launch_merge(c, c.search_wgs * SEARCH_WAVES, a.L, 1, st);
         phase_end(c, SISSO_PHASE_MERGE, st);
     }
-    phase_begin(c, SISSO_PHASE_RESCORE, st);
-    hipLaunchKernelGGL(rescore_kernel, dim3(c.KP), dim3(256), 0, st, c, D);
-    phase_end(c, SISSO_PHASE_RESCORE, st);
-    phase_begin(c, SISSO_PHASE_FINAL, st);
-    hipLaunchKernelGGL(final_kernel, dim3(1), dim3(1024), 0, st, c, D, sc.k, c.KP);
-    phase_end(c, SISSO_PHASE_FINAL, st);
+    launch_rescore_final(c, D, sc.k, st);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -2046,12 +2171,7 @@ int launch_list_search(const Ctx &c, int D, int k, const int32_t *pre, int64_t n
     phase_begin(c, SISSO_PHASE_MERGE, st);
     launch_merge(c, (int)wgs * SEARCH_WAVES, 1, 0, st, 1);
     phase_end(c, SISSO_PHASE_MERGE, st);
-    phase_begin(c, SISSO_PHASE_RESCORE, st);
-    hipLaunchKernelGGL(rescore_kernel, dim3(c.KP), dim3(256), 0, st, c, D);
-    phase_end(c, SISSO_PHASE_RESCORE, st);
-    phase_begin(c, SISSO_PHASE_FINAL, st);
-    hipLaunchKernelGGL(final_kernel, dim3(1), dim3(1024), 0, st, c, D, k, c.KP);
-    phase_end(c, SISSO_PHASE_FINAL, st);
+    launch_rescore_final(c, D, k, st);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
