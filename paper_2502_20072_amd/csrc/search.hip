@@ -75,6 +75,15 @@ __device__ inline int64_t uni(int64_t v) {
 __device__ inline uint64_t uni(uint64_t v) { return (uint64_t)uni((int64_t)v); }
 __device__ inline double uni(double v) { return __longlong_as_double(uni((int64_t)__double_as_longlong(v))); }
 
+// Lane permutation inside rows of 16 lanes (DPP), for both halves of a double.
+template <int CTRL>
+__device__ inline double dpp_f64(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, true);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
 __device__ inline int next_pow2_dev(int x) {
     int p = 1;
     while (p < x) p <<= 1;
@@ -551,6 +560,8 @@ __device__ double theta0_from_prepass(const Ctx &c, int L, int KP) {
 }
 
 // --------------------------------------------------------- search kernel
+constexpr int MT_RECS = 512;  // records per work item with many tasks (JB * TP)
+
 struct SearchArgs {
     int D, TL, JB, R, KP, L, ranged;
     uint64_t r0, r1;
@@ -690,7 +701,7 @@ __global__ __launch_bounds__(256) void search_kernel(Ctx c, SearchArgs a) {
     double *Ls = smem + (size_t)wave * KP * 2;
     uint64_t *Lr = reinterpret_cast<uint64_t *>(Ls + KP);
     double *recs = smem + (size_t)SEARCH_WAVES * KP * 2;
-    double *subf = recs + 256 * RECW;                  // [64][SUBW] (per r, or per task)
+    double *subf = recs + (MT ? a.JB * a.TL : SEARCH_WG) * RECW;  // [64][SUBW] (per r, or per task)
     __shared__ int32_t s_sub[SUBP][QA];                // sub-prefix indices per r
     __shared__ int s_iq[SUBP];                         // last sub-prefix index (or -1)
     __shared__ unsigned long long s_mask[SUBP > 64 ? SUBP : 64];  // record validity per r (ST) / per jj (MT)
@@ -714,9 +725,11 @@ __global__ __launch_bounds__(256) void search_kernel(Ctx c, SearchArgs a) {
     const uint64_t nitems = uni(c.cum[(c.S - 1 + JB - 1) / JB]);
     if (blockIdx.x == 0 && tid == 0) c.stats[1] = nitems;
     const double *__restrict__ Gbase = c.G;
-    for (;;) {
+    // items are dealt round-robin over the workgroups (largest first): a
+    // shared counter would serialise on one address
+    for (uint64_t next = blockIdx.x;; next += gridDim.x) {
         if (tid == 0) {
-            s_item = atomicAdd(c.work_counter, 1u);
+            s_item = next;
             const double ts = theta_load(c.theta_bits);
             s_theta = fmin(ts, theta0);
         }
@@ -739,13 +752,14 @@ __global__ __launch_bounds__(256) void search_kernel(Ctx c, SearchArgs a) {
         const int64_t j0 = JB * jb;
         const uint64_t nsub = q > 0 ? binom(Nj - 1, q) : 1;
 
-        // ---- records: thread -> (r, jj) for one task, (jj, t) for many
-        {
+        // ---- records: thread -> (r, jj) for one task, (jj, t) for many (then
+        //      JB * TL records, several per thread)
+        for (int rid = tid; rid < (MT ? JB * TL : SEARCH_WG); rid += SEARCH_WG) {
             int r, jj, t;
             if (MT) {
                 r = 0;
-                jj = tid / TL;
-                t = tid % TL;
+                jj = rid / TL;
+                t = rid % TL;
             } else {
                 r = tid >> 6;
                 jj = tid & 63;
@@ -976,15 +990,72 @@ __global__ __launch_bounds__(256) void search_kernel(Ctx c, SearchArgs a) {
                 // last row and are masked out), so no load is left pending on
                 // a skipped path
                 auto score = [&](const double (&src)[JG], int jg) {
+                    if (MT) {
+                        // many tasks: the task terms of all JG rows first (independent
+                        // chains), then their sums over the TL task lanes of each last
+                        // index, all rows at once (row-local DPP steps; wider groups
+                        // by lane shuffles)
+                        double sm[JG];
+#pragma unroll
+                        for (int x = 0; x < JG; ++x) {
+                            const int jj = jg + x <= nrow ? jg + x : nrow;
+                            const double *rr = recs + (jj * TL + myt) * RECW;
+                            double u = src[x];
+#pragma unroll
+                            for (int xx = 0; xx < q; ++xx) u = fma(-rr[xx], wq[0][xx], u);
+                            const double d = fma(-rr[q], u * u, dq[0]);
+                            const double z = fma(-rr[q + 1], u, zq[0]);
+                            double rc = __builtin_amdgcn_rcp(d);
+                            rc = fma(rc, fma(-d, rc, 1.0), rc);
+                            sm[x] = fma(-(z * z), rc, rr[q + 3]);
+                        }
+                        if (TL >= 2) {
+#pragma unroll
+                            for (int x = 0; x < JG; ++x) sm[x] += dpp_f64<0xB1>(sm[x]);  // lane ^ 1
+                        }
+                        if (TL >= 4) {
+#pragma unroll
+                            for (int x = 0; x < JG; ++x) sm[x] += dpp_f64<0x4E>(sm[x]);  // lane ^ 2
+                        }
+                        if (TL >= 8) {
+#pragma unroll
+                            for (int x = 0; x < JG; ++x) sm[x] += dpp_f64<0x141>(sm[x]);  // mirror in 8
+                        }
+                        if (TL >= 16) {
+#pragma unroll
+                            for (int x = 0; x < JG; ++x) sm[x] += dpp_f64<0x140>(sm[x]);  // mirror in 16
+                        }
+                        if (TL >= 32) {
+#pragma unroll
+                            for (int x = 0; x < JG; ++x) sm[x] += __shfl_xor(sm[x], 16);
+                        }
+                        if (TL >= 64) {
+#pragma unroll
+                            for (int x = 0; x < JG; ++x) sm[x] += __shfl_xor(sm[x], 32);
+                        }
+#pragma unroll
+                        for (int x = 0; x < JG; ++x) {
+                            const int jj = jg + x <= nrow ? jg + x : nrow;
+                            unsigned long long m = __ballot(sm[x] <= theta_f && tl == 0);
+                            if (CHECK) m &= __ballot(kin && kr > jj);
+                            m = (jg + x <= nrow) ? m : 0ull;
+                            if (m) {
+                                if (lane == 0) {
+                                    qmask[nq] = m;
+                                    qj[nq] = jj;
+                                }
+                                ++nq;
+                            }
+                        }
+                        return;
+                    }
 #pragma unroll
                     for (int x = 0; x < JG; ++x) {
                         const int jj = jg + x <= nrow ? jg + x : nrow;
                         RecSet rv;
-                        if (!MT) {
-                            // all record reads of the step are issued before any use
-                            load_rv(rv, jj);
-                            __asm__ volatile("" ::: "memory");
-                        }
+                        // all record reads of the step are issued before any use
+                        load_rv(rv, jj);
+                        __asm__ volatile("" ::: "memory");
                         body(jj, src[x], jg + x <= nrow, rv);
                     }
                 };
@@ -2055,7 +2126,8 @@ int launch_search(const Ctx &c, const SearchCall &sc, hipStream_t st) {
     a.r0 = sc.r0;
     a.r1 = sc.r1;
     a.TL = MT ? c.TP : 1;
-    a.JB = MT ? (64 < SEARCH_WG / c.TP ? 64 : SEARCH_WG / c.TP) : JBLK;
+    // many tasks: JB * TP <= MT_RECS records of the item in LDS (JB <= 64)
+    a.JB = MT ? (64 < MT_RECS / c.TP ? 64 : MT_RECS / c.TP) : JBLK;
     a.R = MT ? 1 : SUBP;
     a.L = (c.KP + PRE_Q - 1) / PRE_Q;
     const int q = D - 2;
@@ -2097,7 +2169,8 @@ int launch_search(const Ctx &c, const SearchCall &sc, hipStream_t st) {
         }
         phase_end(c, SISSO_PHASE_PREPASS, st);
         phase_begin(c, SISSO_PHASE_SEARCH, st);
-        const size_t lds = lds_lists + (size_t)256 * RECW * sizeof(double) + (size_t)64 * SUBW * sizeof(double);
+        const size_t nrec = MT ? (size_t)a.JB * c.TP : (size_t)SEARCH_WG;
+        const size_t lds = lds_lists + nrec * RECW * sizeof(double) + (size_t)64 * SUBW * sizeof(double);
         if (s3)
             hipLaunchKernelGGL(search3_kernel, dim3(c.search_wgs), dim3(SEARCH_WG), lds_lists, st, c, a,
                                (const double *)c.rec3, (const uint64_t *)c.cum);
