@@ -100,7 +100,12 @@ static Layout compute_layout(int64_t n_total, int64_t S, int T, int D_max, int k
     L.pre = take(64 + (size_t)(S / 4 + 8) * sizeof(uint64_t) + PRE_Q * SISSO_MAX_D * sizeof(int32_t) +
                  64 + (size_t)PRE_Q * S * d + PRE_Q * d + 1024 +
                  (size_t)(SISSO_MAX_D + 1) * (S + 1) * sizeof(uint64_t) + 256);
-    L.rec3_bytes = (D_max >= 3 && T == 1) ? (size_t)((S + 3) / 4) * S * 16 * d : 0;
+    // one row of four (i1, j) records per j > i1 group: sum over groups of (S - 2 - 4 g)
+    {
+        const int64_t ng3 = S >= 3 ? (S - 3) / 4 + 1 : 0;
+        const int64_t rows3 = ng3 * (S - 2) - 4 * (ng3 * (ng3 - 1) / 2);
+        L.rec3_bytes = (D_max >= 3 && T == 1 && S >= 3) ? (size_t)rows3 * 16 * d : 0;
+    }
     L.rec3 = take(L.rec3_bytes);
     L.lists = take((size_t)nlists * L.KP * 2 * d + (size_t)nlists * L.KP * 2 * d);
     L.merged = take((size_t)L.KP * 2 * d);

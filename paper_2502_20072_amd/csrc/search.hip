@@ -225,13 +225,13 @@ __device__ void wave_sort_list(double *Ls, uint64_t *Lr, int KP) {
 // {0..N_jb-2}, grouped R at a time.
 __device__ void s3_tile_table(const Ctx &c);
 
-__device__ void search_init_body(const Ctx &c, int64_t e, int D, int R, int JB, int s3) {
+__device__ void search_init_body(const Ctx &c, int64_t e, bool leader, int D, int R, int JB, int s3) {
     if (e < (int64_t)(SISSO_MAX_D + 1) * (c.S + 1)) {
         const int r = (int)(e / (c.S + 1));
         const int64_t n = e % (c.S + 1);
         c.btab[e] = binom(n, r);
     }
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
+    if (leader) {
         *c.work_counter = 0;
         *c.cand_counter = 0;
         *c.theta_bits = (unsigned long long)__double_as_longlong(INF);
@@ -259,7 +259,8 @@ __device__ void search_init_body(const Ctx &c, int64_t e, int D, int R, int JB, 
 }
 
 __global__ void search_init_kernel(Ctx c, int D, int R, int JB, int s3) {
-    search_init_body(c, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, D, R, JB, s3);
+    search_init_body(c, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, threadIdx.x == 0 && blockIdx.x == 0, D, R,
+                     JB, s3);
 }
 
 // ----------------------------------------------------- threshold pre-pass
@@ -1115,23 +1116,39 @@ constexpr int S3_KC = 128;            // k per tile: two adjacent per lane
 #ifndef S3_JG
 #define S3_JG 2                       // G rows per prefetch group (two groups in flight)
 #endif
+constexpr int S3_XCDS = 8;            // XCDs of the chip
+#ifndef S3_XCD_RUN
+#define S3_XCD_RUN 64                 // consecutive tiles dealt within one XCD
+#endif
 
-// record of (i1, j), i1 = S3_NR g + r:
-//   rec[((g S + j) S3_NR + r) 4 + {0, 1, 2, 3}] = {v, 1/d_j, z_j / s_j, p}
+// Rows of the record table: group g (i1 = S3_NR g .. S3_NR g + 3) holds rows
+// j = S3_NR g + 1 .. S - 2, starting at row s3_rowoff(S, g).
+__host__ __device__ inline int64_t s3_rowoff(int64_t S, int64_t g) {
+    // sum over g' < g of (S - 2 - S3_NR g')
+    return g * (S - 2) - (int64_t)S3_NR * (g * (g - 1) / 2);
+}
+__host__ __device__ inline int64_t s3_rows(int64_t S) {
+    const int64_t ng = (S - 3) / S3_NR + 1;  // groups with at least one row (S >= 3)
+    return s3_rowoff(S, ng);
+}
+
+// record of (i1, j), i1 = S3_NR g + r, in row R = s3_rowoff(S, g) + j - S3_NR g - 1:
+//   rec[(R S3_NR + r) 4 + {0, 1, 2, 3}] = {v, 1/d_j, z_j / s_j, p}
 // with v = G[i1][j], d_j = 1 - v^2, s_j = sqrt(d_j), z_j = (b_j - v b_i1) / s_j,
 // p = c - b_i1^2 - z_j^2 (the SSE of the pair); p = NaN (fails every
 // comparison) unless i1 < j, column i1 is live and d_j > RANK_EPS.
 // (its grid also does the per-search initialisation of search_init_kernel)
+// Grid: x over (j, r) of one group, y over groups (blockIdx.y = g).
 __global__ __launch_bounds__(256) void rec3_kernel(Ctx c, double *__restrict__ rec) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    search_init_body(c, e, 3, SUBP, JBLK, 1);
+    const int64_t ex = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t g = blockIdx.y;
+    search_init_body(c, g * (int64_t)gridDim.x * blockDim.x + ex, ex == 0 && g == 0, 3, SUBP, JBLK, 1);
     const int64_t S = c.S;
-    const int64_t ng = (S + S3_NR - 1) / S3_NR;
-    if (e >= ng * S * S3_NR) return;
-    const int r = (int)(e % S3_NR);
-    const int64_t gj = e / S3_NR;
-    const int64_t j = gj % S;
-    const int64_t i1 = (gj / S) * S3_NR + r;
+    const int r = (int)(ex % S3_NR);
+    const int64_t j = S3_NR * g + 1 + ex / S3_NR;
+    if (g > (S - 3) / S3_NR || j > S - 2) return;
+    const int64_t i1 = S3_NR * g + r;
+    const int64_t e = (s3_rowoff(S, g) + j - S3_NR * g - 1) * S3_NR + r;
     double v = 0.0, al = 0.0, zs = 0.0, p = __builtin_nan("");
     if (i1 < j && Gat(c, i1, i1, 0) > RANK_EPS) {
         const double zp = c.bhat[i1 * c.TP];
@@ -1221,9 +1238,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S3_WPE))) v
     const double *__restrict__ Gb = c.G;
     const int TP = c.TP;
 
-    // tiles are dealt round-robin over the waves: their costs are nearly
-    // equal, and a shared counter would serialise on one address
-    for (uint64_t t = (uint64_t)blockIdx.x * SEARCH_WAVES + wave;; t += (uint64_t)gridDim.x * SEARCH_WAVES) {
+    // Tiles are dealt round-robin over the waves (their costs are nearly
+    // equal; a shared counter would serialise on one address), XCD-aware:
+    // workgroups are placed on the eight XCDs in turn (workgroup b on XCD
+    // b mod 8), and runs of S3_XCD_RUN consecutive tiles, which share blocks
+    // of G, go to the waves of one XCD and its L2.
+    const bool xa = (gridDim.x % S3_XCDS) == 0;
+    const uint64_t xcd = xa ? blockIdx.x % S3_XCDS : 0;
+    const uint64_t nx = xa ? S3_XCDS : 1;
+    const uint64_t U = (uint64_t)gridDim.x / nx * SEARCH_WAVES;      // waves per XCD
+    const uint64_t u0 = (uint64_t)blockIdx.x / nx * SEARCH_WAVES + wave;
+    for (uint64_t sx = u0;; sx += U) {
+        const uint64_t t = ((sx / S3_XCD_RUN) * nx + xcd) * S3_XCD_RUN + sx % S3_XCD_RUN;
         if (t >= ntiles) break;
         // tile -> (j-block, column chunk, group)
         int64_t lo = 0, hi = nb - 1;
@@ -1234,9 +1260,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S3_WPE))) v
         const int64_t jb = lo;
         int64_t kc0, ng;
         s3_block(S, jb, kc0, ng);
-        // column chunk fastest: the four waves of a workgroup usually take
-        // four chunks of one (block, group) and share its records in the
-        // scalar cache
+        // column chunk fastest: the waves of a workgroup usually take chunks
+        // of one (block, group) and share its records in the scalar cache;
+        // a run of tiles on one XCD covers a few groups over the same chunks
+        // of G
         const int64_t nkb = s3_nchunks(S) - kc0;
         const int64_t rem = (int64_t)(t - tcum[jb]);
         const int64_t kcx = kc0 + rem % nkb;
@@ -1287,7 +1314,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S3_WPE))) v
             reinterpret_cast<const char *>(Gb + (((j0 >> 6) * nt) << 12));
         const uint32_t voff = (uint32_t)((((kk >> 6) << 12) + (kk & 63) + ((jlo & 63) << 6)) * 8);
         // records of row jlo + x are 128 bytes at recj + 128 x (uniform)
-        const char *__restrict__ recj = reinterpret_cast<const char *>(rec + (size_t)(g * S + jlo) * (S3_NR * 4));
+        const char *__restrict__ recj =
+            reinterpret_cast<const char *>(rec + (size_t)(s3_rowoff(S, g) + jlo - S3_NR * g - 1) * (S3_NR * 4));
         int nq = 0;
         auto sweep = [&](auto diagc) {
             constexpr bool DIAG = decltype(diagc)::value;
@@ -2155,10 +2183,13 @@ int launch_search(const Ctx &c, const SearchCall &sc, hipStream_t st) {
         const bool s3 = D == 3 && !MT && c.rec3 != nullptr && s3_tiles_host(c.S) < (1ull << 31);
         if (s3) {
             // record table + initialisation in one launch (its grid covers the binomial table)
-            int64_t nrec = (c.S + S3_NR - 1) / S3_NR * c.S * S3_NR;
+            // x: the rows of one group (j, r); y: groups; the grid also covers
+            // the binomial table of the initialisation
+            const int64_t ngr = (c.S - 3) / S3_NR + 1;
+            int64_t bx = ((c.S - 2) * S3_NR + 255) / 256;
             const int64_t ninit = (int64_t)init_blocks * 256;
-            if (nrec < ninit) nrec = ninit;
-            hipLaunchKernelGGL(rec3_kernel, dim3((unsigned)((nrec + 255) / 256)), dim3(256), 0, st, c, c.rec3);
+            if (bx * 256 * ngr < ninit) bx = (ninit / ngr + 255) / 256 + 1;
+            hipLaunchKernelGGL(rec3_kernel, dim3((unsigned)bx, (unsigned)ngr), dim3(256), 0, st, c, c.rec3);
         } else {
             hipLaunchKernelGGL(search_init_kernel, dim3(init_blocks), dim3(256), 0, st, c, D, a.R, a.JB, 0);
         }

@@ -38,6 +38,22 @@ def test_grid_size_does_not_change_results():
     from paper_2502_20072_amd import SissoError
     with pytest.raises(SissoError):
         s.set_search_grid(0)
+    s.close()
+    # several column chunks and tile rows; grids that are and are not a
+    # multiple of the eight XCDs the tiles are dealt over
+    p = make_problem(n=300, S=300, D=3, k=50, seed=613, beta=(1.5, -0.8, 0.6), sigma=0.05)
+    _say("grid invariance S=300 n=300 D=3 k=50")
+    s = L0Search(p.F, p.y, p.task_offsets, D_max=3, k_max=50)
+    s.gram()
+    ref = None
+    for w in (5, 1000, 1024, 1536):
+        s.set_search_grid(w)
+        s.search(3, 50)
+        out = s.topk()
+        if ref is None:
+            ref = out
+        else:
+            assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1]), f"grid {w} differs"
     with pytest.raises(SissoError):
         s.set_search_grid(4096)
     s.close()

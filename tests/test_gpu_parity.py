@@ -252,3 +252,28 @@ def test_fewer_valid_tuples_than_k():
     assert np.sum(np.isfinite(gsse)) == 4
     oidx, osse, _ = oracle.topk(F, p.y, 2, 6)
     compare_topk(q, 2, 6, gidx, gsse, oidx, osse)
+
+
+@pytest.mark.parametrize("S,n,seed", [(3, 12, 90), (5, 20, 91), (129, 70, 92), (131, 60, 93), (257, 50, 94)])
+def test_d3_one_task_tile_edges(S, n, seed):
+    """One task, D = 3 (pair-record table, two columns per lane, 32-row by
+    128-column tiles): sizes at and past the tile and chunk edges (S - 2 rows,
+    S odd, S just past 128 and 256), and columns that make pairs rank
+    deficient on both sides of a chunk edge."""
+    _say(f"d3 one task S={S} n={n} seed={seed}")
+    p = tiny_problem(seed, S=S, n=n, D=3, sigma=0.2)
+    F = p.F.copy()
+    if S > 130:
+        F[128] = F[127]                      # duplicate across the first chunk edge
+        F[130] = 2.0                         # constant column in the second chunk
+        F[S - 1] = 0.5 * F[1] - F[2] + 3.0   # exact combination, last column
+    from synth.problems import Problem
+    q = Problem(F=F, y=p.y, task_offsets=p.task_offsets, planted=[], D=3, k=40, exprs=p.exprs, meta={})
+    k = min(40, math.comb(S, 3))
+    gidx, gsse, _ = _run(q, 3, k)
+    oidx, osse, _ = oracle.topk(F, p.y, 3, k)
+    compare_topk(q, 3, k, gidx, gsse, oidx, osse)
+    if S > 130:
+        for t in gidx:
+            t = set(int(v) for v in t)
+            assert not {127, 128} <= t and 130 not in t and not {1, 2, S - 1} <= t
