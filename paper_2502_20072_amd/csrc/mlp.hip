@@ -210,9 +210,17 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int WT = H + 8;  // LDS row stride of the staged W2 (BF16 elements)
 
+template <int CTRL>
+__device__ inline float dpp_f32(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+
 __device__ inline int hid_of(int s, int g, int e) { return 32 * s + (e < 4 ? 4 * g + e : 16 + 4 * g + (e - 4)); }
 
-__global__ __launch_bounds__(256) void mlp_infer_bf16_kernel(const float *__restrict__ P, const float *__restrict__ x,
+// Register budget for two waves per SIMD (the W2 fragments are reused by
+// every sample group; one wave per SIMD left every load latency exposed).
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void mlp_infer_bf16_kernel(
+    const float *__restrict__ P, const float *__restrict__ x,
                                                              int64_t n, float *__restrict__ out) {
     __shared__ __attribute__((aligned(16))) __bf16 w2t[H][WT];  // [output j][MFMA k order]
     for (int e = threadIdx.x; e < H * H; e += 256) {
@@ -245,20 +253,26 @@ __global__ __launch_bounds__(256) void mlp_infer_bf16_kernel(const float *__rest
         w3r[cb] = P[OW3 + 16 * cb + r16];
     }
     const float b3 = P[OB3];
+    // the inputs of the next group of samples are loaded while this one is
+    // computed (lanes of k-group 0 hold the 8 inputs of sample r16)
+    auto load_x = [&](int64_t gs, float4 &lo, float4 &hi) {
+        const int64_t i = gs + wave * 16 + r16;
+        lo = (float4){0.f, 0.f, 0.f, 0.f};
+        hi = (float4){0.f, 0.f, 0.f, 0.f};
+        if (g == 0 && i < n) {
+            lo = reinterpret_cast<const float4 *>(x + i * IN)[0];
+            hi = reinterpret_cast<const float4 *>(x + i * IN)[1];
+        }
+    };
+    float4 xlo, xhi;
+    load_x((int64_t)blockIdx.x * 64, xlo, xhi);
     for (int64_t g0 = (int64_t)blockIdx.x * 64; g0 < n; g0 += (int64_t)gridDim.x * 64) {
         const int64_t i0 = g0 + wave * 16;
-        // x^T as the B operand: lanes of k-group 0 hold the 8 inputs of sample r16
+        // x^T as the B operand
         bf16x8 Bx;
-        {
-            const int64_t i = i0 + r16;
-            float4 lo = {0.f, 0.f, 0.f, 0.f}, hi = {0.f, 0.f, 0.f, 0.f};
-            if (g == 0 && i < n) {
-                lo = reinterpret_cast<const float4 *>(x + i * IN)[0];
-                hi = reinterpret_cast<const float4 *>(x + i * IN)[1];
-            }
-            Bx[0] = (__bf16)lo.x; Bx[1] = (__bf16)lo.y; Bx[2] = (__bf16)lo.z; Bx[3] = (__bf16)lo.w;
-            Bx[4] = (__bf16)hi.x; Bx[5] = (__bf16)hi.y; Bx[6] = (__bf16)hi.z; Bx[7] = (__bf16)hi.w;
-        }
+        Bx[0] = (__bf16)xlo.x; Bx[1] = (__bf16)xlo.y; Bx[2] = (__bf16)xlo.z; Bx[3] = (__bf16)xlo.w;
+        Bx[4] = (__bf16)xhi.x; Bx[5] = (__bf16)xhi.y; Bx[6] = (__bf16)xhi.z; Bx[7] = (__bf16)xhi.w;
+        load_x(g0 + (int64_t)gridDim.x * 64, xlo, xhi);
         bf16x8 A2[H / 32];
 #pragma unroll
         for (int s = 0; s < H / 32; ++s)
@@ -285,9 +299,15 @@ __global__ __launch_bounds__(256) void mlp_infer_bf16_kernel(const float *__rest
         for (int cb = 0; cb < H / 16; ++cb)
 #pragma unroll
             for (int r = 0; r < 4; ++r) part[r] = fmaf(fmaxf(acc[cb][r] + b2r[cb], 0.f), w3r[cb], part[r]);
+        // sum over the 16 columns of a row: row-local DPP steps (lane ^ 1,
+        // lane ^ 2, mirror in 8, mirror in 16); every lane gets the row sum
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-            for (int m = 8; m >= 1; m >>= 1) part[r] += __shfl_xor(part[r], m);  // over the 16 columns of a row
+        for (int r = 0; r < 4; ++r) {
+            part[r] += dpp_f32<0xB1>(part[r]);
+            part[r] += dpp_f32<0x4E>(part[r]);
+            part[r] += dpp_f32<0x141>(part[r]);
+            part[r] += dpp_f32<0x140>(part[r]);
+        }
         if (r16 == 0) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
