@@ -109,6 +109,8 @@ def main() -> int:
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="before the timed region, copy a buffer of this many MiB three times with torch "
                          "(a plain copy kernel of known size, to calibrate HBM byte counters)")
+    ap.add_argument("--search-grid", type=int, default=0,
+                    help="fix the search grid (workgroups) instead of autotuning it, e.g. for counter runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the search shards by "
@@ -149,7 +151,11 @@ def main() -> int:
     stream = s.stream
     # launch tuning on the problem itself (changes no arithmetic), before timing
     s.gram()
-    grid = s.autotune(D, k, args.tune_cache)
+    if args.search_grid > 0:
+        s.set_search_grid(args.search_grid)
+        grid = args.search_grid
+    else:
+        grid = s.autotune(D, k, args.tune_cache)
 
     def step():
         s.gram()

@@ -166,25 +166,27 @@ __device__ void list_insert(double *Ls, uint64_t *Lr, int KP, double s, uint64_t
     }
     if (pos >= KP) return;
     if (Ls[pos] == s && Lr[pos] == r) return;  // the same tuple, offered twice (list search)
-    double vs[KP_MAX / 64];
-    uint64_t vr[KP_MAX / 64];
-#pragma unroll
-    for (int m = 0; m < KP_MAX / 64; ++m) {
+    // shift the entries above pos up by one, highest chunk of 64 first: a
+    // chunk is read whole before it is written, and its lowest lane reads the
+    // top entry of the chunk below before that chunk is written (few live
+    // registers, whatever the list length)
+    for (int m = nper - 1; m >= 0 && 64 * m + 63 > pos; --m) {
         const int e = lane + 64 * m;
-        if (m < nper && e > pos) {
-            vs[m] = Ls[e - 1];
-            vr[m] = Lr[e - 1];
+        const bool mv = e > pos;
+        double vs = 0.0;
+        uint64_t vr = 0;
+        if (mv) {
+            vs = Ls[e - 1];
+            vr = Lr[e - 1];
         }
-    }
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    __builtin_amdgcn_wave_barrier();
-#pragma unroll
-    for (int m = 0; m < KP_MAX / 64; ++m) {
-        const int e = lane + 64 * m;
-        if (m < nper && e > pos) {
-            Ls[e] = vs[m];
-            Lr[e] = vr[m];
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_wave_barrier();
+        if (mv) {
+            Ls[e] = vs;
+            Lr[e] = vr;
         }
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_wave_barrier();
     }
     if (lane == 0) {
         Ls[pos] = s;
@@ -1412,14 +1414,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S3_WPE))) v
             const unsigned long long fm[2] = {s_q[wave][e][0], s_q[wave][e][1]};
             const double *rp = reinterpret_cast<const double *>(recj + (size_t)jr * 128);
             const double2 gv = *reinterpret_cast<const double2 *>(gtile + (voff + (uint32_t)jr * 512u));
+            // (r, sl) are wave-uniform here: pick the k-data by selects, so
+            // the arrays stay in registers (an indexed read would move them to
+            // scratch memory, stored on every tile)
+            auto pick = [&](const double (&arr)[S3_NR][2], int r, int sl) {
+                double v = arr[0][0];
+#pragma unroll
+                for (int q = 0; q < S3_NR; ++q)
+#pragma unroll
+                    for (int h = 0; h < 2; ++h)
+                        if (q == r && h == sl) v = arr[q][h];
+                return v;
+            };
             for (int r = 0; r < S3_NR; ++r) {
                 const double v = rp[4 * r], al = rp[4 * r + 1], zs = rp[4 * r + 2], p = rp[4 * r + 3];
                 for (int sl = 0; sl < 2; ++sl) {
                     const double gg = sl ? gv.y : gv.x;
                     const int64_t k = sl ? k1 : k0;
-                    const double u = fma(-v, w[r][sl], gg);
-                    const double d = fma(-al, u * u, dq[r][sl]);
-                    const double z = fma(-zs, u, zq[r][sl]);
+                    const double u = fma(-v, pick(w, r, sl), gg);
+                    const double d = fma(-al, u * u, pick(dq, r, sl));
+                    const double z = fma(-zs, u, pick(zq, r, sl));
                     const double es = (d > RANK_EPS) ? p - z * z / d : INF;
                     const double thc = fmin(theta_f, Ls[KP - 1]);
                     bool take = ((fm[sl] >> lane) & 1ull) && k < S && k > j && es <= thc;
@@ -1655,19 +1669,42 @@ __global__ __launch_bounds__(256) void list_search_kernel(Ctx c, const int32_t *
                     int pos = 0;
 #pragma unroll
                     for (int a = 0; a < M; ++a) pos += P[a] < kc;
+                    // pos differs across lanes: the prefix values are picked by
+                    // selects over constant indexes, so gP, bP and gk stay in
+                    // registers (an indexed read would put them in scratch memory)
+                    // (each candidate passes through an empty asm, so the
+                    // compiler cannot fold the selects back into an indexed load)
+                    auto opaque = [](double x) {
+                        __asm__ volatile("" : "+v"(x));
+                        return x;
+                    };
+                    auto pick1 = [&](const double (&arr)[M], int a) {
+                        double r = opaque(arr[0]);
+#pragma unroll
+                        for (int q = 1; q < M; ++q) r = a == q ? opaque(arr[q]) : r;
+                        return r;
+                    };
+                    auto pickg = [&](int a, int b) {  // b <= a (lower triangle)
+                        double r = opaque(gP[0][0]);
+#pragma unroll
+                        for (int q = 1; q < M; ++q)
+#pragma unroll
+                            for (int q2 = 0; q2 <= q; ++q2) r = (a == q && b == q2) ? opaque(gP[q][q2]) : r;
+                        return r;
+                    };
                     double g4[M + 1][M + 1], b4[M + 1];
 #pragma unroll
                     for (int u = 0; u <= M; ++u) {
                         const int au = u < pos ? u : u - 1;  // prefix slot of tuple slot u (u != pos)
-                        b4[u] = u == pos ? bk : bP[au];
+                        b4[u] = u == pos ? bk : pick1(bP, au);
 #pragma unroll
                         for (int v2 = 0; v2 <= u; ++v2) {
                             const int av = v2 < pos ? v2 : v2 - 1;
                             double val;
                             if (u == pos && v2 == pos) val = gkk;
-                            else if (u == pos) val = gk[av];
-                            else if (v2 == pos) val = gk[au];
-                            else val = gP[au][av];
+                            else if (u == pos) val = pick1(gk, av);
+                            else if (v2 == pos) val = pick1(gk, au);
+                            else val = pickg(au, av);
                             g4[u][v2] = val;
                         }
                     }
@@ -1969,38 +2006,54 @@ __global__ __launch_bounds__(256) void rescore_kernel(Ctx c) {
         if (tid < nacc) red[tid][0] = ((red[tid][0] + red[tid][1]) + red[tid][2]) + red[tid][3];
         __syncthreads();
         if (tid == 0) {
-            double M[D][D], v[D], L[D][D], z[D];
+            // fully unrolled (D is fixed), so the small matrices stay in registers
+            double M[D][D], v[D], L[D][D], z[D], bt[D];
             int e = 0;
+#pragma unroll
             for (int m = 0; m < D; ++m)
+#pragma unroll
                 for (int l = 0; l <= m; ++l) {
                     M[m][l] = red[e][0];
                     M[l][m] = red[e][0];
                     ++e;
                 }
+#pragma unroll
             for (int m = 0; m < D; ++m) v[m] = red[e++][0];
-            int ok = 1;
-            for (int m = 0; m < D && ok; ++m) {
+            // Cholesky; once a pivot fails the rest is computed on a unit
+            // pivot and discarded
+            bool ok = true;
+#pragma unroll
+            for (int m = 0; m < D; ++m) {
+#pragma unroll
                 for (int jx = 0; jx < m; ++jx) {
                     double s = M[m][jx];
+#pragma unroll
                     for (int l = 0; l < jx; ++l) s -= L[m][l] * L[jx][l];
                     L[m][jx] = s / L[jx][jx];
                 }
                 double d = M[m][m];
+#pragma unroll
                 for (int l = 0; l < m; ++l) d -= L[m][l] * L[m][l];
-                if (!(M[m][m] > 0.0) || !(d > RANK_EPS * M[m][m])) ok = 0;
-                else L[m][m] = sqrt(d);
+                ok = ok && (M[m][m] > 0.0) && (d > RANK_EPS * M[m][m]);
+                L[m][m] = ok ? sqrt(d) : 1.0;
             }
             if (ok) {
+#pragma unroll
                 for (int m = 0; m < D; ++m) {
                     double s = v[m];
+#pragma unroll
                     for (int l = 0; l < m; ++l) s -= L[m][l] * z[l];
                     z[m] = s / L[m][m];
                 }
+#pragma unroll
                 for (int m = D - 1; m >= 0; --m) {
                     double s = z[m];
-                    for (int l = m + 1; l < D; ++l) s -= L[l][m] * s_beta[l];
-                    s_beta[m] = s / L[m][m];
+#pragma unroll
+                    for (int l = m + 1; l < D; ++l) s -= L[l][m] * bt[l];
+                    bt[m] = s / L[m][m];
                 }
+#pragma unroll
+                for (int m = 0; m < D; ++m) s_beta[m] = bt[m];
             }
             s_ok = ok;
         }
