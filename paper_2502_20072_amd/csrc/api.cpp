@@ -104,9 +104,11 @@ static Layout compute_layout(int64_t n_total, int64_t S, int T, int D_max, int k
     {
         const int64_t ng3 = S >= 3 ? (S - 3) / 4 + 1 : 0;
         const int64_t rows3 = ng3 * (S - 2) - 4 * (ng3 * (ng3 - 1) / 2);
-        L.rec3_bytes = (D_max >= 3 && T == 1 && S >= 3) ? (size_t)rows3 * 16 * d : 0;
+        L.rec3_bytes = (D_max >= 3 && S >= 3) ? (size_t)rows3 * 16 * d : 0;
     }
     L.rec3 = take(L.rec3_bytes);
+    L.G1_bytes = (D_max >= 3 && S >= 3 && T > 1) ? Sp * Sp * d : 0;
+    L.G1 = take(L.G1_bytes);
     L.lists = take((size_t)nlists * L.KP * 2 * d + (size_t)nlists * L.KP * 2 * d);
     L.merged = take((size_t)L.KP * 2 * d);
     L.rescored = take((size_t)L.KP * d);
@@ -167,8 +169,10 @@ static void carve(sisso_l0 *h) {
     c.work_counter = (unsigned int *)(p + 8);
     c.cand_counter = (unsigned int *)(p + 12);
     c.pre_count = (int32_t *)(p + 16);
+    c.pre_done = (unsigned int *)(p + 20);
     c.stats = (uint64_t *)(p + 24);
     c.merge_count = (unsigned int *)(p + 56);
+    c.tstar = (int32_t *)(p + 60);
     p += 64;
     c.cum = (uint64_t *)p;
     p += (size_t)(c.S / 4 + 8) * sizeof(uint64_t);
@@ -180,6 +184,7 @@ static void carve(sisso_l0 *h) {
     p += align256((size_t)PRE_Q * c.S * sizeof(double));
     c.btab = (uint64_t *)p;
     c.rec3 = L.rec3_bytes ? (double *)(base + L.rec3) : nullptr;
+    c.G1 = L.G1_bytes ? (double *)(base + L.G1) : c.G;
     const int64_t nl = L.nwaves;
     char *q = base + L.lists;
     c.list_sse = (double *)q;

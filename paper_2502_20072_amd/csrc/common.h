@@ -208,8 +208,10 @@ struct Layout {
     size_t lp_slices;  // bf16 [NS][S][nchunk * LP_XC] precision form: slices
     size_t stat_bits;  // uint64 [4] error report scratch
     size_t pre;        // pre-pass scratch
-    size_t rec3;       // D = 3, one task: pair records double [ceil(S/4)][S][4][4] (0 bytes otherwise)
+    size_t rec3;       // D = 3: pair records of the filter task, double [ceil(S/4)][S][4][4] (0 bytes otherwise)
     size_t rec3_bytes;
+    size_t G1;         // D = 3, several tasks: the filter task's matrix alone, double [S][S] tiled (0 bytes otherwise)
+    size_t G1_bytes;
     size_t lists;      // per-wave top lists: (double sse, uint64 rank) [nwaves][KP]
     size_t merged;     // merged candidates [KP] (sse, rank)
     size_t rescored;   // rescored candidates [KP] (sse, rank)

@@ -24,11 +24,14 @@ __device__ inline double wave_sum(double v) {
 
 // One workgroup: clears the status words, then wave w handles tasks w,
 // w + 4, ... (so no other workgroup can set a status bit before the clear).
+// Last, it names the filter task: the task of largest c_t (the first such),
+// whose SSE alone is a lower bound of any tuple's SSE summed over tasks.
 __global__ __launch_bounds__(256) void stats_y_kernel(const double *__restrict__ y,
                                                       const int64_t *__restrict__ off, int T,
                                                       double *__restrict__ ybar,
                                                       double *__restrict__ cyy,
-                                                      uint32_t *__restrict__ flags) {
+                                                      uint32_t *__restrict__ flags,
+                                                      int32_t *__restrict__ tstar) {
     const int lane = threadIdx.x & 63;
     if (threadIdx.x < 64) flags[threadIdx.x] = 0u;
     __syncthreads();
@@ -56,6 +59,13 @@ __global__ __launch_bounds__(256) void stats_y_kernel(const double *__restrict__
         ybar[t] = m;
         cyy[t] = ss;
     }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int best = 0;
+        for (int t = 1; t < T; ++t)
+            if (cyy[t] > cyy[best]) best = t;
+        *tstar = best;
     }
 }
 
@@ -272,9 +282,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 // diagonal is 1 for a non-constant column and 0 for a constant one; padding
 // rows/columns and padded tasks are written as zeros.
 constexpr int FIN_ROWS = 16;  // tile rows per finishing workgroup (divides 64)
+//
+// With several tasks the filter task's tiles are also written, in the
+// one-task layout, to G1 (bitwise the values written to G).
 __global__ __launch_bounds__(256) void gram_finish_kernel(const double *__restrict__ part, int64_t S, int T,
                                                           int TP, int nsplit, const double *__restrict__ inv_s,
-                                                          double *__restrict__ G, int64_t nt) {
+                                                          double *__restrict__ G, int64_t nt,
+                                                          double *__restrict__ G1,
+                                                          const int32_t *__restrict__ tstar) {
     __shared__ double tr[GT][FIN_ROWS + 1];
     const int64_t npair = nt * (nt + 1) / 2;
     const int qr = (int)(blockIdx.x % (GT / FIN_ROWS));  // row band of the tile pair
@@ -288,6 +303,7 @@ __global__ __launch_bounds__(256) void gram_finish_kernel(const double *__restri
     }
     const int64_t tk = ti + pr;
     const double *ist = inv_s + (int64_t)t * S;
+    const bool one = G1 != nullptr && t == *tstar;  // also write the one-task copy
     // each thread owns PER elements of rows [FIN_ROWS qr, FIN_ROWS (qr + 1));
     // the split partials are summed split by split, two splits of loads in
     // flight (indices clamped in range, out-of-range elements masked after)
@@ -323,6 +339,7 @@ __global__ __launch_bounds__(256) void gram_finish_kernel(const double *__restri
             v = i == k ? (ist[i] > 0.0 ? 1.0 : 0.0) : acc[m] * (ist[a] * ist[cc]);
         }
         G[((((ti * nt + tk) << 12) + (li << 6) + lk)) * TP + t] = v;
+        if (one) G1[((ti * nt + tk) << 12) + (li << 6) + lk] = v;
         tr[lk][li - FIN_ROWS * qr] = v;
         if (t == T - 1)
             for (int tp = T; tp < TP; ++tp) G[((((ti * nt + tk) << 12) + (li << 6) + lk)) * TP + tp] = 0.0;
@@ -334,6 +351,7 @@ __global__ __launch_bounds__(256) void gram_finish_kernel(const double *__restri
         // holds columns [FIN_ROWS qr, FIN_ROWS (qr + 1)) of every such row
         const int li = e / FIN_ROWS, lk = FIN_ROWS * qr + e % FIN_ROWS;
         G[((((tk * nt + ti) << 12) + (li << 6) + lk)) * TP + t] = tr[li][lk - FIN_ROWS * qr];
+        if (one) G1[((tk * nt + ti) << 12) + (li << 6) + lk] = tr[li][lk - FIN_ROWS * qr];
         if (t == T - 1)
             for (int tp = T; tp < TP; ++tp) G[((((tk * nt + ti) << 12) + (li << 6) + lk)) * TP + tp] = 0.0;
     }
@@ -356,7 +374,8 @@ int launch_untile(const Ctx &c, int t, double *dst, hipStream_t st) {
 // ------------------------------------------------------------- launchers
 int launch_stats(const Ctx &c, hipStream_t st) {
     phase_begin(c, SISSO_PHASE_STATS, st);
-    hipLaunchKernelGGL(stats_y_kernel, dim3(1), dim3(256), 0, st, c.y, c.off_dev, c.T, c.ybar, c.cyy, c.flags);
+    hipLaunchKernelGGL(stats_y_kernel, dim3(1), dim3(256), 0, st, c.y, c.off_dev, c.T, c.ybar, c.cyy, c.flags,
+                       c.tstar);
     const int64_t jobs = c.S * c.T;
     hipLaunchKernelGGL(stats_x_kernel, dim3((unsigned)((jobs + 3) / 4)), dim3(256), 0, st, c.F, c.y,
                        c.off_dev, c.n_total, c.S, c.T, c.TP, c.ybar, c.mu, c.inv_s, c.bhat, c.flags);
@@ -376,7 +395,7 @@ int launch_gram(const Ctx &c, hipStream_t st) {
     }
     const int64_t npair64 = c.Gnt * (c.Gnt + 1) / 2;
     hipLaunchKernelGGL(gram_finish_kernel, dim3((unsigned)(npair64 * c.T * (GT / FIN_ROWS))), dim3(256), 0, st, c.part, c.S, c.T,
-                       c.TP, c.nsplit, c.inv_s, c.G, c.Gnt);
+                       c.TP, c.nsplit, c.inv_s, c.G, c.Gnt, c.G1 != c.G ? c.G1 : nullptr, c.tstar);
     phase_end(c, SISSO_PHASE_GRAM, st);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }

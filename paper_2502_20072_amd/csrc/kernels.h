@@ -29,9 +29,12 @@ struct Ctx {
     uint64_t *btab;                  // binomials C(n, r), r <= SISSO_MAX_D, n <= S
     int32_t *pre_prefix;             // pre-pass: chosen prefixes [PRE_Q][SISSO_MAX_D]
     int32_t *pre_count;              // pre-pass: number of chosen prefixes
+    unsigned int *pre_done;          // pre-pass: extension blocks finished (the last one pools)
     double *pre_sse;                 // pre-pass: extension scores [PRE_Q][S]
     double *pre_bound;               // pre-pass: per-prefix L-th best [PRE_Q]
-    double *rec3;                    // D = 3, one task: pair records [ceil(S/4)][S][4][4] (null if absent)
+    double *rec3;                    // D = 3: pair records of the filter task [ceil(S/4)][S][4][4] (null if absent)
+    double *G1;                      // the filter task's matrix alone, one-task tiled layout (G itself when T = 1)
+    int32_t *tstar;                  // filter task: the task of largest |y_t - ybar_t|^2 (0 when T = 1)
     double *list_sse;                // per-wave lists [nwaves][KP]
     uint64_t *list_rank;
     double *cand_sse;                // merge: compacted candidates [nwaves * KP]

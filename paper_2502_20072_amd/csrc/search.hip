@@ -448,7 +448,10 @@ __global__ __launch_bounds__(PRE_WG) void pre_select_kernel(Ctx c) {
     __shared__ SelScratch sc;
     const int tid = threadIdx.x;
     constexpr int q = D - 1;
-    if (tid == 0) *c.pre_count = 0;
+    if (tid == 0) {
+        *c.pre_count = 0;
+        *c.pre_done = 0;
+    }
     // 1. the PRE_M most relevant full-rank features (up to the last
     //    histogram bin), in increasing index order
     const int N = gather_candidates(key, id, c.S, [&](int64_t j) {
@@ -552,6 +555,34 @@ __global__ __launch_bounds__(PRE_WG) void pre_extend_kernel(Ctx c, int ranged, u
     // at least L of the kept candidates (distinct real tuples) are <= the bound
     const double bound = block_threshold(key, N, L, sc);
     if (tid == 0) c.pre_bound[qq] = bound;
+    if (c.T == 1) return;
+    // several tasks: the tuples of all blocks are distinct, so the KP-th
+    // smallest of their pooled scores is a bound as well, and usually far
+    // below the largest per-block one (the weakest prefix no longer sets it).
+    // The last block to finish computes it.
+    const int nk = N < c.S ? N : (int)c.S;
+    for (int x = tid; x < nk; x += PRE_WG) c.pre_sse[(int64_t)qq * c.S + x] = key[x];
+    __shared__ int s_last;
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) s_last = atomicAdd(c.pre_done, 1u) == (unsigned)Q - 1u;  // blocks qq >= Q left above
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    const int KP = c.KP;
+    const int64_t npool = (int64_t)Q * c.S;
+    const int NP = gather_candidates(key, id, npool, [&](int64_t x) {
+        // (every block kept the same count nk)
+        return x % c.S < nk ? __hip_atomic_load(&c.pre_sse[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : INF;
+    });
+    __syncthreads();
+    const double pooled = block_threshold(key, NP, KP, sc);
+    if (tid == 0 && pooled < INF) {
+        double mx = 0.0;
+        for (int b = 0; b < Q; ++b) mx = fmax(mx, c.pre_bound[b]);
+        const double th = fmin(mx, pooled);
+        for (int b = 0; b < Q; ++b) c.pre_bound[b] = th;
+    }
 }
 
 __device__ double theta0_from_prepass(const Ctx &c, int L, int KP) {
@@ -1151,15 +1182,19 @@ __global__ __launch_bounds__(256) void rec3_kernel(Ctx c, double *__restrict__ r
     if (g > (S - 3) / S3_NR || j > S - 2) return;
     const int64_t i1 = S3_NR * g + r;
     const int64_t e = (s3_rowoff(S, g) + j - S3_NR * g - 1) * S3_NR + r;
+    // the filter task's pair (i1, j) (the only task when T = 1)
+    const int ts = *c.tstar;
+    const double *G1 = c.G1;
+    const int64_t nt = c.Gnt;
     double v = 0.0, al = 0.0, zs = 0.0, p = __builtin_nan("");
-    if (i1 < j && Gat(c, i1, i1, 0) > RANK_EPS) {
-        const double zp = c.bhat[i1 * c.TP];
-        const double pp = c.cyy[0] - zp * zp;
-        const double g = Gat(c, i1, j, 0);
-        const double d = Gat(c, j, j, 0) - g * g;
+    if (i1 < j && G1[gidx(i1, i1, nt, 1, 0)] > RANK_EPS) {
+        const double zp = c.bhat[i1 * c.TP + ts];
+        const double pp = c.cyy[ts] - zp * zp;
+        const double g = G1[gidx(i1, j, nt, 1, 0)];
+        const double d = G1[gidx(j, j, nt, 1, 0)] - g * g;
         if (d > RANK_EPS) {
             const double sj = sqrt(d);
-            const double zn = (c.bhat[j * c.TP] - g * zp) / sj;
+            const double zn = (c.bhat[j * c.TP + ts] - g * zp) / sj;
             v = g;
             al = 1.0 / d;
             zs = zn / sj;
@@ -1214,6 +1249,10 @@ uint64_t s3_tiles_host(int64_t S) {
 #ifndef S3_WPE
 #define S3_WPE 4                      // waves per SIMD the register budget is sized for
 #endif
+// MT: several tasks (the sweep filters on the filter task alone, the exact
+// path sums every task); a template parameter so that the one-task kernel's
+// registers are not shaped by the several-task exact path
+template <bool MT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S3_WPE))) void search3_kernel(Ctx c, SearchArgs a, const double *__restrict__ rec,
                                                       const uint64_t *__restrict__ tcum) {
     extern __shared__ double smem[];
@@ -1237,8 +1276,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S3_WPE))) v
     const int64_t nb = s3_nblocks(S);
     const uint64_t ntiles = tcum[nb];
     const int64_t nt = c.Gnt;
-    const double *__restrict__ Gb = c.G;
+    // the filter task's matrix and statistics (the only task when T = 1)
+    const double *__restrict__ Gb = c.G1;
     const int TP = c.TP;
+    const int ts = *c.tstar;
+    const double *__restrict__ inv_st = c.inv_s + (int64_t)ts * S;
 
     // Tiles are dealt round-robin over the waves (their costs are nearly
     // equal; a shared counter would serialise on one address), XCD-aware:
@@ -1291,14 +1333,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S3_WPE))) v
             // G[k][k] is 1 for a live column and 0 for a constant one; the
             // contiguous 1/|x - mean| row says which (0 = constant)
             const int64_t kd1 = kv1 ? k1 : kk;
-            const double gd0 = c.inv_s[kk] > 0.0 ? 1.0 : 0.0;
-            const double gd1 = c.inv_s[kd1] > 0.0 ? 1.0 : 0.0;
-            const double b0 = c.bhat[kk * TP], b1 = c.bhat[kd1 * TP];
+            const double gd0 = inv_st[kk] > 0.0 ? 1.0 : 0.0;
+            const double gd1 = inv_st[kd1] > 0.0 ? 1.0 : 0.0;
+            const double b0 = c.bhat[kk * TP + ts], b1 = c.bhat[kd1 * TP + ts];
 #pragma unroll
             for (int r = 0; r < S3_NR; ++r) {
                 int64_t i1 = S3_NR * g + r;
                 if (i1 > S - 1) i1 = S - 1;
-                const double zp = c.bhat[i1 * TP];
+                const double zp = c.bhat[i1 * TP + ts];
                 const double2 wv = *reinterpret_cast<const double2 *>(Gb + gidx(i1, kk, nt, 1, 0));
                 w[r][0] = wv.x;
                 w[r][1] = wv.y;
@@ -1434,26 +1476,75 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S3_WPE))) v
                     const double u = fma(-v, pick(w, r, sl), gg);
                     const double d = fma(-al, u * u, pick(dq, r, sl));
                     const double z = fma(-zs, u, pick(zq, r, sl));
+                    const int32_t tup[3] = {(int32_t)(S3_NR * g + r), (int32_t)j, (int32_t)k};
+                    // the step's flag covers all four i1 of the group: this
+                    // i1's own terms decide (NaN records: i1 >= j or a rank
+                    // deficient pair).  One task: that is the SSE; several:
+                    // it is the filter task's SSE, a lower bound of the sum
                     const double es = (d > RANK_EPS) ? p - z * z / d : INF;
-                    const double thc = fmin(theta_f, Ls[KP - 1]);
-                    bool take = ((fm[sl] >> lane) & 1ull) && k < S && k > j && es <= thc;
-                    uint64_t rk = 0;
-                    if (take) {
-                        const int32_t tup[3] = {(int32_t)(S3_NR * g + r), (int32_t)j, (int32_t)k};
-                        rk = pack_tuple(tup, 3);
-                        if (a.ranged) {
-                            const uint64_t lr = lex_rank(BinomTab{c.btab, c.S}, c.S, 3, tup);
-                            if (lr < a.r0 || lr >= a.r1) take = false;
-                        }
+                    bool take = ((fm[sl] >> lane) & 1ull) && k < S && k > j &&
+                                es <= (MT ? theta_f : fmin(theta_f, Ls[KP - 1]));
+                    if (take && a.ranged) {
+                        const uint64_t lr = lex_rank(BinomTab{c.btab, c.S}, c.S, 3, tup);
+                        if (lr < a.r0 || lr >= a.r1) take = false;
                     }
                     unsigned long long m = __ballot(take);
-                    offered += (unsigned)__popcll(m);
+                    if (!MT) {
+                        const uint64_t rk = take ? pack_tuple(tup, 3) : 0;
+                        offered += (unsigned)__popcll(m);
+                        while (m) {
+                            const int src = __ffsll((long long)m) - 1;
+                            m &= m - 1;
+                            const double cs = __shfl(es, src);
+                            const uint64_t cr = (uint64_t)__shfl((long long)rk, src);
+                            list_insert(Ls, Lr, KP, cs, cr);
+                        }
+                        continue;
+                    }
+                    // several tasks: the passing columns are scored over every
+                    // task, 64 / LT tuples at a time, LT lanes per tuple (lane
+                    // q LT + l sums the tasks t = l mod LT of tuple q), then a
+                    // butterfly sum and rank flag over each tuple's LT lanes
+                    const int LT = TP < 64 ? TP : 64;
+                    const int R = 64 / LT, slot = lane / LT;
                     while (m) {
-                        const int src = __ffsll((long long)m) - 1;
-                        m &= m - 1;
-                        const double cs = __shfl(es, src);
-                        const uint64_t cr = (uint64_t)__shfl((long long)rk, src);
-                        list_insert(Ls, Lr, KP, cs, cr);
+                        int src = -1;
+                        for (int q = 0; q < R; ++q) {
+                            const int sb = m ? __ffsll((long long)m) - 1 : -1;
+                            if (slot == q) src = sb;
+                            m &= m - 1;
+                        }
+                        const int32_t kq = (int32_t)__shfl((int)k, src < 0 ? 0 : src);
+                        double part = 0.0;
+                        bool okp = true;
+                        if (src >= 0) {
+                            const int32_t tq[3] = {tup[0], tup[1], kq};
+                            for (int t = lane % LT; t < c.T; t += LT) {
+                                double gm[3][3], bv[3];
+#pragma unroll
+                                for (int m2 = 0; m2 < 3; ++m2) {
+#pragma unroll
+                                    for (int j2 = 0; j2 <= m2; ++j2) gm[m2][j2] = Gat(c, tq[m2], tq[j2], t);
+                                    bv[m2] = c.bhat[(int64_t)tq[m2] * TP + t];
+                                }
+                                part += ne_sse_core<3>(gm, bv, c.cyy[t], okp);
+                            }
+                        }
+                        for (int o = 1; o < LT; o <<= 1) {
+                            part += __shfl_xor(part, o);
+                            okp = __shfl_xor((int)okp, o) != 0 && okp;
+                        }
+                        const double esv = okp ? part : INF;
+                        for (int q = 0; q < R; ++q) {
+                            if (__shfl(src, q * LT) < 0) break;
+                            const double v2 = __shfl(esv, q * LT);
+                            const int32_t kv = __shfl(kq, q * LT);
+                            if (v2 <= fmin(theta_f, Ls[KP - 1])) {
+                                const int32_t tv[3] = {tup[0], tup[1], kv};
+                                ++offered;
+                                list_insert(Ls, Lr, KP, v2, pack_tuple(tv, 3));
+                            }
+                        }
                     }
                 }
             }
@@ -2233,7 +2324,9 @@ int launch_search(const Ctx &c, const SearchCall &sc, hipStream_t st) {
     } else {
         phase_begin(c, SISSO_PHASE_PREPASS, st);
         // one task, D = 3: record table + tile sweep (tile count within the 32-bit work counter)
-        const bool s3 = D == 3 && !MT && c.rec3 != nullptr && s3_tiles_host(c.S) < (1ull << 31);
+        // D = 3: the record-table sweep, on the filter task's matrix when
+        // there are several tasks
+        const bool s3 = D == 3 && c.rec3 != nullptr && s3_tiles_host(c.S) < (1ull << 31);
         if (s3) {
             // record table + initialisation in one launch (its grid covers the binomial table)
             // x: the rows of one group (j, r); y: groups; the grid also covers
@@ -2255,8 +2348,11 @@ int launch_search(const Ctx &c, const SearchCall &sc, hipStream_t st) {
         phase_begin(c, SISSO_PHASE_SEARCH, st);
         const size_t nrec = MT ? (size_t)a.JB * c.TP : (size_t)SEARCH_WG;
         const size_t lds = lds_lists + nrec * RECW * sizeof(double) + (size_t)64 * SUBW * sizeof(double);
-        if (s3)
-            hipLaunchKernelGGL(search3_kernel, dim3(c.search_wgs), dim3(SEARCH_WG), lds_lists, st, c, a,
+        if (s3 && MT)
+            hipLaunchKernelGGL(search3_kernel<true>, dim3(c.search_wgs), dim3(SEARCH_WG), lds_lists, st, c, a,
+                               (const double *)c.rec3, (const uint64_t *)c.cum);
+        else if (s3)
+            hipLaunchKernelGGL(search3_kernel<false>, dim3(c.search_wgs), dim3(SEARCH_WG), lds_lists, st, c, a,
                                (const double *)c.rec3, (const uint64_t *)c.cum);
         else switch (D) {
             case 2: MT ? launch_one<2, true>(c, a, lds, st) : launch_one<2, false>(c, a, lds, st); break;

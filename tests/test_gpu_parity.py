@@ -277,3 +277,65 @@ def test_d3_one_task_tile_edges(S, n, seed):
         for t in gidx:
             t = set(int(v) for v in t)
             assert not {127, 128} <= t and 130 not in t and not {1, 2, S - 1} <= t
+
+
+@pytest.mark.parametrize("S,n,T,seed", [(5, 40, 2, 95), (70, 300, 3, 96), (129, 260, 2, 97), (257, 400, 4, 98)])
+def test_d3_multitask_filter_task(S, n, T, seed):
+    """Several tasks, D = 3: the sweep filters on the task of largest
+    |y_t - mean|^2 alone (its SSE bounds the summed SSE from below) and scores
+    flagged tuples over every task.  The target is scaled up on a task that is
+    not the first, so the filter task is an inner one; a column constant on
+    another task and a pair of columns equal on one task only make tuples
+    rank deficient in a task the filter does not look at."""
+    _say(f"d3 multi-task S={S} n={n} T={T} seed={seed}")
+    w = 1.0 + np.random.default_rng(seed).random(T)
+    sizes = np.floor(n * w / w.sum()).astype(np.int64)
+    sizes[-1] += n - sizes.sum()
+    p = tiny_problem(seed, S=S, n=n, T=T, D=3, sigma=0.3, task_sizes=sizes)
+    F, y, off = p.F.copy(), p.y.copy(), p.task_offsets
+    big = T - 1
+    y[off[big]:off[big + 1]] *= 10.0
+    if S >= 70:
+        F[4, off[0]:off[1]] = 3.0                    # constant on task 0 only
+        F[9, off[1]:off[2]] = F[8, off[1]:off[2]]    # equal to column 8 on task 1 only
+    from synth.problems import Problem
+    q = Problem(F=F, y=y, task_offsets=off, planted=[], D=3, k=30, exprs=p.exprs, meta={})
+    k = min(30, math.comb(S, 3))
+    gidx, gsse, gcoef = _run(q, 3, k)
+    oidx, osse, _ = oracle.topk(F, y, 3, k, off)
+    compare_topk(q, 3, k, gidx, gsse, oidx, osse, gcoef=gcoef)
+    if S >= 70:
+        for t in gidx:
+            t = set(int(v) for v in t)
+            assert 4 not in t and not {8, 9} <= t
+
+
+def test_multitask_full_size_sampled():
+    """The 16-task workload at full size (S = 1500, 5.6e8 tuples): every
+    returned SSE is the oracle's SSE of that tuple, the planted tuple is first,
+    and no tuple that shares two features with the best one (4,491 tuples, the
+    likeliest competitors) nor a random sample beats the k-th result."""
+    p = make_config("multitask_t16_s1500_d3")
+    _say(f"multi-task full size S={p.S} T={len(p.task_offsets) - 1} n={p.F.shape[1]}")
+    gidx, gsse, _ = _run(p, 3, p.k)
+    assert np.all(np.isfinite(gsse)) and np.all(np.diff(gsse) >= 0)
+    for t, v in zip(gidx, gsse):
+        ref = oracle.tuple_sse(p.F, p.y, tuple(int(x) for x in t), p.task_offsets)
+        assert abs(v - ref) <= 1e-10 * ref, (t, v, ref)
+    assert tuple(int(x) for x in gidx[0]) == tuple(sorted(p.planted))
+    top = {tuple(int(x) for x in t) for t in gidx}
+    sk = float(gsse[-1])
+    best = [int(x) for x in gidx[0]]
+    cands = set()
+    for drop in range(3):
+        keep = [best[m] for m in range(3) if m != drop]
+        for f in range(p.S):
+            if f not in keep:
+                cands.add(tuple(sorted(keep + [f])))
+    rng = np.random.default_rng(11)
+    for _ in range(300):
+        cands.add(tuple(sorted(int(x) for x in rng.choice(p.S, size=3, replace=False))))
+    for t in cands:
+        if t in top:
+            continue
+        assert oracle.tuple_sse(p.F, p.y, t, p.task_offsets) >= sk * (1 - 1e-9), t
