@@ -99,7 +99,7 @@ static Layout compute_layout(int64_t n_total, int64_t S, int T, int D_max, int k
     // pre-pass + counters: theta, work counter, cand counter, cum table, prefixes, scores
     L.pre = take(64 + (size_t)(S / 4 + 8) * sizeof(uint64_t) + PRE_Q * SISSO_MAX_D * sizeof(int32_t) +
                  64 + (size_t)PRE_Q * S * d + PRE_Q * d + 1024 +
-                 (size_t)(SISSO_MAX_D + 1) * (S + 1) * sizeof(uint64_t) + 256);
+                 (size_t)(SISSO_MAX_D + 1) * (S + 1) * sizeof(uint64_t) + 64 + 256);
     // one row of four (i1, j) records per j > i1 group: sum over groups of (S - 2 - 4 g)
     {
         const int64_t ng3 = S >= 3 ? (S - 3) / 4 + 1 : 0;
@@ -109,6 +109,19 @@ static Layout compute_layout(int64_t n_total, int64_t S, int T, int D_max, int k
     L.rec3 = take(L.rec3_bytes);
     L.G1_bytes = (D_max >= 3 && S >= 3 && T > 1) ? Sp * Sp * d : 0;
     L.G1 = take(L.G1_bytes);
+    // several tasks, D = 3: a pool with a record for every step of the sweep
+    // plus one partly filled chunk per wave, so that it cannot run out; above
+    // 1 GiB of records the several-task search keeps its general kernel
+    L.mtq_chunks = 0;
+    if (L.G1_bytes) {
+        const uint64_t steps = s3_tiles_host(S) * 32;
+        const uint64_t chunks = (steps + MTQ_CHUNK - 1) / MTQ_CHUNK + (uint64_t)nlists;
+        if (chunks * MTQ_CHUNK * 3 * sizeof(uint64_t) <= (1ull << 30)) L.mtq_chunks = (int)chunks;
+    }
+    const size_t nch = (size_t)L.mtq_chunks;
+    L.mtq = take(nch * MTQ_CHUNK * 3 * sizeof(uint64_t));
+    L.mtq_n = take(nch * sizeof(uint32_t));
+    L.mtq_pre = take(nch ? (nch + 1) * sizeof(uint64_t) : 0);
     L.lists = take((size_t)nlists * L.KP * 2 * d + (size_t)nlists * L.KP * 2 * d);
     L.merged = take((size_t)L.KP * 2 * d);
     L.rescored = take((size_t)L.KP * d);
@@ -170,9 +183,9 @@ static void carve(sisso_l0 *h) {
     c.cand_counter = (unsigned int *)(p + 12);
     c.pre_count = (int32_t *)(p + 16);
     c.pre_done = (unsigned int *)(p + 20);
+    c.mtq_taken = (unsigned int *)(p + 60);
     c.stats = (uint64_t *)(p + 24);
     c.merge_count = (unsigned int *)(p + 56);
-    c.tstar = (int32_t *)(p + 60);
     p += 64;
     c.cum = (uint64_t *)p;
     p += (size_t)(c.S / 4 + 8) * sizeof(uint64_t);
@@ -183,8 +196,14 @@ static void carve(sisso_l0 *h) {
     c.pre_sse = (double *)p;
     p += align256((size_t)PRE_Q * c.S * sizeof(double));
     c.btab = (uint64_t *)p;
+    p += (size_t)(SISSO_MAX_D + 1) * (c.S + 1) * sizeof(uint64_t);
+    c.tstar = (int32_t *)p;
     c.rec3 = L.rec3_bytes ? (double *)(base + L.rec3) : nullptr;
     c.G1 = L.G1_bytes ? (double *)(base + L.G1) : c.G;
+    c.mtq_chunks = L.mtq_chunks;
+    c.mtq = L.mtq_chunks ? (uint64_t *)(base + L.mtq) : nullptr;
+    c.mtq_n = L.mtq_chunks ? (uint32_t *)(base + L.mtq_n) : nullptr;
+    c.mtq_pre = L.mtq_chunks ? (uint64_t *)(base + L.mtq_pre) : nullptr;
     const int64_t nl = L.nwaves;
     char *q = base + L.lists;
     c.list_sse = (double *)q;
@@ -504,6 +523,7 @@ extern "C" int32_t sisso_l0_topk(sisso_l0 *h, int32_t k, int32_t *idx, double *s
     uint32_t flags[4];
     memcpy(flags, h->stage, sizeof(flags));
     if (flags[FLAG_NONFINITE]) return fail(h, SISSO_EINVAL, "F or y holds a non-finite value");
+    if (flags[FLAG_CAPACITY]) return fail(h, SISSO_EDEVICE, "internal step queue overflow (results incomplete)");
     memcpy(sse, h->stage + (L.res_sse - L.res), (size_t)k * sizeof(double));
     memcpy(idx, h->stage + (L.res_idx - L.res), (size_t)k * D * sizeof(int32_t));
     if (coef) memcpy(coef, h->stage + (L.res_coef - L.res), (size_t)k * T * (D + 1) * sizeof(double));

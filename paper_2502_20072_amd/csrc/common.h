@@ -158,6 +158,7 @@ __host__ __device__ inline void unpack_tuple(uint64_t k, int D, int32_t *t) {
 // nt = ceil(S / 64).  A search step reads one row of one tile, so a chunk of
 // 64 steps stays inside 32 KB of contiguous memory.
 constexpr int GT = 64;
+constexpr int MTQ_CHUNK = 256;  // queued sweep steps per pool chunk (several tasks, D = 3)
 __host__ __device__ inline int64_t gidx(int64_t i, int64_t k, int64_t nt, int TP, int t) {
     return ((((i >> 6) * nt + (k >> 6)) << 12) + ((i & 63) << 6) + (k & 63)) * TP + t;
 }
@@ -212,6 +213,10 @@ struct Layout {
     size_t rec3_bytes;
     size_t G1;         // D = 3, several tasks: the filter task's matrix alone, double [S][S] tiled (0 bytes otherwise)
     size_t G1_bytes;
+    size_t mtq;        // D = 3, several tasks: flagged sweep steps, uint64 [mtq_chunks][MTQ_CHUNK][3]
+    size_t mtq_n;      //   uint32 [mtq_chunks] keys per chunk
+    size_t mtq_pre;    //   uint64 [mtq_chunks + 1] exclusive prefix of the counts
+    int mtq_chunks;    //   chunks in the pool (0: no queue)
     size_t lists;      // per-wave top lists: (double sse, uint64 rank) [nwaves][KP]
     size_t merged;     // merged candidates [KP] (sse, rank)
     size_t rescored;   // rescored candidates [KP] (sse, rank)
@@ -240,6 +245,6 @@ inline int next_pow2(int x) {
 }
 
 // device status flag indices
-enum { FLAG_NONFINITE = 0, FLAG_WORK = 1, FLAG_CAND = 2, FLAG_THETA = 4 /* uint64 at 4..5 */ };
+enum { FLAG_NONFINITE = 0, FLAG_CAPACITY = 1, FLAG_CAND = 2, FLAG_THETA = 4 /* uint64 at 4..5 */ };
 
 }  // namespace sl0

@@ -24,8 +24,9 @@ __device__ inline double wave_sum(double v) {
 
 // One workgroup: clears the status words, then wave w handles tasks w,
 // w + 4, ... (so no other workgroup can set a status bit before the clear).
-// Last, it names the filter task: the task of largest c_t (the first such),
-// whose SSE alone is a lower bound of any tuple's SSE summed over tasks.
+// Last, it names the filter tasks: the tasks of largest and second largest
+// c_t (the first such; -1 for the second when T = 1), whose SSEs bound any
+// tuple's SSE summed over tasks from below.
 __global__ __launch_bounds__(256) void stats_y_kernel(const double *__restrict__ y,
                                                       const int64_t *__restrict__ off, int T,
                                                       double *__restrict__ ybar,
@@ -62,10 +63,17 @@ __global__ __launch_bounds__(256) void stats_y_kernel(const double *__restrict__
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        int best = 0;
-        for (int t = 1; t < T; ++t)
-            if (cyy[t] > cyy[best]) best = t;
-        *tstar = best;
+        int best = 0, second = -1;
+        for (int t = 1; t < T; ++t) {
+            if (cyy[t] > cyy[best]) {
+                second = best;
+                best = t;
+            } else if (second < 0 || cyy[t] > cyy[second]) {
+                second = t;
+            }
+        }
+        tstar[0] = best;
+        tstar[1] = second;
     }
 }
 

@@ -34,7 +34,13 @@ struct Ctx {
     double *pre_bound;               // pre-pass: per-prefix L-th best [PRE_Q]
     double *rec3;                    // D = 3: pair records of the filter task [ceil(S/4)][S][4][4] (null if absent)
     double *G1;                      // the filter task's matrix alone, one-task tiled layout (G itself when T = 1)
-    int32_t *tstar;                  // filter task: the task of largest |y_t - ybar_t|^2 (0 when T = 1)
+    uint64_t *mtq;                   // several tasks, D = 3: flagged sweep steps [mtq_chunks][MTQ_CHUNK][3]
+    uint32_t *mtq_n;                 //   keys per chunk
+    uint64_t *mtq_pre;               //   exclusive prefix of mtq_n over the chunks taken [+1]
+    unsigned int *mtq_taken;         //   chunks taken from the pool (may run past mtq_chunks)
+    int mtq_chunks;                  //   chunks in the pool (0: none)
+    int32_t *tstar;                  // filter tasks [2]: the tasks of largest and second largest
+                                     // |y_t - ybar_t|^2 (0 and -1 when T = 1)
     double *list_sse;                // per-wave lists [nwaves][KP]
     uint64_t *list_rank;
     double *cand_sse;                // merge: compacted candidates [nwaves * KP]
@@ -67,6 +73,7 @@ struct SearchCall {
     uint64_t r0, r1;
 };
 
+uint64_t s3_tiles_host(int64_t S);  // tiles of the D = 3 record-table sweep
 int launch_stats(const Ctx &c, hipStream_t st);
 int launch_gram(const Ctx &c, hipStream_t st);  // FP64 MFMA or precision form, then finish
 int launch_gram_lp(const Ctx &c, int NS, hipStream_t st);

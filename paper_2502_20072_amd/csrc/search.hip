@@ -239,6 +239,8 @@ __device__ void search_init_body(const Ctx &c, int64_t e, bool leader, int D, in
         *c.theta_bits = (unsigned long long)__double_as_longlong(INF);
         *c.pre_count = 0;
         *c.merge_count = 0;
+        *c.mtq_taken = 0;
+        c.flags[FLAG_CAPACITY] = 0;
         c.stats[1] = 0;
         if (s3) {
             s3_tile_table(c);
@@ -1183,7 +1185,7 @@ __global__ __launch_bounds__(256) void rec3_kernel(Ctx c, double *__restrict__ r
     const int64_t i1 = S3_NR * g + r;
     const int64_t e = (s3_rowoff(S, g) + j - S3_NR * g - 1) * S3_NR + r;
     // the filter task's pair (i1, j) (the only task when T = 1)
-    const int ts = *c.tstar;
+    const int ts = c.tstar[0];
     const double *G1 = c.G1;
     const int64_t nt = c.Gnt;
     double v = 0.0, al = 0.0, zs = 0.0, p = __builtin_nan("");
@@ -1249,6 +1251,104 @@ uint64_t s3_tiles_host(int64_t S) {
 #ifndef S3_WPE
 #define S3_WPE 4                      // waves per SIMD the register budget is sized for
 #endif
+// Several tasks, D = 3: scores one flagged step of the sweep (row j of
+// group g, column chunk kcx, the flag masks fm of the step's two columns per
+// lane).  Everything is reloaded from memory (the sweep's registers are not
+// live here): the filter task's test is redone per i1 and column with a true
+// division; the tuples that pass are tested with the second filter task's
+// SSE added; the rest are scored over every task, 64 / LT tuples at a time
+// with LT lanes each (lane q LT + l sums the tasks t = l mod LT of tuple q,
+// then a butterfly sum and rank flag), and inserted into the wave's list.
+__device__ __forceinline__ unsigned mt_step(const Ctx &c, const SearchArgs &a, const double *__restrict__ rec,
+                                            double *Ls, uint64_t *Lr, int KP, int64_t j, int64_t g, int64_t kcx,
+                                            unsigned long long fm0, unsigned long long fm1, double theta_f) {
+    const int lane = threadIdx.x & 63;
+    const int64_t S = c.S, nt = c.Gnt;
+    const int TP = c.TP, ts = c.tstar[0], t2 = c.tstar[1];
+    const double *__restrict__ G1 = c.G1;
+    const double *__restrict__ inv_st = c.inv_s + (int64_t)ts * S;
+    auto task_sse = [&](const int32_t (&tq)[3], int t, bool &ok) {
+        double gm[3][3], bv[3];
+#pragma unroll
+        for (int m2 = 0; m2 < 3; ++m2) {
+#pragma unroll
+            for (int j2 = 0; j2 <= m2; ++j2) gm[m2][j2] = Gat(c, tq[m2], tq[j2], t);
+            bv[m2] = c.bhat[(int64_t)tq[m2] * TP + t];
+        }
+        return ne_sse_core<3>(gm, bv, c.cyy[t], ok);
+    };
+    const int64_t k0 = kcx * S3_KC + 2 * lane, k1 = k0 + 1;
+    const bool kv0 = k0 < S, kv1 = k1 < S;
+    const int64_t kk = kv0 ? k0 : ((S - 1) & ~(int64_t)1);
+    const int64_t kd1 = kv1 ? k1 : kk;
+    const double2 gv = *reinterpret_cast<const double2 *>(G1 + gidx(j, kk, nt, 1, 0));
+    const double gd0 = inv_st[kk] > 0.0 ? 1.0 : 0.0, gd1 = inv_st[kd1] > 0.0 ? 1.0 : 0.0;
+    const double b0 = c.bhat[kk * TP + ts], b1 = c.bhat[kd1 * TP + ts];
+    const double *rp = rec + (s3_rowoff(S, g) + j - S3_NR * g - 1) * (S3_NR * 4);
+    const int LT = TP < 64 ? TP : 64;
+    const int R = 64 / LT, slot = lane / LT;
+    unsigned offered = 0;
+    for (int r = 0; r < S3_NR; ++r) {
+        const int64_t i1 = S3_NR * g + r, i1c = i1 < S ? i1 : S - 1;
+        const double v = rp[4 * r], al = rp[4 * r + 1], zs = rp[4 * r + 2], p = rp[4 * r + 3];
+        const double zp = c.bhat[i1c * TP + ts];
+        const double2 wv = *reinterpret_cast<const double2 *>(G1 + gidx(i1c, kk, nt, 1, 0));
+        for (int sl = 0; sl < 2; ++sl) {
+            const double w = sl ? wv.y : wv.x, gg = sl ? gv.y : gv.x, gd = sl ? gd1 : gd0;
+            const int64_t k = sl ? k1 : k0;
+            const double dq = ((sl ? kv1 : kv0) && gd > RANK_EPS) ? gd - w * w : __builtin_nan("");
+            const double zq = (sl ? b1 : b0) - w * zp;
+            const double u = fma(-v, w, gg);
+            const double d = fma(-al, u * u, dq);
+            const double z = fma(-zs, u, zq);
+            const double es = (d > RANK_EPS) ? p - z * z / d : INF;
+            const int32_t tup[3] = {(int32_t)i1, (int32_t)j, (int32_t)k};
+            bool take = (((sl ? fm1 : fm0) >> lane) & 1ull) && k < S && k > j && es <= theta_f;
+            if (take && a.ranged) {
+                const uint64_t lr = lex_rank(BinomTab{c.btab, c.S}, c.S, 3, tup);
+                if (lr < a.r0 || lr >= a.r1) take = false;
+            }
+            if (take && t2 >= 0) {
+                bool ok2 = true;
+                const double e2 = task_sse(tup, t2, ok2);
+                take = ok2 && es + e2 <= theta_f;
+            }
+            unsigned long long m = __ballot(take);
+            while (m) {
+                int src = -1;
+                for (int q = 0; q < R; ++q) {
+                    const int sb = m ? __ffsll((long long)m) - 1 : -1;
+                    if (slot == q) src = sb;
+                    m &= m - 1;
+                }
+                const int32_t kq = __shfl((int32_t)k, src < 0 ? 0 : src);
+                double part = 0.0;
+                bool okp = true;
+                if (src >= 0) {
+                    const int32_t tq[3] = {tup[0], tup[1], kq};
+                    for (int t = lane % LT; t < c.T; t += LT) part += task_sse(tq, t, okp);
+                }
+                for (int o = 1; o < LT; o <<= 1) {
+                    part += __shfl_xor(part, o);
+                    okp = __shfl_xor((int)okp, o) != 0 && okp;
+                }
+                const double esv = okp ? part : INF;
+                for (int q = 0; q < R; ++q) {
+                    if (__shfl(src, q * LT) < 0) break;
+                    const double v2 = __shfl(esv, q * LT);
+                    const int32_t kv = __shfl(kq, q * LT);
+                    if (v2 <= fmin(theta_f, Ls[KP - 1])) {
+                        const int32_t tv[3] = {tup[0], tup[1], kv};
+                        ++offered;
+                        list_insert(Ls, Lr, KP, v2, pack_tuple(tv, 3));
+                    }
+                }
+            }
+        }
+    }
+    return offered;
+}
+
 // MT: several tasks (the sweep filters on the filter task alone, the exact
 // path sums every task); a template parameter so that the one-task kernel's
 // registers are not shaped by the several-task exact path
@@ -1279,7 +1379,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S3_WPE))) v
     // the filter task's matrix and statistics (the only task when T = 1)
     const double *__restrict__ Gb = c.G1;
     const int TP = c.TP;
-    const int ts = *c.tstar;
+    const int ts = c.tstar[0];
+    const int t2 = MT ? c.tstar[1] : -1;
+    const int64_t gw = (int64_t)blockIdx.x * SEARCH_WAVES + wave;
+    // several tasks: flagged steps are queued in chunks taken from a pool (one
+    // atomic per MTQ_CHUNK steps) and scored by a later, evenly spread kernel
+    // (the steps cluster in the few tiles of the best features)
+    int qchunk = -1, qn = 0;
     const double *__restrict__ inv_st = c.inv_s + (int64_t)ts * S;
 
     // Tiles are dealt round-robin over the waves (their costs are nearly
@@ -1454,6 +1560,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S3_WPE))) v
             const int jr = s_qj[wave][e];
             const int64_t j = jlo + jr;
             const unsigned long long fm[2] = {s_q[wave][e][0], s_q[wave][e][1]};
+            if (MT) {
+                // several tasks: queue the step (row j of group g, chunk kcx,
+                // the flags); a later, evenly spread kernel scores it.  The
+                // pool holds a record per sweep step plus a partly filled
+                // chunk per wave, so a take past its end cannot happen; it
+                // would be reported, not dropped silently
+                if (qchunk != -2 && (qchunk < 0 || qn == MTQ_CHUNK)) {
+                    if (qchunk >= 0 && lane == 0) c.mtq_n[qchunk] = (uint32_t)qn;
+                    unsigned got = 0;
+                    if (lane == 0) got = atomicAdd(c.mtq_taken, 1u);
+                    got = (unsigned)__shfl((int)got, 0);
+                    qchunk = got < (unsigned)c.mtq_chunks ? (int)got : -2;
+                    if (qchunk == -2 && lane == 0) atomicOr(&c.flags[FLAG_CAPACITY], 1u);
+                    qn = 0;
+                }
+                if (qchunk >= 0) {
+                    if (lane < 3) {
+                        const uint64_t w0 = ((uint64_t)j << 40) | ((uint64_t)g << 20) | (uint64_t)kcx;
+                        c.mtq[((int64_t)qchunk * MTQ_CHUNK + qn) * 3 + lane] = lane == 0 ? w0 : lane == 1 ? fm[0] : fm[1];
+                    }
+                    ++qn;
+                }
+                continue;
+            }
             const double *rp = reinterpret_cast<const double *>(recj + (size_t)jr * 128);
             const double2 gv = *reinterpret_cast<const double2 *>(gtile + (voff + (uint32_t)jr * 512u));
             // (r, sl) are wave-uniform here: pick the k-data by selects, so
@@ -1488,8 +1618,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S3_WPE))) v
                         const uint64_t lr = lex_rank(BinomTab{c.btab, c.S}, c.S, 3, tup);
                         if (lr < a.r0 || lr >= a.r1) take = false;
                     }
-                    unsigned long long m = __ballot(take);
                     if (!MT) {
+                        unsigned long long m = __ballot(take);
                         const uint64_t rk = take ? pack_tuple(tup, 3) : 0;
                         offered += (unsigned)__popcll(m);
                         while (m) {
@@ -1501,51 +1631,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S3_WPE))) v
                         }
                         continue;
                     }
-                    // several tasks: the passing columns are scored over every
-                    // task, 64 / LT tuples at a time, LT lanes per tuple (lane
-                    // q LT + l sums the tasks t = l mod LT of tuple q), then a
-                    // butterfly sum and rank flag over each tuple's LT lanes
-                    const int LT = TP < 64 ? TP : 64;
-                    const int R = 64 / LT, slot = lane / LT;
-                    while (m) {
-                        int src = -1;
-                        for (int q = 0; q < R; ++q) {
-                            const int sb = m ? __ffsll((long long)m) - 1 : -1;
-                            if (slot == q) src = sb;
-                            m &= m - 1;
-                        }
-                        const int32_t kq = (int32_t)__shfl((int)k, src < 0 ? 0 : src);
-                        double part = 0.0;
-                        bool okp = true;
-                        if (src >= 0) {
-                            const int32_t tq[3] = {tup[0], tup[1], kq};
-                            for (int t = lane % LT; t < c.T; t += LT) {
-                                double gm[3][3], bv[3];
-#pragma unroll
-                                for (int m2 = 0; m2 < 3; ++m2) {
-#pragma unroll
-                                    for (int j2 = 0; j2 <= m2; ++j2) gm[m2][j2] = Gat(c, tq[m2], tq[j2], t);
-                                    bv[m2] = c.bhat[(int64_t)tq[m2] * TP + t];
-                                }
-                                part += ne_sse_core<3>(gm, bv, c.cyy[t], okp);
-                            }
-                        }
-                        for (int o = 1; o < LT; o <<= 1) {
-                            part += __shfl_xor(part, o);
-                            okp = __shfl_xor((int)okp, o) != 0 && okp;
-                        }
-                        const double esv = okp ? part : INF;
-                        for (int q = 0; q < R; ++q) {
-                            if (__shfl(src, q * LT) < 0) break;
-                            const double v2 = __shfl(esv, q * LT);
-                            const int32_t kv = __shfl(kq, q * LT);
-                            if (v2 <= fmin(theta_f, Ls[KP - 1])) {
-                                const int32_t tv[3] = {tup[0], tup[1], kv};
-                                ++offered;
-                                list_insert(Ls, Lr, KP, v2, pack_tuple(tv, 3));
-                            }
-                        }
-                    }
                 }
             }
         }
@@ -1556,7 +1641,77 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S3_WPE))) v
         }
     }
     if (lane == 0 && offered) atomicAdd(c.cand_counter, offered);
+    if (MT && qchunk >= 0 && lane == 0) c.mtq_n[qchunk] = (uint32_t)qn;
+    for (int m = lane; m < KP; m += 64) {
+        c.list_sse[gw * KP + m] = Ls[m];
+        c.list_rank[gw * KP + m] = Lr[m];
+    }
+}
+
+// Several tasks, D = 3: exclusive prefix of the queued chunks' counts (one
+// workgroup of PRE_WG threads, PRE_WG consecutive counts per pass).
+__global__ __launch_bounds__(PRE_WG) void mt_scan_kernel(Ctx c) {
+    __shared__ unsigned wsum[PRE_WG / 64];
+    __shared__ unsigned long long carry;
+    const int nreg = (int)min(*c.mtq_taken, (unsigned)c.mtq_chunks);
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < nreg; base += PRE_WG) {
+        const int r = base + (int)threadIdx.x;
+        const unsigned v = r < nreg ? c.mtq_n[r] : 0u;
+        const unsigned incl = block_scan(v, wsum);
+        const unsigned long long cy = carry;
+        if (r < nreg) c.mtq_pre[r] = cy + incl - v;
+        __syncthreads();
+        if (threadIdx.x == PRE_WG - 1) carry = cy + incl;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) c.mtq_pre[nreg] = carry;
+}
+
+// Several tasks, D = 3: scores the queued sweep steps.  The steps, in chunk
+// order, are cut into equal contiguous runs, one per wave.  For each step the
+// wave scores the step with mt_step.  Wave gw starts from the sweep's list
+// gw.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S3_WPE))) void mt_eval_kernel(
+    Ctx c, SearchArgs a, const double *__restrict__ rec) {
+    extern __shared__ double smem[];
+    const int KP = a.KP;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t gw = (int64_t)blockIdx.x * SEARCH_WAVES + wave;
+    const int64_t nw = (int64_t)gridDim.x * SEARCH_WAVES;
+    double *Ls = smem + (size_t)wave * KP * 2;
+    uint64_t *Lr = reinterpret_cast<uint64_t *>(Ls + KP);
+    for (int m = lane; m < KP; m += 64) {
+        Ls[m] = c.list_sse[gw * KP + m];
+        Lr[m] = c.list_rank[gw * KP + m];
+    }
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_wave_barrier();
+    const int nreg = (int)min(*c.mtq_taken, (unsigned)c.mtq_chunks);
+    const uint64_t total = nreg > 0 ? c.mtq_pre[nreg] : 0;
+    const uint64_t per = (total + nw - 1) / nw;
+    const uint64_t e0 = (uint64_t)gw * per, e1 = e0 + per < total ? e0 + per : total;
+    double th = fmin(theta0_from_prepass(c, a.L, KP), theta_load(c.theta_bits));
+    const double theta_f = th < INF ? th * (1.0 + THETA_SLACK) : INF;
+    unsigned offered = 0;
+    if (e0 < e1) {
+        int lo = 0, hi = nreg - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (c.mtq_pre[mid] <= e0) lo = mid; else hi = mid - 1;
+        }
+        int reg = lo;
+        for (uint64_t e = e0; e < e1; ++e) {
+            while (reg + 1 <= nreg - 1 && c.mtq_pre[reg + 1] <= e) ++reg;
+            const int64_t at = ((int64_t)reg * MTQ_CHUNK + (int64_t)(e - c.mtq_pre[reg])) * 3;
+            const uint64_t w0 = c.mtq[at];
+            offered += mt_step(c, a, rec, Ls, Lr, KP, (int64_t)(w0 >> 40), (int64_t)((w0 >> 20) & 0xFFFFF),
+                               (int64_t)(w0 & 0xFFFFF), c.mtq[at + 1], c.mtq[at + 2], theta_f);
+        }
+    }
+    if (lane == 0 && offered) atomicAdd(c.cand_counter, offered);
     for (int m = lane; m < KP; m += 64) {
         c.list_sse[gw * KP + m] = Ls[m];
         c.list_rank[gw * KP + m] = Lr[m];
@@ -2326,7 +2481,8 @@ int launch_search(const Ctx &c, const SearchCall &sc, hipStream_t st) {
         // one task, D = 3: record table + tile sweep (tile count within the 32-bit work counter)
         // D = 3: the record-table sweep, on the filter task's matrix when
         // there are several tasks
-        const bool s3 = D == 3 && c.rec3 != nullptr && s3_tiles_host(c.S) < (1ull << 31);
+        const bool s3 = D == 3 && c.rec3 != nullptr && s3_tiles_host(c.S) < (1ull << 31) &&
+                        (!MT || c.mtq_chunks > 0);
         if (s3) {
             // record table + initialisation in one launch (its grid covers the binomial table)
             // x: the rows of one group (j, r); y: groups; the grid also covers
@@ -2348,9 +2504,13 @@ int launch_search(const Ctx &c, const SearchCall &sc, hipStream_t st) {
         phase_begin(c, SISSO_PHASE_SEARCH, st);
         const size_t nrec = MT ? (size_t)a.JB * c.TP : (size_t)SEARCH_WG;
         const size_t lds = lds_lists + nrec * RECW * sizeof(double) + (size_t)64 * SUBW * sizeof(double);
-        if (s3 && MT)
+        if (s3 && MT) {
             hipLaunchKernelGGL(search3_kernel<true>, dim3(c.search_wgs), dim3(SEARCH_WG), lds_lists, st, c, a,
                                (const double *)c.rec3, (const uint64_t *)c.cum);
+            hipLaunchKernelGGL(mt_scan_kernel, dim3(1), dim3(PRE_WG), 0, st, c);
+            hipLaunchKernelGGL(mt_eval_kernel, dim3(c.search_wgs), dim3(SEARCH_WG), lds_lists, st, c, a,
+                               (const double *)c.rec3);
+        }
         else if (s3)
             hipLaunchKernelGGL(search3_kernel<false>, dim3(c.search_wgs), dim3(SEARCH_WG), lds_lists, st, c, a,
                                (const double *)c.rec3, (const uint64_t *)c.cum);
