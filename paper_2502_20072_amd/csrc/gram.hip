@@ -365,6 +365,65 @@ __global__ __launch_bounds__(256) void gram_finish_kernel(const double *__restri
     }
 }
 
+// Several tasks (TP <= 16): one workgroup per (tile pair ti <= tk, band of
+// FR_T rows) takes every task, so that each element's TP task values (task
+// fastest in G) are written together.  Per task the split partials of the
+// band are summed in the same order as the one-task kernel and scaled; the
+// band is held in LDS for all tasks ([task][row][col], one padding double per
+// task against bank conflicts), then written row by row to tile (ti, tk) and
+// column by column to tile (tk, ti), both as contiguous runs of whole task
+// groups.  The filter task's values also go to G1.
+constexpr int FR_T = 4;  // tile rows per workgroup of the several-task finish
+__global__ __launch_bounds__(256) void gram_finish_tasks_kernel(const double *__restrict__ part, int64_t S, int T,
+                                                                int TP, int nsplit, const double *__restrict__ inv_s,
+                                                                double *__restrict__ G, int64_t nt,
+                                                                double *__restrict__ G1,
+                                                                const int32_t *__restrict__ tstar) {
+    extern __shared__ double val[];  // [TP][FR_T * 64 + 1]
+    constexpr int NB = GT / FR_T;
+    constexpr int VS = FR_T * GT + 1;
+    const int qr = (int)(blockIdx.x % NB);
+    int64_t pr = blockIdx.x / NB;
+    int64_t ti = 0;
+    while (pr >= nt - ti) {
+        pr -= nt - ti;
+        ++ti;
+    }
+    const int64_t tk = ti + pr;
+    const int ts = G1 != nullptr ? *tstar : -1;
+    const int tid = threadIdx.x;
+    for (int t = 0; t < TP; ++t) {
+        const double *ist = inv_s + (int64_t)t * S;
+        for (int e = tid; e < FR_T * GT; e += 256) {
+            const int li = FR_T * qr + e / GT, lk = e % GT;
+            const int64_t i = ti * GT + li, k = tk * GT + lk;
+            double v = 0.0;
+            if (t < T && i < S && k < S) {
+                const int64_t a = (ti == tk && i > k) ? k : i, cc = (ti == tk && i > k) ? i : k;  // canonical (upper)
+                double acc = 0.0;
+                for (int sp = 0; sp < nsplit; ++sp) acc += part[((int64_t)sp * T + t) * S * S + a * S + cc];
+                v = i == k ? (ist[i] > 0.0 ? 1.0 : 0.0) : acc * (ist[a] * ist[cc]);
+            }
+            val[t * VS + e] = v;
+            if (t == ts) G1[((ti * nt + tk) << 12) + (li << 6) + lk] = v;
+        }
+    }
+    __syncthreads();
+    for (int x = tid; x < FR_T * GT * TP; x += 256) {
+        const int t = x % TP, e = x / TP;
+        const int li = FR_T * qr + e / GT, lk = e % GT;
+        G[(((ti * nt + tk) << 12) + (li << 6) + lk) * TP + t] = val[t * VS + e];
+    }
+    if (ti == tk) return;
+    for (int x = tid; x < GT * FR_T * TP; x += 256) {
+        const int t = x % TP, y = x / TP;
+        const int r = y % FR_T, lk = y / FR_T;
+        const double v = val[t * VS + r * GT + lk];
+        G[(((tk * nt + ti) << 12) + (lk << 6) + FR_T * qr + r) * TP + t] = v;
+        if (t == ts) G1[((tk * nt + ti) << 12) + (lk << 6) + FR_T * qr + r] = v;
+    }
+}
+
 // Unpack task t of the tiled matrices into a plain row-major S x S array.
 __global__ __launch_bounds__(256) void untile_kernel(const double *__restrict__ G, int64_t S, int64_t nt, int TP,
                                                      int t, double *__restrict__ dst) {
@@ -402,8 +461,16 @@ int launch_gram(const Ctx &c, hipStream_t st) {
                            c.off_dev, c.T, c.mu, ntile, c.nsplit, c.part);
     }
     const int64_t npair64 = c.Gnt * (c.Gnt + 1) / 2;
-    hipLaunchKernelGGL(gram_finish_kernel, dim3((unsigned)(npair64 * c.T * (GT / FIN_ROWS))), dim3(256), 0, st, c.part, c.S, c.T,
-                       c.TP, c.nsplit, c.inv_s, c.G, c.Gnt, c.G1 != c.G ? c.G1 : nullptr, c.tstar);
+    if (c.T > 1 && c.TP <= 16) {
+        const size_t lds = (size_t)c.TP * (FR_T * GT + 1) * sizeof(double);
+        hipLaunchKernelGGL(gram_finish_tasks_kernel, dim3((unsigned)(npair64 * (GT / FR_T))), dim3(256), lds, st,
+                           c.part, c.S, c.T, c.TP, c.nsplit, c.inv_s, c.G, c.Gnt, c.G1 != c.G ? c.G1 : nullptr,
+                           c.tstar);
+    } else {
+        hipLaunchKernelGGL(gram_finish_kernel, dim3((unsigned)(npair64 * c.T * (GT / FIN_ROWS))), dim3(256), 0, st,
+                           c.part, c.S, c.T, c.TP, c.nsplit, c.inv_s, c.G, c.Gnt, c.G1 != c.G ? c.G1 : nullptr,
+                           c.tstar);
+    }
     phase_end(c, SISSO_PHASE_GRAM, st);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }

@@ -1251,22 +1251,22 @@ uint64_t s3_tiles_host(int64_t S) {
 #ifndef S3_WPE
 #define S3_WPE 4                      // waves per SIMD the register budget is sized for
 #endif
-// Several tasks, D = 3: scores one flagged step of the sweep (row j of
-// group g, column chunk kcx, the flag masks fm of the step's two columns per
-// lane).  Everything is reloaded from memory (the sweep's registers are not
-// live here): the filter task's test is redone per i1 and column with a true
-// division; the tuples that pass are tested with the second filter task's
-// SSE added; the rest are scored over every task, 64 / LT tuples at a time
-// with LT lanes each (lane q LT + l sums the tasks t = l mod LT of tuple q,
-// then a butterfly sum and rank flag), and inserted into the wave's list.
-__device__ __forceinline__ unsigned mt_step(const Ctx &c, const SearchArgs &a, const double *__restrict__ rec,
-                                            double *Ls, uint64_t *Lr, int KP, int64_t j, int64_t g, int64_t kcx,
-                                            unsigned long long fm0, unsigned long long fm1, double theta_f) {
+// Several tasks, D = 3: the exact scoring of queued sweep steps, in two
+// phases per wave.  mt_step_candidates redoes, for one step (row j of group
+// g, column chunk kcx, the flag masks of the step's two columns per lane),
+// the filter task's test per i1 and column with a true division, and appends
+// the tuples that pass (key, filter-task SSE) to the wave's LDS buffer.
+// mt_flush then takes up to 64 buffered tuples, one per lane: the second
+// largest task's SSE is added (a tighter lower bound), and the survivors are
+// scored over every task, 64 / LT tuples at a time with LT lanes each (lane
+// q LT + l sums the tasks t = l mod LT of tuple q, then a butterfly sum and
+// rank flag), and inserted into the wave's list.
+constexpr int MT_BUF = 128;  // buffered tuples per wave (a flush takes 64)
+
+__device__ __forceinline__ unsigned mt_flush(const Ctx &c, double *Ls, uint64_t *Lr, int KP, const uint64_t *bk,
+                                             const double *be, int cnt, double theta_f) {
     const int lane = threadIdx.x & 63;
-    const int64_t S = c.S, nt = c.Gnt;
-    const int TP = c.TP, ts = c.tstar[0], t2 = c.tstar[1];
-    const double *__restrict__ G1 = c.G1;
-    const double *__restrict__ inv_st = c.inv_s + (int64_t)ts * S;
+    const int TP = c.TP, t2 = c.tstar[1];
     auto task_sse = [&](const int32_t (&tq)[3], int t, bool &ok) {
         double gm[3][3], bv[3];
 #pragma unroll
@@ -1277,6 +1277,63 @@ __device__ __forceinline__ unsigned mt_step(const Ctx &c, const SearchArgs &a, c
         }
         return ne_sse_core<3>(gm, bv, c.cyy[t], ok);
     };
+    bool take = lane < cnt;
+    const uint64_t key = take ? bk[lane] : 0;
+    int32_t tup[3] = {0, 1, 2};
+    if (take) {
+        unpack_tuple(key, 3, tup);
+        if (t2 >= 0) {
+            bool ok2 = true;
+            const double e2 = task_sse(tup, t2, ok2);
+            take = ok2 && be[lane] + e2 <= theta_f;
+        }
+    }
+    const int LT = TP < 64 ? TP : 64;
+    const int R = 64 / LT, slot = lane / LT;
+    unsigned offered = 0;
+    unsigned long long m = __ballot(take);
+    while (m) {
+        int src = -1;
+        for (int q = 0; q < R; ++q) {
+            const int sb = m ? __ffsll((long long)m) - 1 : -1;
+            if (slot == q) src = sb;
+            m &= m - 1;
+        }
+        const uint64_t kq = (uint64_t)__shfl((long long)key, src < 0 ? 0 : src);
+        double part = 0.0;
+        bool okp = true;
+        if (src >= 0) {
+            int32_t tq[3];
+            unpack_tuple(kq, 3, tq);
+            for (int t = lane % LT; t < c.T; t += LT) part += task_sse(tq, t, okp);
+        }
+        for (int o = 1; o < LT; o <<= 1) {
+            part += __shfl_xor(part, o);
+            okp = __shfl_xor((int)okp, o) != 0 && okp;
+        }
+        const double esv = okp ? part : INF;
+        for (int q = 0; q < R; ++q) {
+            if (__shfl(src, q * LT) < 0) break;
+            const double v2 = __shfl(esv, q * LT);
+            const uint64_t k2 = (uint64_t)__shfl((long long)kq, q * LT);
+            if (v2 <= fmin(theta_f, Ls[KP - 1])) {
+                ++offered;
+                list_insert(Ls, Lr, KP, v2, k2);
+            }
+        }
+    }
+    return offered;
+}
+
+__device__ __forceinline__ unsigned mt_step(const Ctx &c, const SearchArgs &a, const double *__restrict__ rec,
+                                            double *Ls, uint64_t *Lr, int KP, uint64_t *bk, double *be, int &nbuf,
+                                            int64_t j, int64_t g, int64_t kcx, unsigned long long fm0,
+                                            unsigned long long fm1, double theta_f) {
+    const int lane = threadIdx.x & 63;
+    const int64_t S = c.S, nt = c.Gnt;
+    const int TP = c.TP, ts = c.tstar[0];
+    const double *__restrict__ G1 = c.G1;
+    const double *__restrict__ inv_st = c.inv_s + (int64_t)ts * S;
     const int64_t k0 = kcx * S3_KC + 2 * lane, k1 = k0 + 1;
     const bool kv0 = k0 < S, kv1 = k1 < S;
     const int64_t kk = kv0 ? k0 : ((S - 1) & ~(int64_t)1);
@@ -1285,14 +1342,14 @@ __device__ __forceinline__ unsigned mt_step(const Ctx &c, const SearchArgs &a, c
     const double gd0 = inv_st[kk] > 0.0 ? 1.0 : 0.0, gd1 = inv_st[kd1] > 0.0 ? 1.0 : 0.0;
     const double b0 = c.bhat[kk * TP + ts], b1 = c.bhat[kd1 * TP + ts];
     const double *rp = rec + (s3_rowoff(S, g) + j - S3_NR * g - 1) * (S3_NR * 4);
-    const int LT = TP < 64 ? TP : 64;
-    const int R = 64 / LT, slot = lane / LT;
     unsigned offered = 0;
+#pragma unroll
     for (int r = 0; r < S3_NR; ++r) {
         const int64_t i1 = S3_NR * g + r, i1c = i1 < S ? i1 : S - 1;
         const double v = rp[4 * r], al = rp[4 * r + 1], zs = rp[4 * r + 2], p = rp[4 * r + 3];
         const double zp = c.bhat[i1c * TP + ts];
         const double2 wv = *reinterpret_cast<const double2 *>(G1 + gidx(i1c, kk, nt, 1, 0));
+#pragma unroll
         for (int sl = 0; sl < 2; ++sl) {
             const double w = sl ? wv.y : wv.x, gg = sl ? gv.y : gv.x, gd = sl ? gd1 : gd0;
             const int64_t k = sl ? k1 : k0;
@@ -1308,40 +1365,35 @@ __device__ __forceinline__ unsigned mt_step(const Ctx &c, const SearchArgs &a, c
                 const uint64_t lr = lex_rank(BinomTab{c.btab, c.S}, c.S, 3, tup);
                 if (lr < a.r0 || lr >= a.r1) take = false;
             }
-            if (take && t2 >= 0) {
-                bool ok2 = true;
-                const double e2 = task_sse(tup, t2, ok2);
-                take = ok2 && es + e2 <= theta_f;
-            }
-            unsigned long long m = __ballot(take);
-            while (m) {
-                int src = -1;
-                for (int q = 0; q < R; ++q) {
-                    const int sb = m ? __ffsll((long long)m) - 1 : -1;
-                    if (slot == q) src = sb;
-                    m &= m - 1;
+            const unsigned long long m = __ballot(take);
+            if (m) {
+                if (take) {
+                    const int at = nbuf + __popcll(m & ((1ull << lane) - 1ull));
+                    bk[at] = pack_tuple(tup, 3);
+                    be[at] = es;
                 }
-                const int32_t kq = __shfl((int32_t)k, src < 0 ? 0 : src);
-                double part = 0.0;
-                bool okp = true;
-                if (src >= 0) {
-                    const int32_t tq[3] = {tup[0], tup[1], kq};
-                    for (int t = lane % LT; t < c.T; t += LT) part += task_sse(tq, t, okp);
-                }
-                for (int o = 1; o < LT; o <<= 1) {
-                    part += __shfl_xor(part, o);
-                    okp = __shfl_xor((int)okp, o) != 0 && okp;
-                }
-                const double esv = okp ? part : INF;
-                for (int q = 0; q < R; ++q) {
-                    if (__shfl(src, q * LT) < 0) break;
-                    const double v2 = __shfl(esv, q * LT);
-                    const int32_t kv = __shfl(kq, q * LT);
-                    if (v2 <= fmin(theta_f, Ls[KP - 1])) {
-                        const int32_t tv[3] = {tup[0], tup[1], kv};
-                        ++offered;
-                        list_insert(Ls, Lr, KP, v2, pack_tuple(tv, 3));
+                nbuf += __popcll(m);
+                __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                __builtin_amdgcn_wave_barrier();
+                if (nbuf >= 64) {
+                    offered += mt_flush(c, Ls, Lr, KP, bk, be, 64, theta_f);
+                    // keep the rest (fewer than 64) at the front
+                    const int rest = nbuf - 64;
+                    uint64_t kx = 0;
+                    double ex = 0.0;
+                    if (lane < rest) {
+                        kx = bk[64 + lane];
+                        ex = be[64 + lane];
                     }
+                    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                    __builtin_amdgcn_wave_barrier();
+                    if (lane < rest) {
+                        bk[lane] = kx;
+                        be[lane] = ex;
+                    }
+                    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                    __builtin_amdgcn_wave_barrier();
+                    nbuf = rest;
                 }
             }
         }
@@ -1385,7 +1437,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S3_WPE))) v
     // several tasks: flagged steps are queued in chunks taken from a pool (one
     // atomic per MTQ_CHUNK steps) and scored by a later, evenly spread kernel
     // (the steps cluster in the few tiles of the best features)
-    int qchunk = -1, qn = 0;
+    // (wave gw owns chunk gw; further chunks come from the pool above the
+    // launched waves' own, one atomic each)
+    int qchunk = MT ? (int)gw : -1, qn = 0;
     const double *__restrict__ inv_st = c.inv_s + (int64_t)ts * S;
 
     // Tiles are dealt round-robin over the waves (their costs are nearly
@@ -1566,11 +1620,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S3_WPE))) v
                 // pool holds a record per sweep step plus a partly filled
                 // chunk per wave, so a take past its end cannot happen; it
                 // would be reported, not dropped silently
-                if (qchunk != -2 && (qchunk < 0 || qn == MTQ_CHUNK)) {
-                    if (qchunk >= 0 && lane == 0) c.mtq_n[qchunk] = (uint32_t)qn;
+                if (qchunk >= 0 && qn == MTQ_CHUNK) {
+                    if (lane == 0) c.mtq_n[qchunk] = (uint32_t)qn;
                     unsigned got = 0;
                     if (lane == 0) got = atomicAdd(c.mtq_taken, 1u);
-                    got = (unsigned)__shfl((int)got, 0);
+                    got = (unsigned)__shfl((int)got, 0) + gridDim.x * SEARCH_WAVES;
                     qchunk = got < (unsigned)c.mtq_chunks ? (int)got : -2;
                     if (qchunk == -2 && lane == 0) atomicOr(&c.flags[FLAG_CAPACITY], 1u);
                     qn = 0;
@@ -1650,10 +1704,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S3_WPE))) v
 
 // Several tasks, D = 3: exclusive prefix of the queued chunks' counts (one
 // workgroup of PRE_WG threads, PRE_WG consecutive counts per pass).
-__global__ __launch_bounds__(PRE_WG) void mt_scan_kernel(Ctx c) {
+__global__ __launch_bounds__(PRE_WG) void mt_scan_kernel(Ctx c, int nown) {
     __shared__ unsigned wsum[PRE_WG / 64];
     __shared__ unsigned long long carry;
-    const int nreg = (int)min(*c.mtq_taken, (unsigned)c.mtq_chunks);
+    const int nreg = (int)min(*c.mtq_taken + (unsigned)nown, (unsigned)c.mtq_chunks);
     if (threadIdx.x == 0) carry = 0;
     __syncthreads();
     for (int base = 0; base < nreg; base += PRE_WG) {
@@ -1671,10 +1725,10 @@ __global__ __launch_bounds__(PRE_WG) void mt_scan_kernel(Ctx c) {
 
 // Several tasks, D = 3: scores the queued sweep steps.  The steps, in chunk
 // order, are cut into equal contiguous runs, one per wave.  For each step the
-// wave scores the step with mt_step.  Wave gw starts from the sweep's list
-// gw.
+// wave scores the steps with mt_step and mt_flush.  Wave gw starts from the
+// sweep's list gw.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S3_WPE))) void mt_eval_kernel(
-    Ctx c, SearchArgs a, const double *__restrict__ rec) {
+    Ctx c, SearchArgs a, const double *__restrict__ rec, int nown) {
     extern __shared__ double smem[];
     const int KP = a.KP;
     const int lane = threadIdx.x & 63;
@@ -1689,12 +1743,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S3_WPE))) v
     }
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     __builtin_amdgcn_wave_barrier();
-    const int nreg = (int)min(*c.mtq_taken, (unsigned)c.mtq_chunks);
+    const int nreg = (int)min(*c.mtq_taken + (unsigned)nown, (unsigned)c.mtq_chunks);
     const uint64_t total = nreg > 0 ? c.mtq_pre[nreg] : 0;
     const uint64_t per = (total + nw - 1) / nw;
     const uint64_t e0 = (uint64_t)gw * per, e1 = e0 + per < total ? e0 + per : total;
     double th = fmin(theta0_from_prepass(c, a.L, KP), theta_load(c.theta_bits));
     const double theta_f = th < INF ? th * (1.0 + THETA_SLACK) : INF;
+    __shared__ uint64_t s_bk[SEARCH_WAVES][MT_BUF];
+    __shared__ double s_be[SEARCH_WAVES][MT_BUF];
+    uint64_t *bk = s_bk[wave];
+    double *be = s_be[wave];
+    int nbuf = 0;
     unsigned offered = 0;
     if (e0 < e1) {
         int lo = 0, hi = nreg - 1;
@@ -1707,9 +1766,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S3_WPE))) v
             while (reg + 1 <= nreg - 1 && c.mtq_pre[reg + 1] <= e) ++reg;
             const int64_t at = ((int64_t)reg * MTQ_CHUNK + (int64_t)(e - c.mtq_pre[reg])) * 3;
             const uint64_t w0 = c.mtq[at];
-            offered += mt_step(c, a, rec, Ls, Lr, KP, (int64_t)(w0 >> 40), (int64_t)((w0 >> 20) & 0xFFFFF),
-                               (int64_t)(w0 & 0xFFFFF), c.mtq[at + 1], c.mtq[at + 2], theta_f);
+            offered += mt_step(c, a, rec, Ls, Lr, KP, bk, be, nbuf, (int64_t)(w0 >> 40),
+                               (int64_t)((w0 >> 20) & 0xFFFFF), (int64_t)(w0 & 0xFFFFF), c.mtq[at + 1],
+                               c.mtq[at + 2], theta_f);
         }
+        if (nbuf > 0) offered += mt_flush(c, Ls, Lr, KP, bk, be, nbuf, theta_f);
     }
     if (lane == 0 && offered) atomicAdd(c.cand_counter, offered);
     for (int m = lane; m < KP; m += 64) {
@@ -2507,9 +2568,10 @@ int launch_search(const Ctx &c, const SearchCall &sc, hipStream_t st) {
         if (s3 && MT) {
             hipLaunchKernelGGL(search3_kernel<true>, dim3(c.search_wgs), dim3(SEARCH_WG), lds_lists, st, c, a,
                                (const double *)c.rec3, (const uint64_t *)c.cum);
-            hipLaunchKernelGGL(mt_scan_kernel, dim3(1), dim3(PRE_WG), 0, st, c);
+            const int nown = c.search_wgs * SEARCH_WAVES;  // the sweep waves' own chunks
+            hipLaunchKernelGGL(mt_scan_kernel, dim3(1), dim3(PRE_WG), 0, st, c, nown);
             hipLaunchKernelGGL(mt_eval_kernel, dim3(c.search_wgs), dim3(SEARCH_WG), lds_lists, st, c, a,
-                               (const double *)c.rec3);
+                               (const double *)c.rec3, nown);
         }
         else if (s3)
             hipLaunchKernelGGL(search3_kernel<false>, dim3(c.search_wgs), dim3(SEARCH_WG), lds_lists, st, c, a,
