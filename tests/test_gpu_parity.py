@@ -339,3 +339,41 @@ def test_multitask_full_size_sampled():
         if t in top:
             continue
         assert oracle.tuple_sse(p.F, p.y, t, p.task_offsets) >= sk * (1 - 1e-9), t
+
+
+def test_d3_multitask_range_split():
+    """Several tasks, D = 3, searched in lexicographic rank ranges: each part
+    holds only its range's tuples and the merged parts equal the oracle's
+    top-k (the range test sits in the queued-step scoring)."""
+    _say("d3 multi-task range split S=70 n=360 T=3")
+    p = tiny_problem(99, S=70, n=360, T=3, D=3, sigma=0.4, task_sizes=[100, 140, 120])
+    N = math.comb(70, 3)
+    k = 30
+    oidx, osse, _ = oracle.topk(p.F, p.y, 3, k, p.task_offsets)
+    parts = []
+    cuts = [0, 7, 9000, 30001, N]
+    from paper_2502_20072_amd import rank_of
+    for a, b in zip(cuts, cuts[1:]):
+        kk = min(k, b - a)
+        i, s, _ = _run(p, 3, kk, k_max=k, rng=(a, b))
+        for t, v in zip(i, s):
+            if np.isfinite(v):
+                assert a <= rank_of(70, t) < b
+                parts.append((float(v), tuple(int(x) for x in t)))
+    parts.sort()
+    gi = np.array([t for _, t in parts[:k]])
+    gs = np.array([v for v, _ in parts[:k]])
+    compare_topk(p, 3, k, gi, gs, oidx, osse)
+
+
+def test_d3_many_tasks():
+    """20 tasks (padded to 32): the several-task D = 3 search with 32 lanes
+    per tuple in the exact scoring and the one-task-per-workgroup Gram
+    finish, against the oracle."""
+    _say("d3 20 tasks S=40 n=400")
+    sizes = [20] * 20
+    p = tiny_problem(101, S=40, n=400, T=20, D=3, sigma=0.3, task_sizes=sizes)
+    k = 25
+    gidx, gsse, gcoef = _run(p, 3, k)
+    oidx, osse, _ = oracle.topk(p.F, p.y, 3, k, p.task_offsets)
+    compare_topk(p, 3, k, gidx, gsse, oidx, osse, gcoef=gcoef)
