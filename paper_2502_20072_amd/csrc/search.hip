@@ -227,7 +227,8 @@ __device__ void wave_sort_list(double *Ls, uint64_t *Lr, int KP) {
 // {0..N_jb-2}, grouped R at a time.
 __device__ void s3_tile_table(const Ctx &c);
 
-__device__ void search_init_body(const Ctx &c, int64_t e, bool leader, int D, int R, int JB, int s3) {
+__device__ void search_init_body(const Ctx &c, int64_t e, bool leader, int D, int R, int JB, int s3,
+                                 bool clear_pre = true) {
     if (e < (int64_t)(SISSO_MAX_D + 1) * (c.S + 1)) {
         const int r = (int)(e / (c.S + 1));
         const int64_t n = e % (c.S + 1);
@@ -237,7 +238,7 @@ __device__ void search_init_body(const Ctx &c, int64_t e, bool leader, int D, in
         *c.work_counter = 0;
         *c.cand_counter = 0;
         *c.theta_bits = (unsigned long long)__double_as_longlong(INF);
-        *c.pre_count = 0;
+        if (clear_pre) *c.pre_count = 0;  // (else the pre-pass selection runs beside and sets it)
         *c.merge_count = 0;
         *c.mtq_taken = 0;
         c.flags[FLAG_CAPACITY] = 0;
@@ -442,7 +443,7 @@ __device__ int block_pick_first(const double *key, int n, double t, int M, int *
 // explained sum of squares); the PRE_M most relevant full-rank features;
 // every (D-1)-subset of them scored; the PRE_Q best subsets become prefixes.
 template <int D>
-__global__ __launch_bounds__(PRE_WG) void pre_select_kernel(Ctx c) {
+__device__ void pre_select_body(const Ctx &c) {
     __shared__ double key[PRE_SORT];
     __shared__ int id[PRE_SORT];
     __shared__ int pick[PRE_M > PRE_Q ? PRE_M : PRE_Q];
@@ -499,6 +500,11 @@ __global__ __launch_bounds__(PRE_WG) void pre_select_kernel(Ctx c) {
         for (int m = 0; m < q; ++m) c.pre_prefix[tid * MAXD + m] = sel[loc[m]];
     }
     if (tid == 0) *c.pre_count = Q;
+}
+
+template <int D>
+__global__ __launch_bounds__(PRE_WG) void pre_select_kernel(Ctx c) {
+    pre_select_body<D>(c);
 }
 
 // pre_extend: block qq scores every tuple prefix_qq + {k} that does not
@@ -1174,10 +1180,18 @@ __host__ __device__ inline int64_t s3_rows(int64_t S) {
 // comparison) unless i1 < j, column i1 is live and d_j > RANK_EPS.
 // (its grid also does the per-search initialisation of search_init_kernel)
 // Grid: x over (j, r) of one group, y over groups (blockIdx.y = g).
-__global__ __launch_bounds__(256) void rec3_kernel(Ctx c, double *__restrict__ rec) {
+// Launched with PRE_WG threads per workgroup and one workgroup column more
+// than the records need: workgroup (last, 0) runs the pre-pass selection
+// (independent of the table and of the initialisation, which leaves the
+// pre-pass count to it), beside the record workgroups.
+__global__ __launch_bounds__(PRE_WG) void rec3_kernel(Ctx c, double *__restrict__ rec) {
     const int64_t ex = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t g = blockIdx.y;
-    search_init_body(c, g * (int64_t)gridDim.x * blockDim.x + ex, ex == 0 && g == 0, 3, SUBP, JBLK, 1);
+    search_init_body(c, g * (int64_t)gridDim.x * blockDim.x + ex, ex == 0 && g == 0, 3, SUBP, JBLK, 1, false);
+    if (blockIdx.x == gridDim.x - 1 && g == 0) {
+        pre_select_body<3>(c);
+        return;
+    }
     const int64_t S = c.S;
     const int r = (int)(ex % S3_NR);
     const int64_t j = S3_NR * g + 1 + ex / S3_NR;
@@ -2283,6 +2297,112 @@ __global__ __launch_bounds__(256) void rescore_kernel(Ctx c) {
     }
     int32_t tup[MAXD];
     unpack_tuple(c.merged_rank[cand], D, tup);
+    if (c.T > 1) {
+        // several tasks: wave w takes tasks w, w + 4, ... on its own (wave
+        // sums, the small solve repeated in every lane), then the four wave
+        // totals are added in a fixed order
+        __shared__ double wtot[4];
+        __shared__ int wok[4];
+        const int lane = tid & 63, wave = tid >> 6;
+        double tw = 0.0;
+        bool okw = true;
+        for (int t = wave; t < c.T; t += 4) {
+            const int64_t r0 = c.off_dev[t], r1 = c.off_dev[t + 1];
+            const double ym = c.ybar[t];
+            double mu[D];
+#pragma unroll
+            for (int m = 0; m < D; ++m) mu[m] = c.mu[(int64_t)t * c.S + tup[m]];
+            double acc[NACC];
+#pragma unroll
+            for (int i = 0; i < NACC; ++i) acc[i] = 0.0;
+            for (int64_t i = r0 + lane; i < r1; i += 64) {
+                double x[D];
+#pragma unroll
+                for (int m = 0; m < D; ++m) x[m] = c.F[(int64_t)tup[m] * c.n_total + i] - mu[m];
+                const double yc = c.y[i] - ym;
+                int e = 0;
+#pragma unroll
+                for (int m = 0; m < D; ++m)
+#pragma unroll
+                    for (int l = 0; l <= m; ++l) acc[e++] += x[m] * x[l];
+#pragma unroll
+                for (int m = 0; m < D; ++m) acc[e++] += x[m] * yc;
+            }
+#pragma unroll
+            for (int i = 0; i < NACC; ++i)
+                for (int o = 32; o > 0; o >>= 1) acc[i] += __shfl_xor(acc[i], o);
+            double M[D][D], v[D], L[D][D], z[D], bt[D];
+            int e = 0;
+#pragma unroll
+            for (int m = 0; m < D; ++m)
+#pragma unroll
+                for (int l = 0; l <= m; ++l) {
+                    M[m][l] = acc[e];
+                    M[l][m] = acc[e];
+                    ++e;
+                }
+#pragma unroll
+            for (int m = 0; m < D; ++m) v[m] = acc[e++];
+            bool ok = true;
+#pragma unroll
+            for (int m = 0; m < D; ++m) {
+#pragma unroll
+                for (int jx = 0; jx < m; ++jx) {
+                    double sm = M[m][jx];
+#pragma unroll
+                    for (int l = 0; l < jx; ++l) sm -= L[m][l] * L[jx][l];
+                    L[m][jx] = sm / L[jx][jx];
+                }
+                double d = M[m][m];
+#pragma unroll
+                for (int l = 0; l < m; ++l) d -= L[m][l] * L[m][l];
+                ok = ok && (M[m][m] > 0.0) && (d > RANK_EPS * M[m][m]);
+                L[m][m] = ok ? sqrt(d) : 1.0;
+            }
+#pragma unroll
+            for (int m = 0; m < D; ++m) {
+                double sm = v[m];
+#pragma unroll
+                for (int l = 0; l < m; ++l) sm -= L[m][l] * z[l];
+                z[m] = sm / L[m][m];
+            }
+#pragma unroll
+            for (int m = D - 1; m >= 0; --m) {
+                double sm = z[m];
+#pragma unroll
+                for (int l = m + 1; l < D; ++l) sm -= L[l][m] * bt[l];
+                bt[m] = sm / L[m][m];
+            }
+            okw = okw && ok;
+            double ss = 0.0;
+            for (int64_t i = r0 + lane; i < r1; i += 64) {
+                double er = c.y[i] - ym;
+#pragma unroll
+                for (int m = 0; m < D; ++m) er -= bt[m] * (c.F[(int64_t)tup[m] * c.n_total + i] - mu[m]);
+                ss += er * er;
+            }
+            for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o);
+            tw += ss;
+            if (lane == 0) {
+                double alpha = ym;
+#pragma unroll
+                for (int m = 0; m < D; ++m) alpha -= bt[m] * mu[m];
+                coef[t * (c.D_max + 1)] = alpha;
+#pragma unroll
+                for (int m = 0; m < D; ++m) coef[t * (c.D_max + 1) + 1 + m] = bt[m];
+            }
+        }
+        if (lane == 0) {
+            wtot[wave] = tw;
+            wok[wave] = okw ? 1 : 0;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            const bool all = wok[0] && wok[1] && wok[2] && wok[3];
+            c.resc_sse[cand] = all ? ((wtot[0] + wtot[1]) + wtot[2]) + wtot[3] : INF;
+        }
+        return;
+    }
     double total = 0.0;
     bool valid = true;
     for (int t = 0; t < c.T; ++t) {
@@ -2487,8 +2607,8 @@ static void launch_rescore_final(const Ctx &c, int D, int k, hipStream_t st) {
 }
 
 template <int D>
-static void launch_prepass(const Ctx &c, const SearchCall &sc, int L, hipStream_t st) {
-    hipLaunchKernelGGL((pre_select_kernel<D>), dim3(1), dim3(PRE_WG), 0, st, c);
+static void launch_prepass(const Ctx &c, const SearchCall &sc, int L, hipStream_t st, bool select = true) {
+    if (select) hipLaunchKernelGGL((pre_select_kernel<D>), dim3(1), dim3(PRE_WG), 0, st, c);
     hipLaunchKernelGGL((pre_extend_kernel<D>), dim3(PRE_Q), dim3(PRE_WG), 0, st, c, sc.ranged, sc.r0, sc.r1, L);
 }
 
@@ -2549,16 +2669,17 @@ int launch_search(const Ctx &c, const SearchCall &sc, hipStream_t st) {
             // x: the rows of one group (j, r); y: groups; the grid also covers
             // the binomial table of the initialisation
             const int64_t ngr = (c.S - 3) / S3_NR + 1;
-            int64_t bx = ((c.S - 2) * S3_NR + 255) / 256;
+            int64_t bx = ((c.S - 2) * S3_NR + PRE_WG - 1) / PRE_WG;
             const int64_t ninit = (int64_t)init_blocks * 256;
-            if (bx * 256 * ngr < ninit) bx = (ninit / ngr + 255) / 256 + 1;
-            hipLaunchKernelGGL(rec3_kernel, dim3((unsigned)bx, (unsigned)ngr), dim3(256), 0, st, c, c.rec3);
+            if (bx * PRE_WG * ngr < ninit) bx = (ninit / ngr + PRE_WG - 1) / PRE_WG + 1;
+            // one more column: its first workgroup runs the pre-pass selection
+            hipLaunchKernelGGL(rec3_kernel, dim3((unsigned)(bx + 1), (unsigned)ngr), dim3(PRE_WG), 0, st, c, c.rec3);
         } else {
             hipLaunchKernelGGL(search_init_kernel, dim3(init_blocks), dim3(256), 0, st, c, D, a.R, a.JB, 0);
         }
         switch (D) {
             case 2: launch_prepass<2>(c, sc, a.L, st); break;
-            case 3: launch_prepass<3>(c, sc, a.L, st); break;
+            case 3: launch_prepass<3>(c, sc, a.L, st, !s3); break;
             default: launch_prepass<4>(c, sc, a.L, st); break;
         }
         phase_end(c, SISSO_PHASE_PREPASS, st);
