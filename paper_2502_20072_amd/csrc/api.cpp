@@ -4,6 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <map>
 #include <new>
 #include <string>
@@ -83,6 +84,7 @@ static Layout compute_layout(int64_t n_total, int64_t S, int T, int D_max, int k
     };
     const size_t d = sizeof(double);
     L.off_dev = take((T + 1) * sizeof(int64_t));
+    L.torder = take(T * sizeof(int32_t));
     L.ybar = take(T * d);
     L.cyy = take(T * d);
     L.mu = take((size_t)T * S * d);
@@ -164,6 +166,7 @@ static void carve(sisso_l0 *h) {
     c.TP = L.TP;
     c.Gnt = (c.S + GT - 1) / GT;
     c.off_dev = (int64_t *)(base + L.off_dev);
+    c.torder = (int32_t *)(base + L.torder);
     c.ybar = (double *)(base + L.ybar);
     c.cyy = (double *)(base + L.cyy);
     c.mu = (double *)(base + L.mu);
@@ -261,7 +264,15 @@ extern "C" int32_t sisso_l0_create(const sisso_l0_desc *d, sisso_l0 **out) {
     std::vector<int32_t> cbase(d->T + 1, 0);
     for (int t = 0; t < d->T; ++t) cbase[t + 1] = cbase[t] + (int32_t)((o[t + 1] - o[t] + LP_XC - 1) / LP_XC);
     h->ctx.lp_nchunk = h->lay.lp_ns ? cbase[d->T] : 0;
+    // the Gram's workgroups of the largest tasks go first (a task's
+    // workgroups take time in proportion to its rows)
+    std::vector<int32_t> order(d->T);
+    for (int t = 0; t < d->T; ++t) order[t] = t;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t b) { return o[a + 1] - o[a] > o[b + 1] - o[b]; });
     if (hipMemcpyAsync(h->ctx.off_dev, h->offsets.data(), (d->T + 1) * sizeof(int64_t), hipMemcpyHostToDevice,
+                       h->stream) != hipSuccess ||
+        hipMemcpyAsync(h->ctx.torder, order.data(), d->T * sizeof(int32_t), hipMemcpyHostToDevice,
                        h->stream) != hipSuccess ||
         hipMemcpyAsync(h->ctx.lp_cbase, cbase.data(), (d->T + 1) * sizeof(int32_t), hipMemcpyHostToDevice,
                        h->stream) != hipSuccess ||

@@ -196,6 +196,7 @@ __host__ __device__ inline void colex_unrank_small(uint64_t r, int q, int64_t N,
 // Every region is 256-byte aligned; offsets in bytes from the workspace base.
 struct Layout {
     size_t off_dev;    // int64 [T+1]
+    size_t torder;     // int32 [T] tasks by decreasing row count (the Gram's launch order)
     size_t ybar;       // double [T]
     size_t cyy;        // double [T]   |y_t - ybar_t|^2
     size_t mu;         // double [T][S] column means per task

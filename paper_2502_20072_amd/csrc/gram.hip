@@ -149,19 +149,22 @@ constexpr int LDS_STRIDE = GRAM_KC + 1;
 // the register budget is the whole file: no spills around the prefetch.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void gram_kernel(const double *__restrict__ F, int64_t n_total,
                                                    int64_t S, const int64_t *__restrict__ off,
+                                                   const int32_t *__restrict__ torder,
                                                    int T, const double *__restrict__ mu,
                                                    int ntile, int nsplit,
                                                    double *__restrict__ part) {
     __shared__ double As[GRAM_TILE][LDS_STRIDE];
     __shared__ double Bs[GRAM_TILE][LDS_STRIDE];
 
-    // blockIdx.x -> (split, task, tile pair) ; tile pairs enumerate bi <= bj row by row
+    // blockIdx.x -> (split, task rank, tile pair); tile pairs enumerate
+    // bi <= bj row by row; task ranks follow decreasing row counts
     int64_t b = blockIdx.x;
     const int npair = ntile * (ntile + 1) / 2;
     const int split = (int)(b / ((int64_t)T * npair));
     b -= (int64_t)split * T * npair;
-    const int t = (int)(b / npair);
-    int pr = (int)(b - (int64_t)t * npair);
+    const int tr = (int)(b / npair);
+    const int t = torder[tr];
+    int pr = (int)(b - (int64_t)tr * npair);
     int bi = 0;
     while (pr >= ntile - bi) {
         pr -= ntile - bi;
@@ -458,7 +461,7 @@ int launch_gram(const Ctx &c, hipStream_t st) {
         if (launch_gram_lp(c, c.lp_ns, st)) return -1;
     } else {
         hipLaunchKernelGGL(gram_kernel, dim3((unsigned)blocks), dim3(256), 0, st, c.F, c.n_total, c.S,
-                           c.off_dev, c.T, c.mu, ntile, c.nsplit, c.part);
+                           c.off_dev, c.torder, c.T, c.mu, ntile, c.nsplit, c.part);
     }
     const int64_t npair64 = c.Gnt * (c.Gnt + 1) / 2;
     if (c.T > 1 && c.TP <= 16) {

@@ -14,6 +14,7 @@ struct Ctx {
     int64_t Gnt;  // 64-wide tiles per row of the tiled correlation matrices
     // carved from the workspace
     int64_t *off_dev;
+    int32_t *torder;                 // tasks by decreasing row count (the Gram's launch order)
     double *ybar, *cyy, *mu, *inv_s, *bhat, *G, *part;
     uint32_t *flags;
     int32_t *lp_cbase;               // precision form: first chunk of each task [T+1]
