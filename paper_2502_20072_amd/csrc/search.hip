@@ -1446,13 +1446,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S3_WPE))) v
     const double *__restrict__ Gb = c.G1;
     const int TP = c.TP;
     const int ts = c.tstar[0];
-    const int t2 = MT ? c.tstar[1] : -1;
     const int64_t gw = (int64_t)blockIdx.x * SEARCH_WAVES + wave;
-    // several tasks: flagged steps are queued in chunks taken from a pool (one
-    // atomic per MTQ_CHUNK steps) and scored by a later, evenly spread kernel
-    // (the steps cluster in the few tiles of the best features)
-    // (wave gw owns chunk gw; further chunks come from the pool above the
-    // launched waves' own, one atomic each)
+    // several tasks: flagged steps are queued in chunks of MTQ_CHUNK and scored
+    // by a later, evenly spread kernel (the steps cluster in the few tiles of
+    // the best features); wave gw owns chunk gw, further chunks come from the
+    // pool above the launched waves' own, one atomic each
     int qchunk = MT ? (int)gw : -1, qn = 0;
     const double *__restrict__ inv_st = c.inv_s + (int64_t)ts * S;
 
@@ -1677,27 +1675,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S3_WPE))) v
                     const int32_t tup[3] = {(int32_t)(S3_NR * g + r), (int32_t)j, (int32_t)k};
                     // the step's flag covers all four i1 of the group: this
                     // i1's own terms decide (NaN records: i1 >= j or a rank
-                    // deficient pair).  One task: that is the SSE; several:
-                    // it is the filter task's SSE, a lower bound of the sum
+                    // deficient pair)
                     const double es = (d > RANK_EPS) ? p - z * z / d : INF;
-                    bool take = ((fm[sl] >> lane) & 1ull) && k < S && k > j &&
-                                es <= (MT ? theta_f : fmin(theta_f, Ls[KP - 1]));
+                    bool take = ((fm[sl] >> lane) & 1ull) && k < S && k > j && es <= fmin(theta_f, Ls[KP - 1]);
                     if (take && a.ranged) {
                         const uint64_t lr = lex_rank(BinomTab{c.btab, c.S}, c.S, 3, tup);
                         if (lr < a.r0 || lr >= a.r1) take = false;
                     }
-                    if (!MT) {
-                        unsigned long long m = __ballot(take);
-                        const uint64_t rk = take ? pack_tuple(tup, 3) : 0;
-                        offered += (unsigned)__popcll(m);
-                        while (m) {
-                            const int src = __ffsll((long long)m) - 1;
-                            m &= m - 1;
-                            const double cs = __shfl(es, src);
-                            const uint64_t cr = (uint64_t)__shfl((long long)rk, src);
-                            list_insert(Ls, Lr, KP, cs, cr);
-                        }
-                        continue;
+                    unsigned long long m = __ballot(take);
+                    const uint64_t rk = take ? pack_tuple(tup, 3) : 0;
+                    offered += (unsigned)__popcll(m);
+                    while (m) {
+                        const int src = __ffsll((long long)m) - 1;
+                        m &= m - 1;
+                        const double cs = __shfl(es, src);
+                        const uint64_t cr = (uint64_t)__shfl((long long)rk, src);
+                        list_insert(Ls, Lr, KP, cs, cr);
                     }
                 }
             }
