@@ -88,8 +88,10 @@ typedef struct {
 } sisso_l0_desc;
 
 /* Device bytes the caller must provide in desc->workspace for this problem
- * shape (pure function of n_total, S, T, D_max, k_max; reads no pointer).
- * Returns 0 if the shape is invalid. */
+ * shape (pure function of n_total, S, T, D_max, k_max and precision; reads
+ * no pointer).  With several tasks and D_max >= 3 it includes the filter
+ * task's matrix (S^2 doubles) and the D = 3 step queue (24 bytes per sweep
+ * step, at most 1 GiB).  Returns 0 if the shape is invalid. */
 size_t sisso_l0_workspace_bytes(const sisso_l0_desc *desc);
 
 /* Validate the descriptor and create a handle in *out.  Errors: EINVAL for
@@ -199,7 +201,10 @@ int32_t sisso_l0_autotune(sisso_l0 *h, int32_t D, int32_t k, const char *cache_p
  * and the next D entries the coefficients of the tuple's features, in the
  * units of F and y).  Rows beyond the number of full-rank tuples are filled
  * with idx -1, sse +inf, coef NaN.  Errors: ESTATE before a search or for k
- * above the searched k; EINVAL for null idx/sse or non-finite input data. */
+ * above the searched k; EINVAL for null idx/sse or non-finite input data;
+ * EDEVICE for a HIP error, or if the several-task D = 3 search's step queue
+ * overflowed (sized for every sweep step, so it is not expected; the result
+ * would be incomplete and is not returned). */
 int32_t sisso_l0_topk(sisso_l0 *h, int32_t k, int32_t *idx, double *sse, double *coef);
 
 /* Synchronise the stream and copy task t's precomputed statistics to HOST
