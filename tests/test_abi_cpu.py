@@ -131,3 +131,34 @@ def test_precision_modes_size_the_workspace():
     assert bf16 - fp64 >= 3 * 300 * n_chunks * 256 * 2 + 300 * n_chunks * 4
     assert ws(B.SISSO_PREC_FP16_COMP) == 0      # reserved mode, not built
     assert ws(7) == 0
+
+
+def test_several_task_d3_workspace_holds_filter_matrix_and_step_queue():
+    """With several tasks and D_max >= 3 the workspace also holds the filter
+    task's matrix alone (S^2 doubles, one-task tiled, so padded to 64) and
+    the D = 3 step queue (24 bytes per sweep step plus a chunk per wave);
+    neither exists for one task or for D_max = 2."""
+    S = 300
+    Sp = (S + 63) // 64 * 64
+    off2 = np.array([0, 150, 300], dtype=np.int64)
+
+    def ws(offsets, D_max):
+        return B.sisso_l0_workspace_bytes(_desc(n=int(offsets[-1]), S=S, offsets=offsets, D_max=D_max, k_max=20))
+
+    # one task: D_max 3 vs 2 adds only the pair-record table (and scratch)
+    one3, one2 = ws(np.array([0, 300], dtype=np.int64), 3), ws(np.array([0, 300], dtype=np.int64), 2)
+    two3, two2 = ws(off2, 3), ws(off2, 2)
+    extra_one = one3 - one2
+    extra_two = two3 - two2
+    # several tasks add the one-task matrix and the queue on top of that
+    assert extra_two - extra_one >= Sp * Sp * 8
+    # the queue: one 24-byte record per sweep step (tiles x 32 rows, tiles
+    # of 4 first indices x 32 rows x 128 columns) at the least
+    tiles = 0
+    for jb in range((S - 2) // 32 + 1):
+        j0 = jb * 32
+        jmax = min(j0 + 31, S - 2)
+        kc0 = (j0 + 1) // 128
+        ng = (jmax - 1) // 4 + 1 if jmax >= 1 else 0
+        tiles += ((S + 127) // 128 - kc0) * ng
+    assert extra_two - extra_one >= Sp * Sp * 8 + tiles * 32 * 24
