@@ -316,7 +316,7 @@ __global__ __launch_bounds__(256) void gram_finish_kernel(const double *__restri
     const double *ist = inv_s + (int64_t)t * S;
     const bool one = G1 != nullptr && t == *tstar;  // also write the one-task copy
     // each thread owns PER elements of rows [FIN_ROWS qr, FIN_ROWS (qr + 1));
-    // the split partials are summed split by split, two splits of loads in
+    // the split partials are summed split by split, eight splits of loads in
     // flight (indices clamped in range, out-of-range elements masked after)
     constexpr int PER = GT * FIN_ROWS / 256;
     int64_t src[PER];
@@ -333,7 +333,7 @@ __global__ __launch_bounds__(256) void gram_finish_kernel(const double *__restri
     double acc[PER];
 #pragma unroll
     for (int m = 0; m < PER; ++m) acc[m] = 0.0;
-#pragma unroll 2
+#pragma unroll 8
     for (int sp = 0; sp < nsplit; ++sp) {
         const double *P = part + ((int64_t)sp * T + t) * S * S;
 #pragma unroll
