@@ -117,7 +117,7 @@ def main() -> int:
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the search shards by "
-                                   "lexicographic rank range across GPUs (see DESIGN.md) but no "
+                                   "lexicographic rank range across GPUs, but no "
                                    "multi-GPU path is built", "n_gpus": args.gpus}))
         return 2
 

@@ -45,7 +45,7 @@ enum {
     SISSO_ESTATE = -2,  /* call out of order (search before gram, topk before search) */
     SISSO_ENOMEM = -3,  /* caller's workspace smaller than sisso_l0_workspace_bytes */
     SISSO_EDEVICE = -4, /* a HIP runtime call failed; see sisso_l0_last_error */
-    SISSO_ENOTSUP = -5  /* supported but not in this build (e.g. D > SISSO_MAX_D) */
+    SISSO_ENOTSUP = -5  /* a valid request the library does not implement (e.g. D > SISSO_MAX_D) */
 };
 
 enum {

@@ -3,7 +3,7 @@
  * the l0 step (gfx950).  The paper's exhaustive l0 step is the reference;
  * the proposal ranks (D-1)-prefixes by a learned score so that a D-search
  * can evaluate only the extensions of the best-ranked prefixes exactly
- * (sisso_l0_search_list), with exhaustive search as the judge of recall.
+ * (sisso_l0_search_list), with exhaustive search as the reference for recall.
  *
  * Network: x (SISSO_MLP_IN features, from sisso_l0_prefix_features) ->
  * h1 = relu(x W1 + b1) -> h2 = relu(h1 W2 + b2) -> y = h2 W3 + b3, hidden
