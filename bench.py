@@ -28,13 +28,26 @@ FP64_PEAK = 78.6e12      # MI355X FP64 vector, FLOP/s
 HBM_PEAK = 8.0e12        # bytes/s
 
 
+# Algorithmic FP64 operations of one tuple-task solve (FMA = 2): the
+# incremental root-free Cholesky row of the last index against the prefix,
+# the pivot, the projected right-hand side and the division-free filter, as
+# counted for the method (D = 1: 4, D = 2: 10, D = 3: 17, D = 4: 26).
+ALG_FLOP = {1: 4, 2: 10, 3: 17, 4: 26}
+
+
 def search_flop_per_tuple(D: int, T: int) -> float:
-    """Algorithmic FP64 operations of one tuple in the search kernel.
+    """Algorithmic FP64 operations per tuple: ALG_FLOP[D] per task."""
+    return float(ALG_FLOP[D] * T)
+
+
+def issued_flop_per_tuple(D: int, T: int) -> float:
+    """FP64 operations the search kernel actually issues per tuple.
 
     Per task, with the prefix's Cholesky row and the k-dependent part of the
-    sub-prefix solve hoisted: u = g - v.w (D-2 FMA), d = d' - alpha u^2
-    (1 MUL + 1 FMA), zeta = zeta' - zs u (1 FMA), and the division-free test
-    zeta^2 >= pi d (2 MUL).  FMA counts 2.  Single task: 2(D-2) + 3 + 2 + 2.
+    sub-prefix solve hoisted out of the sweep: u = g - v.w (D-2 FMA),
+    d = d' - alpha u^2 (1 MUL + 1 FMA), zeta = zeta' - zs u (1 FMA), and the
+    division-free test zeta^2 >= pi d (2 MUL).  FMA counts 2.
+    Single task: 2(D-2) + 3 + 2 + 2.
     """
     per_task = 2 * (D - 2) + 3 + 2 + 2
     if T == 1 or D == 3:
@@ -45,6 +58,21 @@ def search_flop_per_tuple(D: int, T: int) -> float:
     # many tasks: the test becomes p - zeta^2 r with r a Newton-refined
     # reciprocal (1 RCP + 2 FMA + 1 MUL + 1 FMA) and a sum over tasks (1 ADD)
     return float(T * (2 * (D - 2) + 3 + 2 + 1 + 1 + 2 * 2 + 2 + 1))
+
+
+def performed_flop(D: int, T: int, ntup: int) -> tuple:
+    """(FLOP, pruned) of the work one search performs.
+
+    One task, or several tasks at D != 3: every tuple is solved in every task,
+    ALG_FLOP[D] * T per tuple.  Several tasks at D = 3: the sweep solves every
+    tuple in one task only (its SSE is a lower bound of the sum over tasks, so
+    the tuples it rejects are pruned exactly) and only the survivors are solved
+    in every task; the work performed is the one-task sweep, ALG_FLOP[3] per
+    tuple, and the few survivors' solves are not counted.
+    """
+    if T > 1 and D == 3:
+        return float(ALG_FLOP[3]) * ntup, True
+    return search_flop_per_tuple(D, T) * ntup, False
 
 
 def measured_traffic(kernel: str, workload: str):
@@ -112,6 +140,8 @@ def main() -> int:
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="before the timed region, copy a buffer of this many MiB three times with torch "
                          "(a plain copy kernel of known size, to calibrate HBM byte counters)")
+    ap.add_argument("--chosen-form", default="multitask_t16_s1500_d3",
+                    help="workload of the chosen (several-task) form reported beside the plain line; '' for none")
     ap.add_argument("--search-grid", type=int, default=0,
                     help="fix the search grid (workgroups) instead of autotuning it, e.g. for counter runs")
     args = ap.parse_args()
@@ -121,7 +151,6 @@ def main() -> int:
                                    "multi-GPU path is built", "n_gpus": args.gpus}))
         return 2
 
-    import numpy as np
     import torch
 
     from synth import make_config
@@ -136,27 +165,73 @@ def main() -> int:
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    from paper_2502_20072_amd import L0Search
     from paper_2502_20072_amd import _binding as B
 
     if args.workload == "batch64_d3":
         return bench_batch(args)
     p = make_config(args.workload)
-    D, k = p.D, p.k
     if args.form == "learned":
         return bench_learned(args, p)
-    ntup = math.comb(p.S, D)
-    dev = torch.device("cuda:0")
-    print(f"bench: workload={args.workload} n={p.n} S={p.S} T={p.T} D={D} k={k} "
-          f"tuples={ntup}", file=sys.stderr, flush=True)
     prec = B.SISSO_PREC_BF16_COMP if args.precision == "bf16" else B.SISSO_PREC_FP64
+    res = bench_exhaustive(args, p, args.workload, prec, args.steps, args.warmup, args.search_grid)
+    res = {"metric": METRIC, **res}
+    if args.chosen_form and args.workload != args.chosen_form:
+        # the chosen form (several tasks of uneven size, D = 3) beside the
+        # plain FP64 line; its own top-k is checked on a stored oracle range
+        q = make_config(args.chosen_form)
+        cf = bench_exhaustive(args, q, args.chosen_form, B.SISSO_PREC_FP64, max(1, args.steps // 2),
+                              max(1, args.warmup), 0)
+        res["chosen_form"] = cf
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline(p, p.D, p.k, args.cpu_seconds)
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+def golden_check(p, name: str, idx, sse, i1_range=None):
+    """Compare a top-k with the stored oracle result of the same workload.
+
+    Returns (matches, note).  matches is None when there is no stored result
+    or the regenerated inputs differ from the ones it was computed on
+    (sha256 of F, y and the task offsets).  Otherwise True iff the index
+    lists are identical and every SSE is within a relative 1e-10."""
+    import numpy as np
+    from synth import input_digest
+
+    tag = f"_i1_{i1_range[0]}_{i1_range[1]}" if i1_range else ""
+    path = os.path.join(ROOT, "tests", "golden", f"oracle_topk_{name}{tag}.json")
+    if not os.path.exists(path):
+        return None, f"no stored oracle result {os.path.basename(path)}"
+    g = json.load(open(path))
+    if g.get("input_sha256") != input_digest(p):
+        return None, "regenerated inputs differ from the stored result's (sha256)"
+    gi = [tuple(int(v) for v in t) for t in idx]
+    oi = [tuple(int(v) for v in t) for t in g["idx"]]
+    osse = np.array(g["sse"])
+    rel = float(np.max(np.abs(np.asarray(sse) - osse) / osse))
+    ok = bool(gi == oi and rel <= 1e-10)
+    return ok, f"{os.path.basename(path)}: indices {'equal' if gi == oi else 'differ'}, max rel SSE diff {rel:.2e}"
+
+
+def bench_exhaustive(args, p, name: str, prec: int, steps: int, warmup: int, search_grid: int) -> dict:
+    """Time whole steps (gram + search + topk) of one workload; returns the
+    fields of a bench line (without the metric)."""
+    import numpy as np
+    import torch
+
+    from paper_2502_20072_amd import L0Search
+    from paper_2502_20072_amd import _binding as B
+
+    D, k = p.D, p.k
+    ntup = math.comb(p.S, D)
+    print(f"bench: workload={name} n={p.n} S={p.S} T={p.T} D={D} k={k} tuples={ntup}",
+          file=sys.stderr, flush=True)
     s = L0Search(p.F, p.y, p.task_offsets, D_max=D, k_max=k, device="cuda:0", precision=prec)
-    stream = s.stream
     # launch tuning on the problem itself (changes no arithmetic), before timing
     s.gram()
-    if args.search_grid > 0:
-        s.set_search_grid(args.search_grid)
-        grid = args.search_grid
+    if search_grid > 0:
+        s.set_search_grid(search_grid)
+        grid = search_grid
     else:
         grid = s.autotune(D, k, args.tune_cache)
 
@@ -165,73 +240,78 @@ def main() -> int:
         s.search(D, k)
         return s.topk(k)
 
-    for _ in range(args.warmup):
-        out = step()
-    # correctness of the benchmarked output against the stored oracle result
-    gold_path = os.path.join(ROOT, "tests", "golden", f"oracle_topk_{args.workload}.json")
-    matches = None
-    if os.path.exists(gold_path):
-        g = json.load(open(gold_path))
-        gi = [tuple(int(v) for v in t) for t in out[0]]
-        oi = [tuple(int(v) for v in t) for t in g["idx"]]
-        rel = float(np.max(np.abs(out[1] - np.array(g["sse"])) / np.array(g["sse"])))
-        matches = bool(gi == oi and rel <= 1e-10)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
+    out = None
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = step()
+    torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    ms_step = dt / args.steps * 1e3
-    value = ntup * args.steps / dt
+    ms_step = dt / steps * 1e3
+    # correctness of the last timed step's output against the stored oracle result
+    if p.T == 1:
+        matches, note = golden_check(p, name, out[0], out[1])
+    else:
+        # several tasks: the stored oracle result covers the tuples whose first
+        # index is 0 or 1; search that rank range and compare
+        r1 = ntup - math.comb(p.S - 2, D)
+        s.search_range(D, k, 0, r1)
+        ri, rs, _ = s.topk(k)
+        matches, note = golden_check(p, name, ri, rs, (0, 2))
+        note += f" (rank range [0, {r1}) = first index in [0, 2))"
 
     # per-phase times with HIP events on the library's stream (separate pass,
     # same launches), averaged over the same number of steps
     B.sisso_l0_profile(s.handle, True)
     acc = {ph: 0.0 for ph in B.PHASES}
-    for _ in range(args.steps):
+    for _ in range(steps):
         s.gram()
         s.search(D, k)
         ms = B.sisso_l0_phase_ms(s.handle)
         for ph in acc:
-            acc[ph] += ms[ph] / args.steps
+            acc[ph] += ms[ph] / steps
     B.sisso_l0_profile(s.handle, False)
     search_s = acc["search"] * 1e-3
-    flop = search_flop_per_tuple(D, p.T) * ntup
+    flop, pruned = performed_flop(D, p.T, ntup)
     achieved = flop / search_s
     kname = "search3_kernel" if D == 3 else "search_kernel"
     roofline = dict(bound="alu", kernel=kname, achieved=achieved / 1e12, peak=FP64_PEAK / 1e12,
-                    unit="TFLOP/s", frac=achieved / FP64_PEAK, traffic=measured_traffic(kname, args.workload),
-                    flop_per_tuple=search_flop_per_tuple(D, p.T),
+                    unit="TFLOP/s", frac=achieved / FP64_PEAK, traffic=measured_traffic(kname, name),
+                    flop_per_tuple=flop / ntup, issued_flop_per_tuple=issued_flop_per_tuple(D, p.T),
                     search_ms=acc["search"], search_tuples_per_s=ntup / search_s)
+    if pruned:
+        roofline["pruned"] = ("several tasks at D=3: the sweep solves every tuple in the task of largest "
+                              "|y_t - mean|^2 only (an exact lower bound of the sum); the survivors' "
+                              "all-task solves are not counted")
     res = {
-        "metric": METRIC,
-        "value": value,
+        "value": ntup * steps / dt,
         "unit": "tuples/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": steps,
+        "warmup": warmup,
         "ms_per_step": ms_step,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "n": p.n, "S": p.S, "T": p.T, "D": D, "k": k,
+        "config": {"workload": name, "n": p.n, "S": p.S, "T": p.T, "D": D, "k": k,
                    "tuples": ntup, "form": "plain FP64" if prec == B.SISSO_PREC_FP64 else
                    "precision form (Gram from BF16 slices, FP64 search and re-score)",
                    "search_grid": grid},
         "topk_matches_oracle": matches,
+        "oracle_check": note,
         "phase_ms": acc,
         "roofline": roofline,
     }
+    if p.T > 1:
+        res["tuple_task_solves_per_s"] = ntup * p.T * steps / dt
     if prec != B.SISSO_PREC_FP64:
         res["precision_report"] = s.precision_report(4096)
     s.close()
-    if not args.no_cpu:
-        res["cpu_baseline"] = cpu_baseline(p, D, k, args.cpu_seconds)
-    print(json.dumps(res), flush=True)
-    return 0
+    return res
 
 
 def bench_batch(args) -> int:

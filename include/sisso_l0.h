@@ -170,6 +170,14 @@ int32_t sisso_l0_search_batch(sisso_l0 *const *hs, int32_t P, int32_t D, int32_t
 int32_t sisso_l0_prefix_best(sisso_l0 *h, int32_t m, const int32_t *prefixes, int64_t n, double *best);
 int32_t sisso_l0_prefix_features(sisso_l0 *h, int32_t m, const int32_t *prefixes, int64_t n, float *feat);
 int32_t sisso_l0_search_list(sisso_l0 *h, int32_t D, int32_t k, const int32_t *prefixes, int64_t n);
+/* Training target of each prefix (the label a learned proposal is fitted
+ * to): runs sisso_l0_prefix_best into best (DEVICE double [n]) and then sets
+ * target[p] (DEVICE float [n]) = -log10(best[p] / c), c = sum over tasks of
+ * |y_t - mean(y_t)|^2, with the fraction clamped to [1e-12, 1]; a prefix
+ * with no full-rank extension, or a malformed row, gets 0.  Same arguments,
+ * rules and errors as sisso_l0_prefix_best, plus EINVAL for a null target. */
+int32_t sisso_l0_prefix_target(sisso_l0 *h, int32_t m, const int32_t *prefixes, int64_t n, double *best,
+                               float *target);
 /* Features (as sisso_l0_prefix_features) of the m-subsets of {0..S-1}
  * (1 <= m <= 3) with colexicographic ranks r0 .. r0 + n - 1, i.e. ordered
  * by largest element, then by the rest in the same order; feat: DEVICE
@@ -230,6 +238,16 @@ uint64_t sisso_l0_scored(const sisso_l0 *h);
  * search); out[3]: slices per value (0 for FP64).  ESTATE before
  * sisso_gram; EINVAL for nsample < 1 or a null out. */
 int32_t sisso_l0_precision_report(sisso_l0 *h, int32_t nsample, double *out);
+
+/* Gram error of the handle's precision mode (section "l0-regularization"
+ * names precision as the method's main accuracy/speed trade-off): the
+ * largest |G_used - G_fp64| over 4096 sampled entries per task of the
+ * correlation matrices, whose entries lie in [-1, 1], so the absolute error
+ * is also the error relative to the unit diagonal.  G_fp64 is the centred
+ * dot product recomputed in FP64 straight from F.  Equals out[0] of
+ * sisso_l0_precision_report(h, 4096, out).  Synchronises the stream; ESTATE
+ * before sisso_gram, EINVAL for null arguments. */
+int32_t sisso_gram_error(sisso_l0 *h, double *max_abs_rel);
 
 /* Per-phase timing with HIP events recorded on the handle's stream.
  * sisso_l0_profile(h, 1) turns it on (0 off; off by default).  After a

@@ -282,20 +282,34 @@ int64_t oracle_l0_topk(const double *F, const double *y, const int64_t *off, int
         int me = 0;
         double *work;
         int32_t tup[ORACLE_MAX_D];
-        int64_t i1;
+        int64_t u, nunits;
 #ifdef _OPENMP
         me = omp_get_thread_num();
 #endif
         work = (double *)malloc(sizeof(double) * (size_t)(D + 2) * (size_t)max_task_rows(off, T));
+        /* A unit of parallel work is one first index (D = 1) or one pair of
+         * leading indices (i1, i2) (D >= 2), so that a range of a few first
+         * indices still keeps every thread busy.  The scheduling changes no
+         * result: every tuple is scored by the same per-tuple QR and the
+         * per-thread heaps are merged by (SSE, lex tuple). */
+        nunits = D == 1 ? i1_hi - i1_lo : (i1_hi - i1_lo) * S;
 #ifdef _OPENMP
 #pragma omp for schedule(dynamic, 1)
 #endif
-        for (i1 = i1_lo; i1 < i1_hi; ++i1) {
-            /* nested loops over i_2 < ... < i_D, written as an odometer */
-            int m;
+        for (u = 0; u < nunits; ++u) {
+            /* nested loops over i_3 < ... < i_D, written as an odometer */
+            int m, lead;
+            const int64_t i1 = i1_lo + (D == 1 ? u : u / S);
             if (S - i1 < D) continue;
             tup[0] = (int32_t)i1;
-            for (m = 1; m < D; ++m) tup[m] = tup[m - 1] + 1;
+            lead = 1;
+            if (D >= 2) {
+                const int64_t i2 = u % S;
+                if (i2 <= i1 || S - i2 < D - 1) continue;
+                tup[1] = (int32_t)i2;
+                lead = 2;
+            }
+            for (m = lead; m < D; ++m) tup[m] = tup[m - 1] + 1;
             for (;;) {
                 cand_t c;
                 int t;
@@ -311,10 +325,10 @@ int64_t oracle_l0_topk(const double *F, const double *y, const int64_t *off, int
                     for (m = 0; m < D; ++m) c.tup[m] = tup[m];
                     heap_offer(&heaps[me], &c);
                 }
-                /* advance the odometer over positions 1..D-1 */
+                /* advance the odometer over positions lead..D-1 */
                 m = D - 1;
-                while (m >= 1 && tup[m] == S - D + m) --m;
-                if (m < 1) break;
+                while (m >= lead && tup[m] == S - D + m) --m;
+                if (m < lead) break;
                 ++tup[m];
                 for (++m; m < D; ++m) tup[m] = tup[m - 1] + 1;
             }

@@ -232,6 +232,15 @@ def sisso_l0_precision_report(h: int, nsample: int = 4096) -> dict:
                 slices=int(out[3]))
 
 
+def sisso_gram_error(h: int) -> float:
+    lib = load()
+    lib.sisso_gram_error.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]
+    lib.sisso_gram_error.restype = ctypes.c_int32
+    out = ctypes.c_double(0.0)
+    _check(lib.sisso_gram_error(h, ctypes.byref(out)), h)
+    return float(out.value)
+
+
 def sisso_l0_set_search_grid(h: int, workgroups: int) -> None:
     lib = load()
     lib.sisso_l0_set_search_grid.argtypes = [ctypes.c_void_p, ctypes.c_int32]
@@ -319,6 +328,7 @@ def _prop_sigs(lib):
         return
     P, V, I32, I64, U64, SZ = ctypes.POINTER, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_size_t
     for name, args in [("sisso_l0_prefix_best", [V, I32, V, I64, V]),
+                       ("sisso_l0_prefix_target", [V, I32, V, I64, V, V]),
                        ("sisso_l0_prefix_features", [V, I32, V, I64, V]),
                        ("sisso_l0_prefix_features_range", [V, I32, U64, I64, V]),
                        ("sisso_l0_search_list", [V, I32, I32, V, I64]),
@@ -355,6 +365,10 @@ def _raw_check(rc: int, what: str):
 
 def sisso_l0_prefix_best(h: int, m: int, prefixes, best) -> None:
     _check(_plib().sisso_l0_prefix_best(h, m, _ptr(prefixes), prefixes.shape[0], _ptr(best)), h)
+
+
+def sisso_l0_prefix_target(h: int, m: int, prefixes, best, target) -> None:
+    _check(_plib().sisso_l0_prefix_target(h, m, _ptr(prefixes), prefixes.shape[0], _ptr(best), _ptr(target)), h)
 
 
 def sisso_l0_prefix_features(h: int, m: int, prefixes, feat) -> None:

@@ -364,6 +364,17 @@ extern "C" int32_t sisso_l0_prefix_best(sisso_l0 *h, int32_t m, const int32_t *p
     return SISSO_OK;
 }
 
+extern "C" int32_t sisso_l0_prefix_target(sisso_l0 *h, int32_t m, const int32_t *prefixes, int64_t n, double *best,
+                                          float *target) {
+    int32_t rc = sisso_l0_prefix_best(h, m, prefixes, n, best);
+    if (rc != SISSO_OK) return rc;
+    if (n > 0 && !target) return fail(h, SISSO_EINVAL, "null output");
+    if (n == 0) return SISSO_OK;
+    if (launch_prefix_target(h->ctx, best, n, target, h->stream))
+        return fail(h, SISSO_EDEVICE, hipGetErrorString(hipGetLastError()));
+    return SISSO_OK;
+}
+
 extern "C" int32_t sisso_l0_prefix_features(sisso_l0 *h, int32_t m, const int32_t *prefixes, int64_t n, float *feat) {
     int32_t rc = check_prefixes(h, m, prefixes, n);
     if (rc != SISSO_OK) return rc;
@@ -604,6 +615,15 @@ extern "C" int32_t sisso_l0_precision_report(sisso_l0 *h, int32_t nsample, doubl
     out[1] = (double)nsample * h->desc.T;
     out[2] = h->search_done ? s : 0.0;
     out[3] = h->lay.lp_ns;
+    return SISSO_OK;
+}
+
+extern "C" int32_t sisso_gram_error(sisso_l0 *h, double *max_abs_rel) {
+    if (!h || !max_abs_rel) return SISSO_EINVAL;
+    double rep[4];
+    const int32_t rc = sisso_l0_precision_report(h, 4096, rep);
+    if (rc != SISSO_OK) return rc;
+    *max_abs_rel = rep[0];
     return SISSO_OK;
 }
 

@@ -2717,6 +2717,29 @@ int launch_prefix_best(const Ctx &c, int M, const int32_t *pre, int64_t n, doubl
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+// Training target of a prefix from its best extension's SSE:
+// -log10(best / sum_t |y_t - mean|^2), the fraction clamped to [1e-12, 1];
+// a prefix with no full-rank extension (best = +inf) or a malformed row
+// (NaN) gets 0 (fraction 1).
+__global__ void prefix_target_kernel(const double *__restrict__ cyy, int T, const double *__restrict__ best,
+                                     int64_t n, float *__restrict__ target) {
+    double ctot = 0.0;
+    for (int t = 0; t < T; ++t) ctot += cyy[t];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double b = best[i];
+        double frac = b / ctot;
+        frac = frac < 1e-12 ? 1e-12 : (frac > 1.0 ? 1.0 : frac);
+        if (!(b <= 1.7976931348623157e308)) frac = 1.0;  // +inf or NaN
+        target[i] = (float)(-log10(frac));
+    }
+}
+
+int launch_prefix_target(const Ctx &c, const double *best, int64_t n, float *target, hipStream_t st) {
+    const unsigned blocks = (unsigned)(n < 262144 ? (n + 255) / 256 : 1024);
+    hipLaunchKernelGGL(prefix_target_kernel, dim3(blocks), dim3(256), 0, st, c.cyy, c.T, best, n, target);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 int launch_prefix_features(const Ctx &c, int M, const int32_t *pre, int64_t n, float *out, hipStream_t st) {
     const unsigned blocks = (unsigned)((n + 255) / 256);
     switch (M) {

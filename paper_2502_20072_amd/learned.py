@@ -42,17 +42,11 @@ def all_prefixes(S: int, m: int, device="cuda:0"):
     return pre
 
 
-def prefix_targets(best, ctot: float):
-    """Training target: -log10 of the best extension's SSE as a fraction of
-    the total sum of squares (larger = better prefix)."""
-    import torch
-    frac = torch.clamp(best / ctot, min=1e-12, max=1.0)
-    frac = torch.where(torch.isfinite(best), frac, torch.ones_like(frac))
-    return (-torch.log10(frac)).to(torch.float32)
-
-
 def training_set(problems: Sequence, m: int, device="cuda:0"):
-    """Features and targets of every m-subset of every problem (GPU)."""
+    """Features and targets of every m-subset of every problem (GPU).
+
+    The target of a prefix is -log10(best extension SSE / total sum of
+    squares), computed on the device by sisso_l0_prefix_target."""
     import torch
     from . import L0Search
     xs, ys = [], []
@@ -62,12 +56,11 @@ def training_set(problems: Sequence, m: int, device="cuda:0"):
         pre = all_prefixes(p.S, m, device)
         feat = torch.empty((pre.shape[0], B.PROP_NF), dtype=torch.float32, device=device)
         best = torch.empty(pre.shape[0], dtype=torch.float64, device=device)
+        target = torch.empty(pre.shape[0], dtype=torch.float32, device=device)
         B.sisso_l0_prefix_features(s.handle, m, pre, feat)
-        B.sisso_l0_prefix_best(s.handle, m, pre, best)
-        ctot = float(sum(((p.y[a:b] - p.y[a:b].mean()) ** 2).sum()
-                         for a, b in zip(p.task_offsets[:-1], p.task_offsets[1:])))
+        B.sisso_l0_prefix_target(s.handle, m, pre, best, target)
         xs.append(feat)
-        ys.append(prefix_targets(best, ctot))
+        ys.append(target)
         torch.cuda.synchronize()
         s.close()
     return torch.cat(xs), torch.cat(ys)
@@ -89,9 +82,16 @@ class ProposalNet:
         self.params = torch.from_numpy(flat).to(device)
 
     def fit(self, X, Y, epochs: int = 20, batch: int = 4096, lr: float = 2e-3, seed: int = 0) -> List[float]:
-        """Adam on the mean squared error; returns the mean loss per epoch."""
+        """Adam on the mean squared error; returns the mean loss per epoch.
+
+        Each epoch visits every example once in a seeded random order, in
+        batches of ``batch`` (clamped to the number of examples); the last
+        batch of an epoch holds the remainder."""
         import torch
-        n = X.shape[0]
+        n = int(X.shape[0])
+        if n < 1:
+            raise ValueError("fit needs at least one training example")
+        batch = max(1, min(int(batch), n))
         grad = torch.zeros_like(self.params)
         m = torch.zeros_like(self.params)
         v = torch.zeros_like(self.params)
@@ -104,16 +104,18 @@ class ProposalNet:
         for _ in range(epochs):
             perm = torch.randperm(n, generator=gen).to(self.device)
             tot, cnt = 0.0, 0
-            for b0 in range(0, n - batch + 1, batch):
+            for i, b0 in enumerate(range(0, n, batch)):
                 idx = perm[b0:b0 + batch]
                 xb, yb = X[idx].contiguous(), Y[idx].contiguous()
-                B.sisso_mlp_forward(self.params, xb, out, ws, st)
+                nb = int(idx.shape[0])
+                B.sisso_mlp_forward(self.params, xb, out[:nb], ws, st)
                 B.sisso_mlp_backward(self.params, xb, yb, grad, loss, ws, st)
                 step += 1
                 B.sisso_mlp_adam(self.params, grad, m, v, step, lr, st)
-                tot += float(loss.item()) if (cnt % 16 == 0) else 0.0
-                cnt += 1
-            hist.append(tot / max(1, (cnt + 15) // 16))
+                if i % 16 == 0:   # sample the loss without a sync per batch
+                    tot += float(loss.item())
+                    cnt += 1
+            hist.append(tot / max(1, cnt))
         return hist
 
     def predict(self, X):

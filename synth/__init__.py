@@ -11,7 +11,9 @@ from .problems import (  # noqa: F401
     CONFIGS,
     make_problem,
     make_config,
+    make_batch_problem,
     make_batch_problems,
     tiny_problem,
     integer_problem,
+    input_digest,
 )

@@ -270,18 +270,20 @@ def make_config(name: str, seed: Optional[int] = None, **override) -> Problem:
     return make_problem(name=name, **cfg)
 
 
+def make_batch_problem(i: int, seed0: int = 4100, D: int = 3, k: int = 100,
+                       S_range=(200, 2000), n_range=(100, 5000), sigma: float = 0.05) -> Problem:
+    """Problem i of the batch of independent single-task searches (seed seed0 + i)."""
+    rng = np.random.Generator(np.random.PCG64(seed0 + i))
+    S = int(rng.integers(S_range[0], S_range[1] + 1))
+    n = int(rng.integers(n_range[0], n_range[1] + 1))
+    return make_problem(n=n, S=S, D=D, k=k, seed=seed0 + i, beta=(1.5, -0.8, 0.6),
+                        sigma=sigma, name=f"batch_{i}")
+
+
 def make_batch_problems(count: int = 64, seed0: int = 4100, D: int = 3, k: int = 100,
                         S_range=(200, 2000), n_range=(100, 5000), sigma: float = 0.05):
     """Independent single-task searches of different S and n (one seed each)."""
-    out = []
-    for i in range(count):
-        rng = np.random.Generator(np.random.PCG64(seed0 + i))
-        S = int(rng.integers(S_range[0], S_range[1] + 1))
-        n = int(rng.integers(n_range[0], n_range[1] + 1))
-        out.append(make_problem(n=n, S=S, D=D, k=k, seed=seed0 + i,
-                                beta=(1.5, -0.8, 0.6), sigma=sigma,
-                                name=f"batch_{i}"))
-    return out
+    return [make_batch_problem(i, seed0, D, k, S_range, n_range, sigma) for i in range(count)]
 
 
 def tiny_problem(seed: int, S: int, n: int, T: int = 1, D: int = 2, k: int = 5,
@@ -319,3 +321,14 @@ def integer_problem(seed: int, S: int, n: int, lo: int = -4, hi: int = 4, T: int
     meta = dict(name="integer", seed=seed, n=n, S=S, T=T)
     return Problem(F=np.ascontiguousarray(F), y=y, task_offsets=offs, planted=[], D=2, k=5,
                    exprs=[f"z{i}" for i in range(S)], meta=meta)
+
+
+def input_digest(p: Problem) -> str:
+    """SHA-256 of a problem's generated inputs (F, y, task offsets), so a
+    stored result can be tied to the exact bytes it was computed from."""
+    import hashlib
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(p.F).tobytes())
+    h.update(np.ascontiguousarray(p.y).tobytes())
+    h.update(np.ascontiguousarray(p.task_offsets).tobytes())
+    return h.hexdigest()

@@ -66,6 +66,29 @@ def test_mlp_forward_backward_adam_match_reference():
     np.testing.assert_allclose(P.cpu().numpy(), ref_p, rtol=0, atol=2e-6)
 
 
+def test_adam_several_steps_match_reference_and_closed_form():
+    from paper_2502_20072_amd import _binding as B
+    import torch
+    rng = np.random.default_rng(31)
+    flat = rng.normal(size=R.NPARAM).astype(np.float32)
+    g = rng.normal(size=R.NPARAM).astype(np.float32)
+    _say("mlp adam: 5 steps, constant gradient")
+    P, G = _t(flat, np.float32), _t(g, np.float32)
+    m, v = torch.zeros_like(P), torch.zeros_like(P)
+    f64 = lambda a: np.asarray(a, dtype=np.float64)
+    ref, rm, rv = f64(flat), np.zeros(R.NPARAM), np.zeros(R.NPARAM)
+    lr = 1e-3
+    for step in range(1, 6):
+        B.sisso_mlp_adam(P, G, m, v, step, lr, _st())
+        ref, rm, rv = R.adam(ref, f64(g), rm, rv, step, lr)
+        got = P.cpu().numpy().astype(np.float64)
+        # FP32 parameters: each step's update is within a few FP32 ulps
+        np.testing.assert_allclose(got, ref, rtol=0, atol=4e-6 * step + 1e-6 * np.max(np.abs(ref)))
+        # closed form: with a constant gradient every step moves by -lr g/(|g|+eps)
+        np.testing.assert_allclose(got, f64(flat) - step * lr * f64(g) / (np.abs(f64(g)) + 1e-8),
+                                   rtol=0, atol=4e-6 * step + 1e-6 * np.max(np.abs(ref)))
+
+
 def test_bf16_inference_close_to_fp64():
     from paper_2502_20072_amd import _binding as B
     import torch
@@ -131,9 +154,13 @@ def test_prefix_best_and_features_match_oracle(m, T):
     pre = _t(np.array(pick, dtype=np.int32))
     best = torch.empty(len(pick), dtype=torch.float64, device="cuda:0")
     feat = torch.empty((len(pick), 8), dtype=torch.float32, device="cuda:0")
-    B.sisso_l0_prefix_best(s.handle, m, pre, best)
+    target = torch.empty(len(pick), dtype=torch.float32, device="cuda:0")
+    B.sisso_l0_prefix_target(s.handle, m, pre, best, target)
+    best2 = torch.empty_like(best)
+    B.sisso_l0_prefix_best(s.handle, m, pre, best2)
     B.sisso_l0_prefix_features(s.handle, m, pre, feat)
-    best, feat = best.cpu().numpy(), feat.cpu().numpy()
+    assert torch.equal(best, best2)
+    best, feat, target = best.cpu().numpy(), feat.cpu().numpy(), target.cpu().numpy()
     s.close()
     ctot = sum(float(((p.y[a:b] - p.y[a:b].mean()) ** 2).sum())
                for a, b in zip(p.task_offsets[:-1], p.task_offsets[1:]))
@@ -141,6 +168,9 @@ def test_prefix_best_and_features_match_oracle(m, T):
         ref = min(oracle.tuple_sse(p.F, p.y, tuple(sorted(P + (j,))), p.task_offsets)
                   for j in range(p.S) if j not in P)
         assert abs(bv - ref) <= 1e-9 * ref, (P, bv, ref)
+        # training target: -log10 of the best extension's share of the total SS
+        tv = target[pick.index(P)]
+        assert abs(tv - (-np.log10(min(1.0, max(1e-12, ref / ctot))))) <= 1e-5 * max(1.0, abs(tv)), (P, tv)
         # features against their definitions
         r2 = np.array([sum(np.corrcoef(p.F[i, a:b], p.y[a:b])[0, 1] ** 2 * ((p.y[a:b] - p.y[a:b].mean()) ** 2).sum()
                            for a, b in zip(p.task_offsets[:-1], p.task_offsets[1:])) / ctot for i in P])

@@ -45,3 +45,42 @@ def test_first_adam_step_is_signed_learning_rate():
     # bias-corrected moments equal g and g^2 after one step
     np.testing.assert_allclose(new, flat - 0.01 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-12)
     np.testing.assert_allclose(m, 0.1 * g, rtol=1e-15)
+
+
+def _constant_gradient_run(adam, steps, lr=0.01, seed=4):
+    rng = np.random.default_rng(seed)
+    flat, g = rng.normal(size=R.NPARAM), rng.normal(size=R.NPARAM)
+    m, v = np.zeros_like(g), np.zeros_like(g)
+    cur = flat.copy()
+    for t in range(1, steps + 1):
+        cur, m, v = adam(cur, g, m, v, t, lr)
+    return flat, g, cur
+
+
+def test_adam_constant_gradient_moves_by_signed_learning_rate_every_step():
+    # With the same gradient g at every step the moments are m_t = (1-b1^t) g
+    # and v_t = (1-b2^t) g^2, so the bias-corrected moments are exactly g and
+    # g^2 at every step and each step moves every parameter by -lr g/(|g|+eps).
+    for steps in (2, 3, 7, 25):
+        flat, g, cur = _constant_gradient_run(R.adam, steps)
+        np.testing.assert_allclose(cur, flat - steps * 0.01 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-12)
+
+
+def test_adam_pin_catches_wrong_bias_correction():
+    # plausible mistakes in the bias correction pass the first-step pin but
+    # not the constant-gradient pin above
+    def no_step_exponent(flat, grad, m, v, step, lr):
+        b1, b2, eps = 0.9, 0.999, 1e-8
+        m = b1 * m + (1 - b1) * grad
+        v = b2 * v + (1 - b2) * grad * grad
+        return flat - lr * (m / (1 - b1)) / (np.sqrt(v / (1 - b2)) + eps), m, v
+
+    def swapped_betas(flat, grad, m, v, step, lr):
+        b1, b2, eps = 0.9, 0.999, 1e-8
+        m = b1 * m + (1 - b1) * grad
+        v = b2 * v + (1 - b2) * grad * grad
+        return flat - lr * (m / (1 - b2 ** step)) / (np.sqrt(v / (1 - b1 ** step)) + eps), m, v
+
+    for bad in (no_step_exponent, swapped_betas):
+        flat, g, cur = _constant_gradient_run(bad, 3)
+        assert np.max(np.abs(cur - (flat - 3 * 0.01 * g / (np.abs(g) + 1e-8)))) > 1e-4

@@ -32,8 +32,8 @@ MUTANTS = {
                            "(alpha * alpha) / cnorm2[c] <= 1e-2"),
     "tasks_not_summed": ("task_fit(F, y, n, off[t], off[t + 1], tup, D, work, &st, NULL);\n                    s += st;",
                          "task_fit(F, y, n, off[t], off[t + 1], tup, D, work, &st, NULL);\n                    s = st;"),
-    "odometer_skips": ("while (m >= 1 && tup[m] == S - D + m) --m;",
-                       "while (m >= 1 && tup[m] >= S - D + m - 1) --m;"),
+    "odometer_skips": ("while (m >= lead && tup[m] == S - D + m) --m;",
+                       "while (m >= lead && tup[m] >= S - D + m - 1) --m;"),
     "tie_break_reversed": ("if (a->tup[j] < b->tup[j]) return -1;\n        if (a->tup[j] > b->tup[j]) return 1;",
                            "if (a->tup[j] < b->tup[j]) return 1;\n        if (a->tup[j] > b->tup[j]) return -1;"),
     "coef_transposed_R": ("s -= A[(int64_t)c * nt + j] * x[c];",
