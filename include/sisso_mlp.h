@@ -68,6 +68,26 @@ size_t sisso_select_workspace_bytes(void);
 int32_t sisso_select_top(const float *scores, int64_t n, int64_t K, uint64_t *out, int64_t cap, int64_t *count,
                          void *workspace, size_t workspace_bytes, void *stream);
 
+/* Message of the last failed sisso_select_top / sisso_select_top_noalloc
+ * call on this host thread ("" after a successful call). */
+const char *sisso_select_last_error(void);
+
+/* sisso_select_top without a workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same selection, results and errors as
+ * sisso_select_top; its scratch (the two level histograms and the cut
+ * state, sisso_select_noalloc_scratch_bytes() = 16,640 bytes, independent
+ * of n) is a fixed device array of the library that each GPU holds from the
+ * first call on it until the process ends.  The call allocates nothing,
+ * host or device.  The stream must belong to the current device (EINVAL
+ * otherwise).  Every call on one GPU uses that GPU's one array: calls that
+ * overlap in time on the same GPU (several host threads, or several streams
+ * in flight) race and must be serialised by the caller.  The array keeps
+ * the last call's contents; each call clears what it needs before use. */
+size_t sisso_select_noalloc_scratch_bytes(void);
+int32_t sisso_select_top_noalloc(const float *scores, int64_t n, int64_t K, uint64_t *out, int64_t cap,
+                                 int64_t *count, void *stream);
+
 /* Colexicographic unranking of n ranks (DEVICE uint64) into prefix rows
  * (DEVICE int32 [n][m], ascending), 1 <= m <= 3: rank r maps to the r-th
  * m-subset of the non-negative integers ordered by largest element, then

@@ -337,6 +337,7 @@ def _prop_sigs(lib):
                        ("sisso_mlp_adam", [V, V, V, V, I32, ctypes.c_float, V]),
                        ("sisso_mlp_infer_bf16", [V, V, I64, V, V]),
                        ("sisso_select_top", [V, I64, I64, V, I64, P(I64), V, SZ, V]),
+                       ("sisso_select_top_noalloc", [V, I64, I64, V, I64, P(I64), V]),
                        ("sisso_colex_unrank", [I32, V, I64, V, V])]:
         f = getattr(lib, name)
         f.argtypes = args
@@ -345,6 +346,10 @@ def _prop_sigs(lib):
     lib.sisso_mlp_workspace_bytes.restype = SZ
     lib.sisso_select_workspace_bytes.argtypes = []
     lib.sisso_select_workspace_bytes.restype = SZ
+    lib.sisso_select_noalloc_scratch_bytes.argtypes = []
+    lib.sisso_select_noalloc_scratch_bytes.restype = SZ
+    lib.sisso_select_last_error.argtypes = []
+    lib.sisso_select_last_error.restype = ctypes.c_char_p
     _sigs_done = True
 
 
@@ -415,6 +420,21 @@ def sisso_select_top(scores, K: int, out, ws, stream: int) -> int:
     _raw_check(_plib().sisso_select_top(_ptr(scores), scores.shape[0], K, _ptr(out), out.shape[0], ctypes.byref(cnt),
                                         _ptr(ws), ws.numel(), stream), "sisso_select_top")
     return int(cnt.value)
+
+
+def sisso_select_top_noalloc(scores, K: int, out, stream: int) -> int:
+    """sisso_select_top on the library's fixed device scratch (no workspace)."""
+    lib = _plib()
+    cnt = ctypes.c_int64(0)
+    rc = lib.sisso_select_top_noalloc(_ptr(scores), scores.shape[0], K, _ptr(out), out.shape[0],
+                                      ctypes.byref(cnt), stream)
+    if rc != SISSO_OK:
+        raise SissoError(rc, "sisso_select_top_noalloc: " + lib.sisso_select_last_error().decode())
+    return int(cnt.value)
+
+
+def sisso_select_noalloc_scratch_bytes() -> int:
+    return int(_plib().sisso_select_noalloc_scratch_bytes())
 
 
 def sisso_colex_unrank(m: int, ranks, prefixes, stream: int) -> None:

@@ -5,6 +5,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "../../include/sisso_l0.h"
 #include "../../include/sisso_mlp.h"
 #include "common.h"
@@ -465,14 +467,20 @@ extern "C" int32_t sisso_mlp_infer_bf16(const float *params, const float *x, int
 
 extern "C" size_t sisso_select_workspace_bytes(void) { return SEL_BINS * sizeof(unsigned int) + 256; }
 
-extern "C" int32_t sisso_select_top(const float *scores, int64_t n, int64_t K, uint64_t *out, int64_t cap,
-                                    int64_t *count, void *workspace, size_t workspace_bytes, void *stream) {
-    if (!scores || !out || !count || !workspace || n < 1 || K < 1 || K > n || cap < 1 ||
-        workspace_bytes < sisso_select_workspace_bytes())
-        return SISSO_EINVAL;
-    hipStream_t st = (hipStream_t)stream;
-    unsigned int *hist = (unsigned int *)workspace;  // [SEL_BINS], then the state
-    SelState *ss = (SelState *)((char *)workspace + SEL_BINS * sizeof(unsigned int));
+static thread_local const char *g_select_err = "";
+
+static int32_t select_fail(int32_t code, const char *msg) {
+    g_select_err = msg;
+    return code;
+}
+
+// The selection on a scratch area of sisso_select_workspace_bytes() bytes:
+// the level histograms (cleared by a kernel before each level) and the state
+// (every field written before it is read).
+static int32_t select_top(const float *scores, int64_t n, int64_t K, uint64_t *out, int64_t cap, int64_t *count,
+                          void *scratch_area, hipStream_t st) {
+    unsigned int *hist = (unsigned int *)scratch_area;  // [SEL_BINS], then the state
+    SelState *ss = (SelState *)((char *)scratch_area + SEL_BINS * sizeof(unsigned int));
     const unsigned grid = (unsigned)(n / 1024 + 1 < 2048 ? n / 1024 + 1 : 2048);
     for (int level = 0; level < 2; ++level) {
         hipLaunchKernelGGL(sel_clear_kernel, dim3(1), dim3(1024), 0, st, hist);
@@ -483,11 +491,79 @@ extern "C" int32_t sisso_select_top(const float *scores, int64_t n, int64_t K, u
     unsigned long long h = 0;
     if (hipMemcpyAsync(&h, &ss->count, sizeof h, hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
-        return SISSO_EDEVICE;
+        return select_fail(SISSO_EDEVICE, "a HIP call of the selection failed");
     *count = (int64_t)h;
-    if (launched() != SISSO_OK) return SISSO_EDEVICE;
-    return (int64_t)h > cap ? SISSO_EINVAL : SISSO_OK;
+    if (launched() != SISSO_OK) return select_fail(SISSO_EDEVICE, "a selection kernel failed to launch");
+    if ((int64_t)h > cap) return select_fail(SISSO_EINVAL, "more scores selected than cap");
+    return SISSO_OK;
 }
+
+static bool select_args_ok(const float *scores, int64_t n, int64_t K, const uint64_t *out, int64_t cap,
+                           const int64_t *count) {
+    return scores && out && count && n >= 1 && K >= 1 && K <= n && cap >= 1;
+}
+
+extern "C" int32_t sisso_select_top(const float *scores, int64_t n, int64_t K, uint64_t *out, int64_t cap,
+                                    int64_t *count, void *workspace, size_t workspace_bytes, void *stream) {
+    g_select_err = "";
+    if (!select_args_ok(scores, n, K, out, cap, count) || !workspace)
+        return select_fail(SISSO_EINVAL, "null pointer, or n, K, cap out of range");
+    if (workspace_bytes < sisso_select_workspace_bytes())
+        return select_fail(SISSO_EINVAL, "workspace smaller than sisso_select_workspace_bytes()");
+    return select_top(scores, n, K, out, cap, count, workspace, (hipStream_t)stream);
+}
+
+// ---------------------------------------------- selection without a workspace
+// For callers that cannot allocate device memory: the selection's scratch
+// lives in this fixed device array.  Every GPU holds its own copy until the
+// process ends; host code reaches it only through the address that
+// hipGetSymbolAddress returns on that device (the array's name is not a
+// device address in host code).
+constexpr size_t SEL_SCRATCH_BYTES = SEL_BINS * sizeof(unsigned int) + 256;
+static __device__ __align__(256) unsigned char scratch[SEL_SCRATCH_BYTES];
+static_assert(sizeof(SelState) <= 256, "selection state fits its slot");
+
+constexpr int SEL_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[SEL_MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.
+static int32_t scratch_address(void **out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return select_fail(SISSO_EDEVICE, "hipGetDevice failed");
+    if (dev < 0 || dev >= SEL_MAX_DEVICES) return select_fail(SISSO_ENOTSUP, "device index beyond 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p)
+            return select_fail(SISSO_EDEVICE, "hipGetSymbolAddress of the selection scratch failed");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return SISSO_OK;
+}
+
+extern "C" size_t sisso_select_noalloc_scratch_bytes(void) { return SEL_SCRATCH_BYTES; }
+
+extern "C" int32_t sisso_select_top_noalloc(const float *scores, int64_t n, int64_t K, uint64_t *out, int64_t cap,
+                                            int64_t *count, void *stream) {
+    g_select_err = "";
+    if (!select_args_ok(scores, n, K, out, cap, count))
+        return select_fail(SISSO_EINVAL, "null pointer, or n, K, cap out of range");
+    if (sisso_select_workspace_bytes() > SEL_SCRATCH_BYTES)
+        return select_fail(SISSO_ENOMEM, "the selection needs more scratch than the fixed device array holds");
+    hipStream_t st = (hipStream_t)stream;
+    int cur = -1, sdev = -1;
+    if (hipGetDevice(&cur) != hipSuccess || hipStreamGetDevice(st, &sdev) != hipSuccess)
+        return select_fail(SISSO_EDEVICE, "cannot query the current device or the stream's device");
+    if (sdev != cur) return select_fail(SISSO_EINVAL, "the stream must belong to the current device");
+    void *area = nullptr;
+    const int32_t rc = scratch_address(&area);
+    if (rc != SISSO_OK) return rc;
+    return select_top(scores, n, K, out, cap, count, area, st);
+}
+
+extern "C" const char *sisso_select_last_error(void) { return g_select_err; }
 
 extern "C" int32_t sisso_colex_unrank(int32_t m, const uint64_t *ranks, int64_t n, int32_t *prefixes, void *stream) {
     if (m < 1 || m > 3 || !ranks || !prefixes || n < 0) return SISSO_EINVAL;
