@@ -440,3 +440,191 @@ def sisso_select_noalloc_scratch_bytes() -> int:
 def sisso_colex_unrank(m: int, ranks, prefixes, stream: int) -> None:
     _raw_check(_plib().sisso_colex_unrank(m, _ptr(ranks), ranks.shape[0], _ptr(prefixes), stream),
                "sisso_colex_unrank")
+
+
+# ---------------------------------------------------------------------------
+# include/sisso_sis.h: screening, feature creation, residuals, top-m, the
+# dimension loop.  Tensors are torch device tensors; marshalling only.
+SISSO_OPS = {"add": 0, "sub": 1, "mul": 2, "div": 3, "abs_diff": 4, "exp": 16, "neg_exp": 17, "log": 18,
+             "abs": 19, "sqrt": 20, "cbrt": 21, "sq": 22, "cb": 23, "inv": 24, "sin": 25, "cos": 26,
+             "six_pow": 27}
+
+
+class sisso_sis_desc(ctypes.Structure):
+    _fields_ = [
+        ("R", ctypes.c_void_p),
+        ("task_offsets", ctypes.POINTER(ctypes.c_int64)),
+        ("n_total", ctypes.c_int64),
+        ("T", ctypes.c_int32),
+        ("nres", ctypes.c_int32),
+        ("workspace", ctypes.c_void_p),
+        ("workspace_bytes", ctypes.c_size_t),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class sisso_fit_desc(ctypes.Structure):
+    _fields_ = [
+        ("X", ctypes.c_void_p),
+        ("y", ctypes.c_void_p),
+        ("task_offsets", ctypes.POINTER(ctypes.c_int64)),
+        ("n_total", ctypes.c_int64),
+        ("M", ctypes.c_int64),
+        ("T", ctypes.c_int32),
+        ("D_max", ctypes.c_int32),
+        ("m_sis", ctypes.c_int32),
+        ("n_res", ctypes.c_int32),
+        ("k", ctypes.c_int32),
+        ("workspace", ctypes.c_void_p),
+        ("workspace_bytes", ctypes.c_size_t),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+_sis_sigs_done = False
+
+
+def _slib():
+    global _sis_sigs_done
+    lib = load()
+    if _sis_sigs_done:
+        return lib
+    P, V, I32, I64, SZ, D = ctypes.POINTER, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_double
+    sigs = {
+        "sisso_sis_workspace_bytes": ([P(sisso_sis_desc)], SZ),
+        "sisso_sis_create": ([P(sisso_sis_desc), P(V)], I32),
+        "sisso_sis_destroy": ([V], None),
+        "sisso_sis_last_error": ([V], ctypes.c_char_p),
+        "sisso_sis_score": ([V, V, I64, V], I32),
+        "sisso_sis_score_op": ([V, I32, V, I64, V, I64, D, D, V, V], I32),
+        "sisso_fc_eval": ([I32, V, I64, I64, V, I64, D, D, V, V, V], I32),
+        "sisso_topm_workspace_bytes": ([I64, I32], SZ),
+        "sisso_topm": ([V, I64, I32, V, V, P(I32), V, SZ, V], I32),
+        "sisso_residuals": ([V, V, I64, I64, V, I32, V, V, I32, I32, V, V], I32),
+        "sisso_fit_workspace_bytes": ([P(sisso_fit_desc)], SZ),
+        "sisso_fit": ([P(sisso_fit_desc), V, V, V, V], I32),
+        "sisso_fit_last_error": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sigs.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _sis_sigs_done = True
+    return lib
+
+
+def _stream_of(t) -> int:
+    import torch
+    return torch.cuda.current_stream(t.device).cuda_stream
+
+
+def _ws(nbytes: int, device):
+    """A 256-byte aligned workspace: (tensor kept alive, aligned address)."""
+    import torch
+    buf = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=device)
+    return buf, (buf.data_ptr() + 255) & ~255
+
+
+class SisScreen:
+    """A screening handle (sisso_sis_create) for residuals R (n, nres) as a
+    device float64 tensor stored residual-major: R[r] is residual r."""
+
+    def __init__(self, R, task_offsets=None):
+        R = R if R.dim() == 2 else R.reshape(1, -1)
+        self.R = R.contiguous()
+        nres, n = self.R.shape
+        self.offsets = np.ascontiguousarray([0, n] if task_offsets is None else task_offsets, dtype=np.int64)
+        self.n, self.T, self.nres = int(n), len(self.offsets) - 1, int(nres)
+        lib = _slib()
+        d = sisso_sis_desc(self.R.data_ptr(), self.offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                           self.n, self.T, self.nres, None, 0, _stream_of(self.R))
+        nbytes = lib.sisso_sis_workspace_bytes(ctypes.byref(d))
+        if nbytes == 0:
+            raise SissoError(SISSO_EINVAL, "screening shape out of range")
+        self._buf, d.workspace = _ws(nbytes, self.R.device)
+        d.workspace_bytes = nbytes
+        h = ctypes.c_void_p()
+        rc = lib.sisso_sis_create(ctypes.byref(d), ctypes.byref(h))
+        if rc != SISSO_OK:
+            raise SissoError(rc, lib.sisso_sis_last_error(None).decode())
+        self.handle = h.value
+
+    def _check(self, rc):
+        if rc != SISSO_OK:
+            raise SissoError(rc, _slib().sisso_sis_last_error(self.handle).decode())
+
+    def score(self, X, scores):
+        """X: (M, n) device float64 (feature-major); scores: (M,) float64."""
+        self._check(_slib().sisso_sis_score(self.handle, X.data_ptr(), X.shape[0], scores.data_ptr()))
+
+    def score_op(self, op: str, X, pairs, lower: float, upper: float, scores, valid=None):
+        self._check(_slib().sisso_sis_score_op(self.handle, SISSO_OPS[op], X.data_ptr(), X.shape[0],
+                                               pairs.data_ptr(), pairs.shape[0], lower, upper, scores.data_ptr(),
+                                               valid.data_ptr() if valid is not None else None))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _slib().sisso_sis_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sisso_fc_eval(op: str, X, pairs, lower: float, upper: float, out, valid) -> None:
+    rc = _slib().sisso_fc_eval(SISSO_OPS[op], X.data_ptr(), X.shape[1], X.shape[0], pairs.data_ptr(), pairs.shape[0],
+                               lower, upper, out.data_ptr() if out is not None else None, valid.data_ptr(),
+                               _stream_of(X))
+    _raw_check(rc, "sisso_fc_eval")
+
+
+def sisso_topm(scores, m: int, out_idx, out_score=None) -> int:
+    lib = _slib()
+    nbytes = lib.sisso_topm_workspace_bytes(scores.shape[0], m)
+    if nbytes == 0:
+        raise SissoError(SISSO_EINVAL, "top-m sizes out of range")
+    buf, addr = _ws(nbytes, scores.device)
+    cnt = ctypes.c_int32(0)
+    rc = lib.sisso_topm(scores.data_ptr(), scores.shape[0], m, out_idx.data_ptr(),
+                        out_score.data_ptr() if out_score is not None else None, ctypes.byref(cnt), addr, nbytes,
+                        _stream_of(scores))
+    _raw_check(rc, "sisso_topm")
+    del buf
+    return int(cnt.value)
+
+
+def sisso_residuals(F, y, task_offsets_dev, idx, coef, R) -> None:
+    """F (S, n), y (n,), task_offsets_dev (T+1,) int64 on the device, idx (r, D)
+    int32, coef (r, T, D+1) float64, R (r, n) float64 out."""
+    r, D = idx.shape
+    rc = _slib().sisso_residuals(F.data_ptr(), y.data_ptr(), F.shape[1], F.shape[0], task_offsets_dev.data_ptr(),
+                                 task_offsets_dev.shape[0] - 1, idx.data_ptr(), coef.data_ptr(), r, D, R.data_ptr(),
+                                 _stream_of(F))
+    _raw_check(rc, "sisso_residuals")
+
+
+def sisso_fit(X, y, task_offsets, D_max: int, m_sis: int, n_res: int, k: int) -> dict:
+    """The dimension loop (sisso_fit).  X (M, n) and y (n,) device float64."""
+    lib = _slib()
+    M, n = X.shape
+    offs = np.ascontiguousarray([0, n] if task_offsets is None else task_offsets, dtype=np.int64)
+    T = len(offs) - 1
+    d = sisso_fit_desc(X.data_ptr(), y.data_ptr(), offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), n, M, T,
+                       D_max, m_sis, n_res, k, None, 0, _stream_of(X))
+    nbytes = lib.sisso_fit_workspace_bytes(ctypes.byref(d))
+    if nbytes == 0:
+        raise SissoError(SISSO_EINVAL, "dimension-loop sizes out of range")
+    buf, d.workspace = _ws(nbytes, X.device)
+    d.workspace_bytes = nbytes
+    sub = np.zeros(D_max * m_sis, dtype=np.int32)
+    models = np.zeros((D_max, k, D_max), dtype=np.int32)
+    sse = np.zeros((D_max, k))
+    coef = np.zeros((D_max, k, T, D_max + 1))
+    rc = lib.sisso_fit(ctypes.byref(d), sub.ctypes.data, models.ctypes.data, sse.ctypes.data, coef.ctypes.data)
+    del buf
+    if rc != SISSO_OK:
+        raise SissoError(rc, lib.sisso_fit_last_error().decode())
+    return dict(subspace=sub, models=models, sse=sse, coef=coef)

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsisso_l0.so")
-SOURCES = ["gram.hip", "gram_lp.hip", "search.hip", "mlp.hip", "api.cpp"]
+SOURCES = ["gram.hip", "gram_lp.hip", "search.hip", "mlp.hip", "sis.hip", "api.cpp", "sis_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
          # no packed-FP32 instructions anywhere in the device code
