@@ -59,7 +59,13 @@ enum {
      * leaves in the correlation matrix is measured by
      * sisso_l0_precision_report. */
     SISSO_PREC_BF16_COMP = 1,
-    SISSO_PREC_FP16_COMP = 2   /* reserved: not built (SISSO_ENOTSUP) */
+    /* The same with two FP16 slices of 11 significant bits (22 bits of each
+     * centred value) and three slice products instead of six: half the MFMA
+     * work of the BF16 form.  FP16 products of these integers reach 2^20, so
+     * the FP32 chunk sums round (they are not exact as in the BF16 form);
+     * the FP64 accumulation of the chunk sums compensates across chunks.
+     * Gram error ~4x that of the BF16 form, reported the same way. */
+    SISSO_PREC_FP16_COMP = 2
 };
 
 #define SISSO_MAX_D 4      /* largest descriptor dimension compiled in */

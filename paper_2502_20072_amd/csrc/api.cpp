@@ -30,6 +30,7 @@ struct sisso_l0 {
     bool ran[SISSO_NPHASE] = {};
     bool prof = false;
     char *stage = nullptr;  // pinned host copy of the result block (one transfer per readout)
+    const void *btab_owner = nullptr;  // the batch whose search table this handle's workspace holds
     ~sisso_l0() {
         for (auto &e : ev)
             if (e) (void)hipEventDestroy(e);
@@ -50,6 +51,7 @@ static int precision_slices(int32_t precision) {
     switch (precision) {
         case SISSO_PREC_FP64: return 0;
         case SISSO_PREC_BF16_COMP: return 3;
+        case SISSO_PREC_FP16_COMP: return 2;
         default: return -1;
     }
 }
@@ -62,16 +64,40 @@ static Layout compute_layout(int64_t n_total, int64_t S, int T, int D_max, int k
     L.TP = next_pow2(T);
     const int64_t ntile = (S + GRAM_TILE - 1) / GRAM_TILE;
     const int64_t blocks = ntile * (ntile + 1) / 2 * T;
-    // split the rows so the Gram launch has >= ~512 workgroups, keeping at
-    // least 256 rows per split
-    const int64_t maxrows = n_total;
-    int64_t ns = (512 + blocks - 1) / blocks;
-    const int64_t byrows = maxrows / 256 > 1 ? maxrows / 256 : 1;
-    if (ns > byrows) ns = byrows;
-    if (ns > 16) ns = 16;
-    if (ns < 1) ns = 1;
+    // Split the rows of every tile pair into ns parts (>= 256 rows each, at
+    // most 8) so that the Gram's workgroups, about equal in cost and one per
+    // CU at a time, fill whole rounds of the 256 CUs: the launch takes
+    // ceil(blocks ns / 256) rounds of 1/ns of a tile pair's work; a split is
+    // taken while it cuts that time by more than 2 % (the finish kernel reads
+    // every split's partial matrices).
+    // With several tasks the workgroups' costs follow the tasks' row counts
+    // (and are launched largest first), so only a small launch is split, to
+    // about 512 workgroups.
+    const int64_t byrows = n_total / 256 > 1 ? n_total / 256 : 1;
+    int64_t ns = 1;
+    if (T == 1) {
+        const int64_t nsmax = byrows < 8 ? byrows : 8;
+        double best = (double)((blocks + 255) / 256);
+        for (int64_t q = 2; q <= nsmax; ++q) {
+            const double f = (double)((blocks * q + 255) / 256) / (double)q;
+            if (f < 0.98 * best) {
+                best = f;
+                ns = q;
+            }
+        }
+    } else {
+        ns = (512 + blocks - 1) / blocks;
+        if (ns > byrows) ns = byrows;
+        if (ns > 16) ns = 16;
+        if (ns < 1) ns = 1;
+    }
     L.nsplit = (int)ns;
-    L.KP = next_pow2(k_max + 16);
+    // candidates re-scored exactly: k + 16 leaves a margin for FP64
+    // normal-equation rounding at the k-th position; the precision form ranks
+    // by SSEs from an approximate Gram (relative error ~1e-6..1e-5), so it
+    // keeps twice as many candidates for the exact re-score
+    L.KP = next_pow2(L.lp_ns > 0 ? 2 * (k_max + 16) : k_max + 16);
+    if (L.KP > KP_MAX) L.KP = KP_MAX;
     if (L.KP < 64) L.KP = 64;
     L.search_wgs = SEARCH_WGS_DEFAULT;
     L.nwaves = SEARCH_WGS_MAX * SEARCH_WAVES;
@@ -83,6 +109,8 @@ static Layout compute_layout(int64_t n_total, int64_t S, int T, int D_max, int k
         return at;
     };
     const size_t d = sizeof(double);
+    L.self = take(sizeof(Ctx));
+    L.btab = take(S3B_TABLE_BYTES);
     L.off_dev = take((T + 1) * sizeof(int64_t));
     L.torder = take(T * sizeof(int32_t));
     L.ybar = take(T * d);
@@ -109,6 +137,15 @@ static Layout compute_layout(int64_t n_total, int64_t S, int T, int D_max, int k
         L.rec3_bytes = (D_max >= 3 && S >= 3) ? (size_t)rows3 * 16 * d : 0;
     }
     L.rec3 = take(L.rec3_bytes);
+    // D = 4, one task: a record row per (pair group, j); kept only while the
+    // table stays within S4_TABLE_MAX (else the general kernel runs)
+    {
+        const int64_t rows4 = S >= 4 ? s4_rows_below(S, S - 2) : 0;
+        const size_t b4 = (size_t)rows4 * S4_ROW * d;
+        L.rec4_bytes = (D_max >= 4 && T == 1 && S >= 4 && b4 <= S4_TABLE_MAX && s4_tiles_host(S) < (1ull << 31)) ? b4 : 0;
+    }
+    L.rec4 = take(L.rec4_bytes);
+    L.r4off = take(L.rec4_bytes ? (size_t)(S + 1) * sizeof(int64_t) : 0);
     L.G1_bytes = (D_max >= 3 && S >= 3 && T > 1) ? Sp * Sp * d : 0;
     L.G1 = take(L.G1_bytes);
     // several tasks, D = 3: a pool with a record for every step of the sweep
@@ -203,6 +240,8 @@ static void carve(sisso_l0 *h) {
     c.tstar = (int32_t *)p;
     c.rec3 = L.rec3_bytes ? (double *)(base + L.rec3) : nullptr;
     c.G1 = L.G1_bytes ? (double *)(base + L.G1) : c.G;
+    c.rec4 = L.rec4_bytes ? (double *)(base + L.rec4) : nullptr;
+    c.r4off = L.rec4_bytes ? (int64_t *)(base + L.r4off) : nullptr;
     c.mtq_chunks = L.mtq_chunks;
     c.mtq = L.mtq_chunks ? (uint64_t *)(base + L.mtq) : nullptr;
     c.mtq_n = L.mtq_chunks ? (uint32_t *)(base + L.mtq_n) : nullptr;
@@ -270,7 +309,9 @@ extern "C" int32_t sisso_l0_create(const sisso_l0_desc *d, sisso_l0 **out) {
     for (int t = 0; t < d->T; ++t) order[t] = t;
     std::stable_sort(order.begin(), order.end(),
                      [&](int32_t a, int32_t b) { return o[a + 1] - o[a] > o[b + 1] - o[b]; });
-    if (hipMemcpyAsync(h->ctx.off_dev, h->offsets.data(), (d->T + 1) * sizeof(int64_t), hipMemcpyHostToDevice,
+    if (hipMemcpyAsync((char *)d->workspace + h->lay.self, &h->ctx, sizeof(Ctx), hipMemcpyHostToDevice,
+                       h->stream) != hipSuccess ||
+        hipMemcpyAsync(h->ctx.off_dev, h->offsets.data(), (d->T + 1) * sizeof(int64_t), hipMemcpyHostToDevice,
                        h->stream) != hipSuccess ||
         hipMemcpyAsync(h->ctx.torder, order.data(), d->T * sizeof(int32_t), hipMemcpyHostToDevice,
                        h->stream) != hipSuccess ||
@@ -671,6 +712,8 @@ extern "C" int32_t sisso_l0_unrank(int64_t S, int32_t D, uint64_t r, int32_t *t)
 // sisso_l0_topk on its handle, exactly as after an unbatched search.
 struct sisso_l0_batch {
     std::vector<sisso_l0 *> hs;
+    std::vector<sisso_l0 *> leads;             // handles whose workspace holds a shared-search table
+    std::vector<BatchSearchArgs> tables;       // the shared search launches
     std::vector<SearchCall> calls;
     std::vector<uint64_t> scored;
     int D = 0, k = 0;
@@ -681,6 +724,8 @@ struct sisso_l0_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     ~sisso_l0_batch() {
+        for (auto h : leads)
+            if (h->btab_owner == this) h->btab_owner = nullptr;
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         for (auto e : evs) (void)hipEventDestroy(e);
@@ -730,28 +775,90 @@ extern "C" int32_t sisso_l0_batch_create(sisso_l0 *const *hs, int32_t P, int32_t
     for (auto &st : b->br)
         if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess)
             return batch_fail(b, SISSO_EDEVICE, "stream creation failed");
-    b->evs.resize(NB + 1, nullptr);
+    b->evs.resize(3 * (NB + 1), nullptr);
     for (auto &e : b->evs)
         if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
             return batch_fail(b, SISSO_EDEVICE, "event creation failed");
     if (hipEventCreateWithFlags(&b->in, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&b->out, hipEventDisableTiming) != hipSuccess)
         return batch_fail(b, SISSO_EDEVICE, "event creation failed");
-    // capture: fork from the capture stream to every branch, one chain per
-    // problem (problems sharing a branch run one after another), join back
+    // one-task D = 3 problems share one search launch (a device queue of tile
+    // runs, largest problems first); the others keep their own search
+    std::vector<int> shared;
+    for (int p = 0; p < P; ++p)
+        if (s3_batchable(b->hs[p]->ctx, D)) shared.push_back(p);
+    std::stable_sort(shared.begin(), shared.end(), [&](int x, int y) {
+        return s3_tiles_host(b->hs[x]->desc.S) > s3_tiles_host(b->hs[y]->desc.S);
+    });
+    std::vector<char> in_shared(P, 0);
+    for (int p : shared) in_shared[p] = 1;
+    // the shared launches' tables (item prefix, context pointers) live in the
+    // workspace of each launch's first problem, which a batch holds until it is
+    // destroyed
+    for (size_t g0 = 0; g0 < shared.size(); g0 += S3B_MAXP) {
+        BatchSearchArgs a{};
+        a.P = (int)std::min(shared.size() - g0, (size_t)S3B_MAXP);
+        sisso_l0 *lead = b->hs[shared[g0]];
+        if (lead->btab_owner) return batch_fail(b, SISSO_EINVAL, "a handle already leads another live batch");
+        std::vector<uint32_t> ends(a.P);
+        std::vector<const Ctx *> ptrs(a.P);
+        uint32_t acc = 0;
+        for (int q = 0; q < a.P; ++q) {
+            sisso_l0 *h = b->hs[shared[g0 + q]];
+            acc += (uint32_t)((s3_tiles_host(h->desc.S) + S3B_RUN - 1) / S3B_RUN);
+            ends[q] = acc;
+            ptrs[q] = (const Ctx *)((const char *)h->desc.workspace + h->lay.self);
+            a.KPmax = std::max(a.KPmax, h->ctx.KP);
+        }
+        char *tab = (char *)lead->desc.workspace + lead->lay.btab;
+        a.item_end = (const uint32_t *)tab;
+        a.ctx = (const Ctx *const *)(tab + S3B_MAXP * sizeof(uint32_t));
+        if (hipMemcpyAsync(tab, ends.data(), a.P * sizeof(uint32_t), hipMemcpyHostToDevice, b->user) != hipSuccess ||
+            hipMemcpyAsync(tab + S3B_MAXP * sizeof(uint32_t), ptrs.data(), a.P * sizeof(void *), hipMemcpyHostToDevice,
+                           b->user) != hipSuccess ||
+            hipStreamSynchronize(b->user) != hipSuccess)
+            return batch_fail(b, SISSO_EDEVICE, "could not write the batch search table");
+        lead->btab_owner = b;
+        b->leads.push_back(lead);
+        b->tables.push_back(a);
+    }
+    // capture: fork to every branch (problems sharing a branch run one after
+    // another); phase 1 = statistics, Gram and the searches' set-up (the whole
+    // search for the others); join; the shared search launches; fork; phase 2 =
+    // merge, re-score and final ordering of the shared problems; join
     if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return batch_fail(b, SISSO_EDEVICE, "hipStreamBeginCapture failed");
-    bool ok = hipEventRecord(b->evs[NB], b->cap) == hipSuccess;
-    for (int i = 0; i < NB && ok; ++i) ok = hipStreamWaitEvent(b->br[i], b->evs[NB], 0) == hipSuccess;
+    auto fork = [&](int stage) {
+        bool ok = hipEventRecord(b->evs[stage * (NB + 1) + NB], b->cap) == hipSuccess;
+        for (int i = 0; i < NB && ok; ++i) ok = hipStreamWaitEvent(b->br[i], b->evs[stage * (NB + 1) + NB], 0) == hipSuccess;
+        return ok;
+    };
+    auto join = [&](int stage) {
+        bool ok = true;
+        for (int i = 0; i < NB && ok; ++i)
+            ok = hipEventRecord(b->evs[stage * (NB + 1) + i], b->br[i]) == hipSuccess &&
+                 hipStreamWaitEvent(b->cap, b->evs[stage * (NB + 1) + i], 0) == hipSuccess;
+        return ok;
+    };
+    bool ok = fork(0);
     for (int p = 0; p < P && ok; ++p) {
         sisso_l0 *h = b->hs[p];
         Ctx c = h->ctx;
         c.ev = nullptr;  // no timing events inside a graph
         hipStream_t st = b->br[p % NB];
-        ok = launch_stats(c, st) == 0 && launch_gram(c, st) == 0 && launch_search(c, b->calls[p], st) == 0;
+        ok = launch_stats(c, st) == 0 && launch_gram(c, st) == 0 &&
+             (in_shared[p] ? launch_batch_prologue(c, b->calls[p], st) == 0 : launch_search(c, b->calls[p], st) == 0);
     }
-    for (int i = 0; i < NB && ok; ++i)
-        ok = hipEventRecord(b->evs[i], b->br[i]) == hipSuccess && hipStreamWaitEvent(b->cap, b->evs[i], 0) == hipSuccess;
+    ok = ok && join(0);
+    for (size_t q = 0; q < b->tables.size() && ok; ++q) ok = launch_batch_search3(b->tables[q], 0, b->cap) == 0;
+    ok = ok && fork(1);
+    for (size_t q = 0; q < shared.size() && ok; ++q) {
+        const int p = shared[q];
+        Ctx c = b->hs[p]->ctx;
+        c.ev = nullptr;
+        ok = launch_batch_epilogue(c, b->calls[p], b->br[q % NB]) == 0;
+    }
+    ok = ok && join(1);
     const hipError_t ec = hipStreamEndCapture(b->cap, &b->graph);
     if (!ok || ec != hipSuccess || !b->graph) return batch_fail(b, SISSO_EDEVICE, "graph capture failed");
     if (hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess)

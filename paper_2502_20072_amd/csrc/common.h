@@ -12,7 +12,10 @@ namespace sl0 {
 constexpr int WAVE = 64;               // CDNA wavefront width
 constexpr double RANK_EPS = 1e-10;     // pivot ratio at or below which a tuple is rank-deficient
 constexpr int GRAM_TILE = 128;         // Gram output tile (rows = cols)
-constexpr int GRAM_KC = 16;            // samples per LDS stage of the Gram
+#ifndef GRAM_KC_SAMPLES
+#define GRAM_KC_SAMPLES 16
+#endif
+constexpr int GRAM_KC = GRAM_KC_SAMPLES;  // samples per LDS stage of the Gram (divides 256)
 constexpr int SEARCH_WG = 256;         // threads per search workgroup (4 waves)
 constexpr int SEARCH_WAVES = SEARCH_WG / WAVE;
 constexpr int SEARCH_WGS_MAX = 2048;   // largest persistent search grid (lists are sized for it)
@@ -192,6 +195,30 @@ __host__ __device__ inline void colex_unrank_small(uint64_t r, int q, int64_t N,
     colex_unrank(BinomCalc{}, r, q, N, t);
 }
 
+// ----------------------------------------- D = 4, one task: record table
+// Pairs (i1, i2) of a D = 4 prefix are grouped four at a time: group
+// (i2, h) holds i1 = 4h .. 4h + 3 (those >= i2 are void), so a group exists
+// for h < ceil(i2 / 4).  Groups are ordered by i2, then h.
+constexpr int S4_NR = 4;        // pairs per group
+constexpr int S4_RECW = 5;      // doubles per pair record: v0, v1, 1/d_j, z_j / s_j, p
+constexpr int S4_ROW = S4_NR * S4_RECW;  // doubles per record row (160 bytes)
+constexpr int S4_KC = 128;      // k per tile: two adjacent per lane
+constexpr int S4_JR = 32;       // j rows per tile (divides 64)
+constexpr size_t S4_TABLE_MAX = (size_t)4 << 30;  // largest record table kept in the workspace
+
+// groups with i2 < i: sum over i' < i of ceil(i' / 4)
+__host__ __device__ inline int64_t s4_groups_below(int64_t i) {
+    if (i <= 1) return 0;
+    const int64_t N = i - 1, a = N / 4, b = N % 4;
+    return (i - 1) + 2 * a * (a - 1) + b * a;
+}
+// record rows of the groups with i2 < i: sum over i' < i of ceil(i'/4) (S - 2 - i')
+__host__ __device__ inline int64_t s4_rows_below(int64_t S, int64_t i) {
+    int64_t acc = 0;
+    for (int64_t x = 1; x < i && x <= S - 3; ++x) acc += ((x + 3) / 4) * (S - 2 - x);
+    return acc;
+}
+
 // -------------------------------------------------------- workspace layout
 // Every region is 256-byte aligned; offsets in bytes from the workspace base.
 struct Layout {
@@ -214,6 +241,11 @@ struct Layout {
     size_t rec3_bytes;
     size_t G1;         // D = 3, several tasks: the filter task's matrix alone, double [S][S] tiled (0 bytes otherwise)
     size_t G1_bytes;
+    size_t rec4;       // D = 4, one task: pair-group records, double [rows][S4_ROW] (0 bytes otherwise)
+    size_t rec4_bytes;
+    size_t self;       // a device copy of the handle's Ctx (read by the batched search)
+    size_t btab;       // batched search: item prefix and context table, when this handle leads a batch
+    size_t r4off;      //   int64 [S + 1] record rows of the groups below each i2
     size_t mtq;        // D = 3, several tasks: flagged sweep steps, uint64 [mtq_chunks][MTQ_CHUNK][3]
     size_t mtq_n;      //   uint32 [mtq_chunks] keys per chunk
     size_t mtq_pre;    //   uint64 [mtq_chunks + 1] exclusive prefix of the counts
@@ -246,6 +278,13 @@ inline int next_pow2(int x) {
 }
 
 // device status flag indices
-enum { FLAG_NONFINITE = 0, FLAG_CAPACITY = 1, FLAG_CAND = 2, FLAG_THETA = 4 /* uint64 at 4..5 */ };
+enum {
+    FLAG_NONFINITE = 0,
+    FLAG_CAPACITY = 1,
+    FLAG_CAND = 2,
+    FLAG_THETA = 4,   /* uint64 at 4..5 */
+    FLAG_BATCHQ = 8,  /* batched search: next queue item (read on the batch's first problem) */
+    FLAG_NLISTS = 9   /* batched search: lists this problem's waves have written */
+};
 
 }  // namespace sl0

@@ -191,14 +191,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[a][c] = (double4_t){0.0, 0.0, 0.0, 0.0};
 
-    // loader mapping: kk = tid % KC (consecutive samples), feature = tid / KC + 16 r
+    // loader mapping: kk = tid % KC (consecutive samples), feature = tid / KC + FPP r
+    constexpr int FPP = 256 / GRAM_KC;          // features per loader pass
+    constexpr int NP = GRAM_TILE / FPP;         // loader passes per operand
     const int kk = tid % GRAM_KC;
     const int f0 = tid / GRAM_KC;
-    double muA[GRAM_TILE / 16], muB[GRAM_TILE / 16];
+    double muA[NP], muB[NP];
 #pragma unroll
-    for (int r = 0; r < GRAM_TILE / 16; ++r) {
-        const int64_t ga = (int64_t)bi * GRAM_TILE + f0 + 16 * r;
-        const int64_t gb = (int64_t)bj * GRAM_TILE + f0 + 16 * r;
+    for (int r = 0; r < NP; ++r) {
+        const int64_t ga = (int64_t)bi * GRAM_TILE + f0 + FPP * r;
+        const int64_t gb = (int64_t)bj * GRAM_TILE + f0 + FPP * r;
         muA[r] = ga < S ? mut[ga] : 0.0;
         muB[r] = gb < S ? mut[gb] : 0.0;
     }
@@ -207,30 +209,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     // flight while the MFMAs of chunk c run out of LDS.  Loads are
     // unconditional (row and feature clamped into range); masking and centring
     // happen at the LDS store, so no load is waited on before the MFMAs.
-    int64_t fa[GRAM_TILE / 16], fb[GRAM_TILE / 16];
-    bool ina[GRAM_TILE / 16], inb[GRAM_TILE / 16];
+    int64_t fa[NP], fb[NP];
+    bool ina[NP], inb[NP];
 #pragma unroll
-    for (int r = 0; r < GRAM_TILE / 16; ++r) {
-        const int64_t ga = (int64_t)bi * GRAM_TILE + f0 + 16 * r;
-        const int64_t gb = (int64_t)bj * GRAM_TILE + f0 + 16 * r;
+    for (int r = 0; r < NP; ++r) {
+        const int64_t ga = (int64_t)bi * GRAM_TILE + f0 + FPP * r;
+        const int64_t gb = (int64_t)bj * GRAM_TILE + f0 + FPP * r;
         ina[r] = ga < S;
         inb[r] = gb < S;
         fa[r] = (ina[r] ? ga : S - 1) * n_total;
         fb[r] = (inb[r] ? gb : S - 1) * n_total;
     }
-    double sa[GRAM_TILE / 16], sb[GRAM_TILE / 16];
+    double sa[NP], sb[NP];
     int64_t row = r0 + c0 * GRAM_KC + kk;
     if (c0 < c1) {
         const int64_t rowc = row < r1 ? row : r1 - 1;
 #pragma unroll
-        for (int r = 0; r < GRAM_TILE / 16; ++r) {
+        for (int r = 0; r < NP; ++r) {
             sa[r] = F[fa[r] + rowc];
             sb[r] = F[fb[r] + rowc];
         }
 #pragma unroll
-        for (int r = 0; r < GRAM_TILE / 16; ++r) {
-            As[f0 + 16 * r][kk] = (row < r1 && ina[r]) ? sa[r] - muA[r] : 0.0;
-            Bs[f0 + 16 * r][kk] = (row < r1 && inb[r]) ? sb[r] - muB[r] : 0.0;
+        for (int r = 0; r < NP; ++r) {
+            As[f0 + FPP * r][kk] = (row < r1 && ina[r]) ? sa[r] - muA[r] : 0.0;
+            Bs[f0 + FPP * r][kk] = (row < r1 && inb[r]) ? sb[r] - muB[r] : 0.0;
         }
     }
     __syncthreads();
@@ -240,7 +242,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         if (more) {
             const int64_t rowc = row < r1 ? row : r1 - 1;
 #pragma unroll
-            for (int r = 0; r < GRAM_TILE / 16; ++r) {
+            for (int r = 0; r < NP; ++r) {
                 sa[r] = F[fa[r] + rowc];
                 sb[r] = F[fb[r] + rowc];
             }
@@ -262,9 +264,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         __syncthreads();
         if (more) {
 #pragma unroll
-            for (int r = 0; r < GRAM_TILE / 16; ++r) {
-                As[f0 + 16 * r][kk] = (row < r1 && ina[r]) ? sa[r] - muA[r] : 0.0;
-                Bs[f0 + 16 * r][kk] = (row < r1 && inb[r]) ? sb[r] - muB[r] : 0.0;
+            for (int r = 0; r < NP; ++r) {
+                As[f0 + FPP * r][kk] = (row < r1 && ina[r]) ? sa[r] - muA[r] : 0.0;
+                Bs[f0 + FPP * r][kk] = (row < r1 && inb[r]) ? sb[r] - muB[r] : 0.0;
             }
         }
         __syncthreads();

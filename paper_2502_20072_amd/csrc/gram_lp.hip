@@ -1,26 +1,37 @@
-// Precision form of the Gram step: BF16 slices on MFMA with exact FP32 chunk
-// sums and FP64 accumulation.
+// Precision forms of the Gram step: BF16 or FP16 slices on MFMA with FP32
+// chunk sums and FP64 accumulation.
 //
 // Each centred column x of a task is cut, per chunk of LP_XC consecutive
-// samples, into NS slices of small integers that BF16 holds exactly:
-//     x = 2^(e - 7) (a_0 + a_1 2^-8 + a_2 2^-16 + ...),   |a_s| <= 128,
-// with 2^e > max |x| over the chunk (a_0 = rint(x 2^(7-e)), each further
-// slice the rounded, 2^8-scaled remainder).  The cross products
-//     sum_k x_i[k] x_j[k] = 2^(e_i + e_j - 14) sum_m 2^(-8m) P_m,
+// samples, into NS slices of small integers that the element type holds
+// exactly (SB significant bits: 8 for BF16, 11 for FP16):
+//     x = 2^(e - (SB-1)) (a_0 + a_1 2^-SB + a_2 2^-2SB + ...),  |a_s| <= 2^(SB-1),
+// with 2^e > max |x| over the chunk (a_0 = rint(x 2^(SB-1-e)), each further
+// slice the rounded, 2^SB-scaled remainder).  The cross products
+//     sum_k x_i[k] x_j[k] = 2^(e_i + e_j - 2(SB-1)) sum_m 2^(-SB m) P_m,
 //     P_m = sum_k sum_{s+u=m} a_s(i,k) a_u(j,k),
-// keep the slice pairs with s + u < NS.  Every term of P_m is an integer of
-// magnitude <= 2^14 and a chunk holds at most 256 samples and at most 4 pairs
-// per m, so P_m (< 2^24) is exact in the FP32 accumulators of the MFMA; only
-// the chunk totals are scaled and summed in FP64.  The result differs from
-// the FP64 Gram only by the dropped slice pairs and the truncation of x to NS
-// slices (relative size ~2^-(8 NS - 1) per element).  F^T y and |y|^2 stay
-// exact FP64 (statistics kernel); the search and the re-score are unchanged.
+// keep the slice pairs with s + u < NS, accumulated in the FP32 accumulators
+// of the MFMA over a chunk; only the chunk totals are scaled and summed in
+// FP64 (the compensating FP64 sum).
+//  * BF16, NS = 3 (six products per K-step): every term of P_m is an integer
+//    of magnitude <= 2^14, a chunk holds at most 256 samples and at most 3
+//    pairs per m, so P_m (< 2^24) is exact in FP32.  The result differs from
+//    the FP64 Gram only by the dropped slice pairs and the truncation of x to
+//    three slices (~2^-20 M_i M_j per sample, M the chunk maxima).
+//  * FP16, NS = 2 (three products per K-step, half the BF16 work): 22 bits of
+//    each value; terms up to 2^20, so the FP32 chunk sums round (a few ulps
+//    of sums below 2^29 per chunk), and the truncation and the dropped
+//    product leave ~2^-18 M_i M_j per sample.
+// F^T y and |y|^2 stay exact FP64 (statistics kernel); the search and the
+// re-score are unchanged.
+#include <type_traits>
+
 #include "common.h"
 #include "kernels.h"
 
 namespace sl0 {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double double4_t __attribute__((ext_vector_type(4)));
 
@@ -34,6 +45,7 @@ constexpr int LP_WN = 2;         // 16-column blocks per wave (64 x 32 per wave)
 // One wavefront per (feature j, chunk g).  Chunks tile every task's rows in
 // LP_XC-sample pieces (a task's last chunk is zero-padded).  Writes the
 // chunk exponent and the NS slices of the centred samples.
+template <typename E, int SB>
 __global__ __launch_bounds__(256) void slice_kernel(Ctx c, int NS) {
     const int lane = threadIdx.x & 63;
     const int64_t job = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -61,11 +73,12 @@ __global__ __launch_bounds__(256) void slice_kernel(Ctx c, int NS) {
     const int64_t np = (int64_t)c.lp_nchunk * LP_XC;
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-        double r = ldexp(x[q], 7 - e);
+        double r = ldexp(x[q], SB - 1 - e);
+        E *sl = reinterpret_cast<E *>(c.lp_slices);
         for (int s = 0; s < NS; ++s) {
             const double a = rint(r);
-            c.lp_slices[((int64_t)s * c.S + j) * np + (int64_t)g * LP_XC + lane + 64 * q] = (__bf16)(float)a;
-            r = (r - a) * 256.0;
+            sl[((int64_t)s * c.S + j) * np + (int64_t)g * LP_XC + lane + 64 * q] = (E)(float)a;
+            r = (r - a) * (double)(1 << SB);
         }
     }
 }
@@ -82,10 +95,11 @@ __global__ __launch_bounds__(256) void slice_kernel(Ctx c, int NS) {
 // v_mfma_f32_16x16x32_bf16 operands: A[i][k] in lane i + 16 (k / 8), element
 // k % 8; B[k][j] in lane j + 16 (k / 8), element k % 8; result D[i][j] in lane
 // j + 16 (i / 4), register i % 4.
-template <int NS>
+template <typename E, int NS, int SB>
 __global__ __launch_bounds__(LP_WG) void gram_lp_kernel(Ctx c, int ntile, int nsplit) {
-    __shared__ __attribute__((aligned(16))) __bf16 As[NS][LP_TILE][LP_ROW];
-    __shared__ __attribute__((aligned(16))) __bf16 Bs[NS][LP_TILE][LP_ROW];
+    typedef E ex8 __attribute__((ext_vector_type(8)));
+    __shared__ __attribute__((aligned(16))) E As[NS][LP_TILE][LP_ROW];
+    __shared__ __attribute__((aligned(16))) E Bs[NS][LP_TILE][LP_ROW];
     __shared__ int es[2 * LP_TILE];
 
     int64_t b = blockIdx.x;
@@ -119,25 +133,26 @@ __global__ __launch_bounds__(LP_WG) void gram_lp_kernel(Ctx c, int ntile, int ns
     // before the MFMAs; a diagonal tile loads its panel twice (the second
     // read hits the cache).
     constexpr int PPT = LP_TILE * 4 / LP_WG;
-    const __bf16 *pa[PPT], *pb[PPT];  // slice 0 of each piece; slice s is s * sstride further
+    const E *pa[PPT], *pb[PPT];  // slice 0 of each piece; slice s is s * sstride further
+    const E *slices = reinterpret_cast<const E *>(c.lp_slices);
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
         const int p = tid + LP_WG * q;
         int64_t fa = (int64_t)bi * LP_TILE + (p >> 2), fb = (int64_t)bj * LP_TILE + (p >> 2);
         fa = fa < c.S ? fa : c.S - 1;
         fb = fb < c.S ? fb : c.S - 1;
-        pa[q] = c.lp_slices + fa * np + 8 * (p & 3);
-        pb[q] = c.lp_slices + fb * np + 8 * (p & 3);
+        pa[q] = slices + fa * np + 8 * (p & 3);
+        pb[q] = slices + fb * np + 8 * (p & 3);
     }
     const int64_t sstride = c.S * np;
-    bf16x8 ra[NS][PPT], rb[NS][PPT];
+    ex8 ra[NS][PPT], rb[NS][PPT];
     auto load_step = [&](int64_t k0) {  // k0: first sample of the K-step (multiple of 32)
 #pragma unroll
         for (int s = 0; s < NS; ++s)
 #pragma unroll
             for (int q = 0; q < PPT; ++q) {
-                ra[s][q] = *reinterpret_cast<const bf16x8 *>(pa[q] + s * sstride + k0);
-                rb[s][q] = *reinterpret_cast<const bf16x8 *>(pb[q] + s * sstride + k0);
+                ra[s][q] = *reinterpret_cast<const ex8 *>(pa[q] + s * sstride + k0);
+                rb[s][q] = *reinterpret_cast<const ex8 *>(pb[q] + s * sstride + k0);
             }
     };
     auto store_step = [&]() {
@@ -146,12 +161,12 @@ __global__ __launch_bounds__(LP_WG) void gram_lp_kernel(Ctx c, int ntile, int ns
 #pragma unroll
             for (int q = 0; q < PPT; ++q) {
                 const int p = tid + LP_WG * q;
-                *reinterpret_cast<bf16x8 *>(&As[s][p >> 2][8 * (p & 3)]) = ra[s][q];
-                *reinterpret_cast<bf16x8 *>(&Bs[s][p >> 2][8 * (p & 3)]) = rb[s][q];
+                *reinterpret_cast<ex8 *>(&As[s][p >> 2][8 * (p & 3)]) = ra[s][q];
+                *reinterpret_cast<ex8 *>(&Bs[s][p >> 2][8 * (p & 3)]) = rb[s][q];
             }
     };
     (void)diag;
-    __bf16 (*Bsrc)[LP_TILE][LP_ROW] = Bs;
+    E (*Bsrc)[LP_TILE][LP_ROW] = Bs;
 
     double4_t acc[4][LP_WN];
 #pragma unroll
@@ -189,28 +204,33 @@ __global__ __launch_bounds__(LP_WG) void gram_lp_kernel(Ctx c, int ntile, int ns
             const int kr = 8 * (lane >> 4);
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
-                bf16x8 av[4];
+                ex8 av[4];
 #pragma unroll
                 for (int m = 0; m < 4; ++m)
-                    av[m] = *reinterpret_cast<const bf16x8 *>(&As[s][wr + 16 * m + (lane & 15)][kr]);
+                    av[m] = *reinterpret_cast<const ex8 *>(&As[s][wr + 16 * m + (lane & 15)][kr]);
 #pragma unroll
                 for (int u = 0; u + s < NS; ++u) {
-                    bf16x8 bv[LP_WN];
+                    ex8 bv[LP_WN];
 #pragma unroll
                     for (int n = 0; n < LP_WN; ++n)
-                        bv[n] = *reinterpret_cast<const bf16x8 *>(&Bsrc[u][wc + 16 * n + (lane & 15)][kr]);
+                        bv[n] = *reinterpret_cast<const ex8 *>(&Bsrc[u][wc + 16 * n + (lane & 15)][kr]);
 #pragma unroll
                     for (int m = 0; m < 4; ++m)
 #pragma unroll
-                        for (int n = 0; n < LP_WN; ++n)
-                            p32[s + u][m][n] =
-                                __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[m], bv[n], p32[s + u][m][n], 0, 0, 0);
+                        for (int n = 0; n < LP_WN; ++n) {
+                            if constexpr (std::is_same<E, _Float16>::value)
+                                p32[s + u][m][n] =
+                                    __builtin_amdgcn_mfma_f32_16x16x32_f16(av[m], bv[n], p32[s + u][m][n], 0, 0, 0);
+                            else
+                                p32[s + u][m][n] =
+                                    __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[m], bv[n], p32[s + u][m][n], 0, 0, 0);
+                        }
                 }
             }
             __syncthreads();
             if (more) store_step();
         }
-        // promote the exact chunk sums: acc += 2^(e_i + e_j - 14) sum_m 2^(-8m) P_m
+        // promote the chunk sums: acc += 2^(e_i + e_j - 2(SB-1)) sum_m 2^(-SB m) P_m
 #pragma unroll
         for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -221,8 +241,8 @@ __global__ __launch_bounds__(LP_WG) void gram_lp_kernel(Ctx c, int ntile, int ns
                     const int ei = es[wr + 16 * m + 4 * (lane >> 4) + r];
                     double v = (double)p32[NS - 1][m][n][r];
 #pragma unroll
-                    for (int mm = NS - 2; mm >= 0; --mm) v = fma(v, 0x1p-8, (double)p32[mm][m][n][r]);
-                    acc[m][n][r] += ldexp(v, ei + ej - 14);
+                    for (int mm = NS - 2; mm >= 0; --mm) v = fma(v, 1.0 / (double)(1 << SB), (double)p32[mm][m][n][r]);
+                    acc[m][n][r] += ldexp(v, ei + ej - 2 * (SB - 1));
                 }
             }
     }
@@ -270,11 +290,21 @@ __global__ __launch_bounds__(256) void gram_check_kernel(Ctx c, int nsample, uns
 
 int launch_gram_lp(const Ctx &c, int NS, hipStream_t st) {
     const int64_t jobs = c.S * c.lp_nchunk;
-    hipLaunchKernelGGL(slice_kernel, dim3((unsigned)((jobs + 3) / 4)), dim3(256), 0, st, c, NS);
     const int ntile = (int)((c.S + LP_TILE - 1) / LP_TILE);
     const int64_t blocks = (int64_t)c.nsplit * c.T * ntile * (ntile + 1) / 2;
+    const dim3 sgrid((unsigned)((jobs + 3) / 4));
+    // the slice count names the form: three BF16 slices or two FP16 slices
     switch (NS) {
-        case 3: hipLaunchKernelGGL((gram_lp_kernel<3>), dim3((unsigned)blocks), dim3(LP_WG), 0, st, c, ntile, c.nsplit); break;
+        case 3:
+            hipLaunchKernelGGL((slice_kernel<__bf16, 8>), sgrid, dim3(256), 0, st, c, NS);
+            hipLaunchKernelGGL((gram_lp_kernel<__bf16, 3, 8>), dim3((unsigned)blocks), dim3(LP_WG), 0, st, c, ntile,
+                               c.nsplit);
+            break;
+        case 2:
+            hipLaunchKernelGGL((slice_kernel<_Float16, 11>), sgrid, dim3(256), 0, st, c, NS);
+            hipLaunchKernelGGL((gram_lp_kernel<_Float16, 2, 11>), dim3((unsigned)blocks), dim3(LP_WG), 0, st, c,
+                               ntile, c.nsplit);
+            break;
         default: return -1;
     }
     return hipGetLastError() == hipSuccess ? 0 : -1;

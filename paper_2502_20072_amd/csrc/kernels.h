@@ -35,6 +35,8 @@ struct Ctx {
     double *pre_bound;               // pre-pass: per-prefix L-th best [PRE_Q]
     double *rec3;                    // D = 3: pair records of the filter task [ceil(S/4)][S][4][4] (null if absent)
     double *G1;                      // the filter task's matrix alone, one-task tiled layout (G itself when T = 1)
+    double *rec4;                    // D = 4, one task: pair-group records [rows][S4_ROW] (null if absent)
+    int64_t *r4off;                  //   record rows of the groups with i2 below each index [S + 1]
     uint64_t *mtq;                   // several tasks, D = 3: flagged sweep steps [mtq_chunks][MTQ_CHUNK][3]
     uint32_t *mtq_n;                 //   keys per chunk
     uint64_t *mtq_pre;               //   exclusive prefix of mtq_n over the chunks taken [+1]
@@ -75,6 +77,7 @@ struct SearchCall {
 };
 
 uint64_t s3_tiles_host(int64_t S);  // tiles of the D = 3 record-table sweep
+uint64_t s4_tiles_host(int64_t S);  // tiles of the D = 4 record-table sweep
 int launch_stats(const Ctx &c, hipStream_t st);
 int launch_gram(const Ctx &c, hipStream_t st);  // FP64 MFMA or precision form, then finish
 int launch_gram_lp(const Ctx &c, int NS, hipStream_t st);
@@ -86,5 +89,21 @@ int launch_prefix_target(const Ctx &c, const double *best, int64_t n, float *tar
 int launch_prefix_features(const Ctx &c, int M, const int32_t *pre, int64_t n, float *out, hipStream_t st);
 int launch_prefix_features_range(const Ctx &c, int M, uint64_t r0, int64_t n, float *out, hipStream_t st);
 int launch_list_search(const Ctx &c, int D, int k, const int32_t *pre, int64_t n, hipStream_t st);
+
+// batched one-task D = 3 search: per-problem prologue, one search launch for
+// all problems, per-problem epilogue (merge, re-score, final ordering)
+constexpr int S3B_MAXP = 128;  // problems per batched search launch
+constexpr int S3B_RUN = 16;    // consecutive tiles per queue item
+struct BatchSearchArgs {
+    int P;                          // problems, ordered by decreasing tile count
+    int KPmax;                      // longest list among them
+    const uint32_t *item_end;       // device [P]: inclusive prefix of the problems' item counts
+    const Ctx *const *ctx;          // device [P]: each problem's Ctx, copied to its workspace
+};
+constexpr size_t S3B_TABLE_BYTES = S3B_MAXP * (sizeof(uint32_t) + sizeof(void *)) + 64;
+bool s3_batchable(const Ctx &c, int D);
+int launch_batch_prologue(const Ctx &c, const SearchCall &sc, hipStream_t st);
+int launch_batch_search3(const BatchSearchArgs &b, int wgs, hipStream_t st);
+int launch_batch_epilogue(const Ctx &c, const SearchCall &sc, hipStream_t st);
 
 }  // namespace sl0

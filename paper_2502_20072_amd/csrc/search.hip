@@ -156,6 +156,39 @@ __device__ double ne_sse(const Ctx &c, int D, const int32_t *tup) {
 }
 
 // Sorted per-wave list in LDS: entries e = lane + 64 m, m < KP/64.
+// A wave's sorted list is written to global memory only up to its first
+// empty (+inf) entry, which is written too as a terminator: readers stop
+// there, so the (usually empty) tail of KP entries costs no traffic.
+__device__ inline void list_store(double *__restrict__ ds, uint64_t *__restrict__ dr, const double *Ls,
+                                  const uint64_t *Lr, int KP) {
+    const int lane = threadIdx.x & 63;
+    int nv = 0;
+    for (int m = 0; m < KP; m += 64) nv += __popcll(__ballot(Ls[m + lane] < INF));
+    for (int m = lane; m < KP && m <= nv; m += 64) {
+        ds[m] = Ls[m];
+        dr[m] = Lr[m];
+    }
+}
+
+// Reads a list written by list_store into LDS (entries past the terminator
+// are +inf).
+__device__ inline void list_load(double *Ls, uint64_t *Lr, const double *__restrict__ ss,
+                                 const uint64_t *__restrict__ sr, int KP) {
+    const int lane = threadIdx.x & 63;
+    bool end = false;
+    for (int m = 0; m < KP; m += 64) {
+        // the live entries are the prefix before the terminator; what lies
+        // after it in the same chunk is stale and is not read as an entry
+        const double v = end ? INF : ss[m + lane];
+        const unsigned long long b = __ballot(v < INF);
+        const int nlive = end ? 0 : (b == ~0ull ? 64 : __builtin_ctzll(~b));
+        const bool live = lane < nlive;
+        Ls[m + lane] = live ? v : INF;
+        Lr[m + lane] = live ? sr[m + lane] : ~0ull;
+        end = end || nlive < 64;
+    }
+}
+
 __device__ void list_insert(double *Ls, uint64_t *Lr, int KP, double s, uint64_t r) {
     const int lane = threadIdx.x & 63;
     const int nper = KP >> 6;
@@ -227,6 +260,10 @@ __device__ void wave_sort_list(double *Ls, uint64_t *Lr, int KP) {
 // {0..N_jb-2}, grouped R at a time.
 __device__ void s3_tile_table(const Ctx &c);
 
+__device__ void s4_tables(const Ctx &c);
+
+// s3: 0 = work-item table of the general kernel, 4 = the D = 4 record-table
+// tiles, other = the D = 3 record-table tiles
 __device__ void search_init_body(const Ctx &c, int64_t e, bool leader, int D, int R, int JB, int s3,
                                  bool clear_pre = true) {
     if (e < (int64_t)(SISSO_MAX_D + 1) * (c.S + 1)) {
@@ -242,7 +279,13 @@ __device__ void search_init_body(const Ctx &c, int64_t e, bool leader, int D, in
         *c.merge_count = 0;
         *c.mtq_taken = 0;
         c.flags[FLAG_CAPACITY] = 0;
+        c.flags[FLAG_BATCHQ] = 0;
+        c.flags[FLAG_NLISTS] = 0;
         c.stats[1] = 0;
+        if (s3 == 4) {
+            s4_tables(c);
+            return;
+        }
         if (s3) {
             s3_tile_table(c);
             return;
@@ -593,7 +636,8 @@ __global__ __launch_bounds__(PRE_WG) void pre_extend_kernel(Ctx c, int ranged, u
     }
 }
 
-__device__ double theta0_from_prepass(const Ctx &c, int L, int KP) {
+template <class CtxT>
+__device__ double theta0_from_prepass(const CtxT &c, int L, int KP) {
     const int Q = *c.pre_count;
     if ((int64_t)Q * L < KP) return INF;
     double th = 0.0;
@@ -1131,10 +1175,7 @@ __global__ __launch_bounds__(256) void search_kernel(Ctx c, SearchArgs a) {
     if (lane == 0 && offered) atomicAdd(c.cand_counter, offered);
     // write this wave's list
     const int64_t gw = (int64_t)blockIdx.x * SEARCH_WAVES + wave;
-    for (int m = lane; m < KP; m += 64) {
-        c.list_sse[gw * KP + m] = Ls[m];
-        c.list_rank[gw * KP + m] = Lr[m];
-    }
+    list_store(c.list_sse + gw * KP, c.list_rank + gw * KP, Ls, Lr, KP);
 }
 
 // ------------------------------------------- D = 3, one task: record table
@@ -1415,58 +1456,29 @@ __device__ __forceinline__ unsigned mt_step(const Ctx &c, const SearchArgs &a, c
     return offered;
 }
 
-// MT: several tasks (the sweep filters on the filter task alone, the exact
-// path sums every task); a template parameter so that the one-task kernel's
-// registers are not shaped by the several-task exact path
-template <bool MT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S3_WPE))) void search3_kernel(Ctx c, SearchArgs a, const double *__restrict__ rec,
-                                                      const uint64_t *__restrict__ tcum) {
-    extern __shared__ double smem[];
-    __shared__ unsigned long long s_q[SEARCH_WAVES][S3_JR][2];
-    __shared__ int s_qj[SEARCH_WAVES][S3_JR];
+// One tile of the D = 3 record-table sweep (see search3_kernel): the tile's
+// k-dependent terms, the sweep over its rows, exact scoring of the flagged
+// steps into the wave's list (one task) or their queueing (several tasks),
+// and the publication of the wave's bound.  Shared by the one-problem kernel
+// and the batched kernel.
+// CtxT: Ctx (a kernel argument) or a Ctx in the constant address space (a
+// copy in device memory, read by the batched kernel): both let the compiler
+// read the fields with scalar loads into scalar registers.
+template <bool MT, class CtxT>
+__device__ __forceinline__ void s3_tile(const CtxT &c, const SearchArgs &a, const double *__restrict__ rec,
+                                        const uint64_t *__restrict__ tcum, uint64_t t, double *Ls, uint64_t *Lr,
+                                        double theta0, double &theta_pub, unsigned &offered, int &qchunk, int &qn,
+                                        unsigned long long (*s_qw)[2], int *s_qjw) {
     const int KP = a.KP;
     const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    double *Ls = smem + (size_t)wave * KP * 2;
-    uint64_t *Lr = reinterpret_cast<uint64_t *>(Ls + KP);
-    for (int m = lane; m < KP; m += 64) {
-        Ls[m] = INF;
-        Lr[m] = ~0ull;
-    }
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    __builtin_amdgcn_wave_barrier();
-    double theta_pub = INF;
-    unsigned offered = 0;
-    const double theta0 = theta0_from_prepass(c, a.L, KP);
     const int64_t S = c.S;
     const int64_t nb = s3_nblocks(S);
-    const uint64_t ntiles = tcum[nb];
     const int64_t nt = c.Gnt;
-    // the filter task's matrix and statistics (the only task when T = 1)
     const double *__restrict__ Gb = c.G1;
     const int TP = c.TP;
     const int ts = c.tstar[0];
-    const int64_t gw = (int64_t)blockIdx.x * SEARCH_WAVES + wave;
-    // several tasks: flagged steps are queued in chunks of MTQ_CHUNK and scored
-    // by a later, evenly spread kernel (the steps cluster in the few tiles of
-    // the best features); wave gw owns chunk gw, further chunks come from the
-    // pool above the launched waves' own, one atomic each
-    int qchunk = MT ? (int)gw : -1, qn = 0;
     const double *__restrict__ inv_st = c.inv_s + (int64_t)ts * S;
-
-    // Tiles are dealt round-robin over the waves (their costs are nearly
-    // equal; a shared counter would serialise on one address), XCD-aware:
-    // workgroups are placed on the eight XCDs in turn (workgroup b on XCD
-    // b mod 8), and runs of S3_XCD_RUN consecutive tiles, which share blocks
-    // of G, go to the waves of one XCD and its L2.
-    const bool xa = (gridDim.x % S3_XCDS) == 0;
-    const uint64_t xcd = xa ? blockIdx.x % S3_XCDS : 0;
-    const uint64_t nx = xa ? S3_XCDS : 1;
-    const uint64_t U = (uint64_t)gridDim.x / nx * SEARCH_WAVES;      // waves per XCD
-    const uint64_t u0 = (uint64_t)blockIdx.x / nx * SEARCH_WAVES + wave;
-    for (uint64_t sx = u0;; sx += U) {
-        const uint64_t t = ((sx / S3_XCD_RUN) * nx + xcd) * S3_XCD_RUN + sx % S3_XCD_RUN;
-        if (t >= ntiles) break;
+    {
         // tile -> (j-block, column chunk, group)
         int64_t lo = 0, hi = nb - 1;
         while (lo < hi) {
@@ -1597,9 +1609,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S3_WPE))) v
                     if (jr > nrow) m0 = m1 = 0;
                     if (m0 | m1) {
                         if (lane == 0) {
-                            s_q[wave][nq][0] = m0;
-                            s_q[wave][nq][1] = m1;
-                            s_qj[wave][nq] = jr;
+                            s_qw[nq][0] = m0;
+                            s_qw[nq][1] = m1;
+                            s_qjw[nq] = jr;
                         }
                         ++nq;
                     }
@@ -1623,9 +1635,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S3_WPE))) v
         // exact scoring of the flagged steps (rare): the same terms, a true
         // division, the rank test and the current bound
         for (int e = 0; e < nq; ++e) {
-            const int jr = s_qj[wave][e];
+            const int jr = s_qjw[e];
             const int64_t j = jlo + jr;
-            const unsigned long long fm[2] = {s_q[wave][e][0], s_q[wave][e][1]};
+            const unsigned long long fm[2] = {s_qw[e][0], s_qw[e][1]};
             if (MT) {
                 // several tasks: queue the step (row j of group g, chunk kcx,
                 // the flags); a later, evenly spread kernel scores it.  The
@@ -1701,12 +1713,527 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S3_WPE))) v
             if (lane == 0) theta_publish(c.theta_bits, tw);
         }
     }
+}
+
+// MT: several tasks (the sweep filters on the filter task alone, the exact
+// path sums every task); a template parameter so that the one-task kernel's
+// registers are not shaped by the several-task exact path
+template <bool MT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S3_WPE))) void search3_kernel(Ctx c, SearchArgs a, const double *__restrict__ rec,
+                                                      const uint64_t *__restrict__ tcum) {
+    extern __shared__ double smem[];
+    __shared__ unsigned long long s_q[SEARCH_WAVES][S3_JR][2];
+    __shared__ int s_qj[SEARCH_WAVES][S3_JR];
+    const int KP = a.KP;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    double *Ls = smem + (size_t)wave * KP * 2;
+    uint64_t *Lr = reinterpret_cast<uint64_t *>(Ls + KP);
+    for (int m = lane; m < KP; m += 64) {
+        Ls[m] = INF;
+        Lr[m] = ~0ull;
+    }
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_wave_barrier();
+    double theta_pub = INF;
+    unsigned offered = 0;
+    const double theta0 = theta0_from_prepass(c, a.L, KP);
+    const uint64_t ntiles = tcum[s3_nblocks(c.S)];
+    const int64_t gw = (int64_t)blockIdx.x * SEARCH_WAVES + wave;
+    // several tasks: flagged steps are queued in chunks of MTQ_CHUNK and scored
+    // by a later, evenly spread kernel (the steps cluster in the few tiles of
+    // the best features); wave gw owns chunk gw, further chunks come from the
+    // pool above the launched waves' own, one atomic each
+    int qchunk = MT ? (int)gw : -1, qn = 0;
+
+    // Tiles are dealt round-robin over the waves (their costs are nearly
+    // equal; a shared counter would serialise on one address), XCD-aware:
+    // workgroups are placed on the eight XCDs in turn (workgroup b on XCD
+    // b mod 8), and runs of S3_XCD_RUN consecutive tiles, which share blocks
+    // of G, go to the waves of one XCD and its L2.
+    const bool xa = (gridDim.x % S3_XCDS) == 0;
+    const uint64_t xcd = xa ? blockIdx.x % S3_XCDS : 0;
+    const uint64_t nx = xa ? S3_XCDS : 1;
+    const uint64_t U = (uint64_t)gridDim.x / nx * SEARCH_WAVES;      // waves per XCD
+    const uint64_t u0 = (uint64_t)blockIdx.x / nx * SEARCH_WAVES + wave;
+    for (uint64_t sx = u0;; sx += U) {
+        const uint64_t t = ((sx / S3_XCD_RUN) * nx + xcd) * S3_XCD_RUN + sx % S3_XCD_RUN;
+        if (t >= ntiles) break;
+        s3_tile<MT, Ctx>(c, a, rec, tcum, t, Ls, Lr, theta0, theta_pub, offered, qchunk, qn, s_q[wave], s_qj[wave]);
+    }
     if (lane == 0 && offered) atomicAdd(c.cand_counter, offered);
     if (MT && qchunk >= 0 && lane == 0) c.mtq_n[qchunk] = (uint32_t)qn;
-    for (int m = lane; m < KP; m += 64) {
-        c.list_sse[gw * KP + m] = Ls[m];
-        c.list_rank[gw * KP + m] = Lr[m];
+    list_store(c.list_sse + gw * KP, c.list_rank + gw * KP, Ls, Lr, KP);
+}
+
+// ---------------------------------------- batched D = 3 search (one task)
+#ifndef S3B_WPE
+#define S3B_WPE 3                     // waves per SIMD of the batched kernel (its per-problem state)
+#endif
+// Several independent one-task problems searched by one launch: the record
+// tables and pre-pass bounds of every problem are built first (each problem
+// on its own), then the waves of one persistent grid pull work items from a
+// device queue -- item = a run of S3B_RUN consecutive tiles of one problem,
+// problems ordered by decreasing tile count, so the largest start first and
+// the small ones fill the tail.  A wave keeps one list per problem it works
+// on: when its next item belongs to another problem it writes the list to
+// that problem's next free list slot (a wave never returns to a problem, as
+// items are taken in queue order) and starts an empty one.  Each problem's
+// merge then reads the lists its waves wrote; the rest is the one-problem
+// path, so the results equal those of separate searches bitwise.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S3B_WPE))) void search3_batch_kernel(
+    BatchSearchArgs b) {
+    extern __shared__ double smem[];
+    __shared__ unsigned long long s_q[SEARCH_WAVES][S3_JR][2];
+    __shared__ int s_qj[SEARCH_WAVES][S3_JR];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    double *Ls = smem + (size_t)wave * b.KPmax * 2;
+    uint64_t *Lr = reinterpret_cast<uint64_t *>(Ls + b.KPmax);
+    uint32_t *queue = b.ctx[0]->flags + FLAG_BATCHQ;
+    const uint32_t nitems = b.item_end[b.P - 1];
+    int cur = -1, qchunk = -1, qn = 0;
+    const Ctx *cur_ctx = nullptr;
+    double theta0 = INF, theta_pub = INF;
+    unsigned offered = 0;
+    SearchArgs a{};
+    a.D = 3;
+    auto flush = [&](const Ctx &c) {
+        uint32_t slot = 0;
+        if (lane == 0) slot = atomicAdd(c.flags + FLAG_NLISTS, 1u);
+        slot = (uint32_t)__shfl((int)slot, 0);
+        if (lane == 0 && offered) atomicAdd(c.cand_counter, offered);
+        if (slot < (uint32_t)c.nwaves)
+            list_store(c.list_sse + (int64_t)slot * a.KP, c.list_rank + (int64_t)slot * a.KP, Ls, Lr, a.KP);
+    };
+    for (;;) {
+        uint32_t it = 0;
+        if (lane == 0) it = atomicAdd(queue, 1u);
+        it = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)__shfl((int)it, 0));
+        if (it >= nitems) break;
+        typedef const __attribute__((address_space(4))) uint32_t CU32;
+        typedef const __attribute__((address_space(4))) uint64_t CU64;
+        CU32 *ie = (CU32 *)(uintptr_t)b.item_end;
+        int p = 0;
+        while (ie[p] <= it) ++p;
+        p = __builtin_amdgcn_readfirstlane(p);
+        const uint32_t first = p ? ie[p - 1] : 0u;
+        const Ctx *cp = (const Ctx *)(uintptr_t)((CU64 *)(uintptr_t)b.ctx)[p];
+        typedef const __attribute__((address_space(4))) Ctx CCtx;
+        CCtx &c = *(CCtx *)(uintptr_t)cp;
+        if (p != cur) {
+            if (cur >= 0) flush(*cur_ctx);
+            cur_ctx = cp;
+            cur = p;
+            a.KP = c.KP;
+            a.L = (c.KP + PRE_Q - 1) / PRE_Q;
+            for (int m = lane; m < a.KP; m += 64) {
+                Ls[m] = INF;
+                Lr[m] = ~0ull;
+            }
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            __builtin_amdgcn_wave_barrier();
+            theta0 = theta0_from_prepass(c, a.L, a.KP);
+            theta_pub = INF;
+            offered = 0;
+        }
+        const uint64_t ntiles = c.cum[s3_nblocks(c.S)];
+        const uint64_t t0 = (uint64_t)(it - first) * S3B_RUN;
+        const uint64_t t1 = t0 + S3B_RUN < ntiles ? t0 + S3B_RUN : ntiles;
+        for (uint64_t t = t0; t < t1; ++t)
+            s3_tile<false, CCtx>(c, a, c.rec3, c.cum, t, Ls, Lr, theta0, theta_pub, offered, qchunk, qn, s_q[wave],
+                                 s_qj[wave]);
     }
+    if (cur >= 0) flush(*cur_ctx);
+}
+
+// ------------------------------------------- D = 4, one task: record table
+// The D = 3 design one level up.  For every prefix (i1, i2, j) the Cholesky
+// row of j against the pair is built once per search into a table
+// (rec4_kernel); the sweep reads the rows of one pair group (four i1 with
+// the same i2) for one j with scalar loads, so the records enter the FP64
+// instructions as scalar operands.  A work tile is (pair group, S4_JR rows j,
+// S4_KC columns k), two adjacent k per lane.  Per tuple, with the pair's
+// k-dependent terms w0 = G[i1][k], w1 = (G[i2][k] - r w0) / s (r = G[i1][i2],
+// s = sqrt(1 - r^2)), d' = G[k][k] - w0^2 - w1^2 and zeta' = b_k - w0 z0 -
+// w1 z1 held in registers for the tile:
+//   u = g - v0 w0 - v1 w1,  d = d' - alpha u^2,  zeta = zeta' - zs u,
+//   pass iff zeta^2 >= (p - theta) d.
+// Record of (i1, i2, j), i1 = 4 h + r in group (i2, h), row
+// R = r4off[i2] + h (S - 2 - i2) + j - i2 - 1:
+//   rec[(R S4_NR + r) S4_RECW + {0..4}] = {v0, v1, 1/d_j, z_j / s_j, p}
+// with v0 = G[i1][j], v1 = (G[i2][j] - r v0) / s, d_j = G[j][j] - v0^2 - v1^2,
+// z0 = b_i1, z1 = (b_i2 - r z0) / s, z_j = (b_j - v0 z0 - v1 z1) / s_j,
+// s_j = sqrt(d_j), p = c - z0^2 - z1^2 - z_j^2 (the SSE of the triple);
+// p = NaN (fails every comparison) unless i1 < i2 < j, column i1 is live,
+// 1 - r^2 > RANK_EPS and d_j > RANK_EPS.
+#ifndef S4_WPE
+#define S4_WPE 3                      // waves per SIMD the register budget is sized for
+#endif
+#ifndef S4_WRUN
+#define S4_WRUN 4                     // consecutive tiles per wave
+#endif
+__host__ __device__ inline void s4_block(int64_t S, int64_t jb, int64_t &kc0, int64_t &ng) {
+    const int64_t j0 = jb * S4_JR;
+    int64_t jmax = j0 + S4_JR - 1;
+    if (jmax > S - 2) jmax = S - 2;
+    kc0 = (j0 + 1) / S4_KC;
+    ng = jmax >= 2 ? s4_groups_below(jmax) : 0;  // groups with i2 < jmax
+}
+__host__ __device__ inline int64_t s4_nblocks(int64_t S) { return S >= 4 ? (S - 2) / S4_JR + 1 : 0; }
+__host__ __device__ inline int64_t s4_nchunks(int64_t S) { return (S + S4_KC - 1) / S4_KC; }
+
+// pair group index -> (i2, h): i2 is the largest index whose groups start at or before g
+__device__ inline int64_t s4_group_i2(int64_t S, int64_t g) {
+    int64_t lo = 1, hi = S - 3;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (s4_groups_below(mid) <= g) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// tcum[jb] = tiles of the blocks before jb; r4off[i] = record rows of the
+// groups with i2 < i (serial, leader thread of the initialisation)
+__device__ void s4_tables(const Ctx &c) {
+    const int64_t S = c.S;
+    const int64_t nb = s4_nblocks(S), nkc = s4_nchunks(S);
+    uint64_t acc = 0;
+    c.cum[0] = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+        int64_t kc0, ng;
+        s4_block(S, b, kc0, ng);
+        acc += (uint64_t)((nkc - kc0) * ng);
+        c.cum[b + 1] = acc;
+    }
+    c.stats[1] = acc;
+    int64_t rows = 0;
+    for (int64_t i = 0; i <= S; ++i) {
+        c.r4off[i] = rows;
+        if (i >= 1 && i <= S - 3) rows += ((i + 3) / 4) * (S - 2 - i);
+    }
+}
+
+uint64_t s4_tiles_host(int64_t S) {
+    const int64_t nb = s4_nblocks(S), nkc = s4_nchunks(S);
+    uint64_t acc = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+        int64_t kc0, ng;
+        s4_block(S, b, kc0, ng);
+        acc += (uint64_t)((nkc - kc0) * ng);
+    }
+    return acc;
+}
+
+__global__ void s4_init_kernel(Ctx c) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    search_init_body(c, e, e == 0, 4, SUBP, JBLK, 4);
+}
+
+// Grid: x over (row, r) (S4_NR threads per row j = i2 + 1 + row), y over
+// pair groups (strided).  zs = z_j / s_j = e / d_j and z_j^2 = e^2 / d_j with
+// e = b_j - v0 z0 - v1 z1, so a record takes one division and no root.
+__global__ __launch_bounds__(256) void rec4_kernel(Ctx c, double *__restrict__ rec) {
+    const int64_t S = c.S;
+    const int64_t ex = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = (int)(ex % S4_NR);
+    const int64_t row = ex / S4_NR;
+    const int64_t ngr = s4_groups_below(S - 2);  // groups with i2 <= S - 3
+    const int64_t nt = c.Gnt;
+    const double *__restrict__ G = c.G;
+    const double cy = c.cyy[0];
+    for (int64_t g = blockIdx.y; g < ngr; g += gridDim.y) {
+        const int64_t i2 = s4_group_i2(S, g);
+        const int64_t j = i2 + 1 + row;
+        if (j > S - 2) continue;
+        const int64_t h = g - s4_groups_below(i2);
+        const int64_t i1 = S4_NR * h + r;
+        double v0 = 0.0, v1 = 0.0, al = 0.0, zs = 0.0, p = __builtin_nan("");
+        if (i1 < i2 && G[gidx(i1, i1, nt, 1, 0)] > RANK_EPS) {
+            const double rr = G[gidx(i1, i2, nt, 1, 0)];
+            const double s2 = G[gidx(i2, i2, nt, 1, 0)] - rr * rr;
+            if (s2 > RANK_EPS) {
+                const double isp = 1.0 / sqrt(s2);
+                const double z0 = c.bhat[i1];
+                const double z1 = (c.bhat[i2] - rr * z0) * isp;
+                const double a0 = G[gidx(i1, j, nt, 1, 0)];
+                const double a1 = (G[gidx(i2, j, nt, 1, 0)] - rr * a0) * isp;
+                const double d = G[gidx(j, j, nt, 1, 0)] - a0 * a0 - a1 * a1;
+                if (d > RANK_EPS) {
+                    const double id = 1.0 / d;
+                    const double e = c.bhat[j] - a0 * z0 - a1 * z1;
+                    v0 = a0;
+                    v1 = a1;
+                    al = id;
+                    zs = e * id;
+                    p = cy - z0 * z0 - z1 * z1 - e * zs;
+                }
+            }
+        }
+        const int64_t row = c.r4off[i2] + h * (S - 2 - i2) + (j - i2 - 1);
+        double *o = rec + (row * S4_NR + r) * S4_RECW;
+        o[0] = v0;
+        o[1] = v1;
+        o[2] = al;
+        o[3] = zs;
+        o[4] = p;
+    }
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S4_WPE))) void search4_kernel(
+    Ctx c, SearchArgs a, const double *__restrict__ rec, const uint64_t *__restrict__ tcum) {
+    extern __shared__ double smem[];
+    __shared__ unsigned long long s_q[SEARCH_WAVES][S4_JR][2];
+    __shared__ int s_qj[SEARCH_WAVES][S4_JR];
+    const int KP = a.KP;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    double *Ls = smem + (size_t)wave * KP * 2;
+    uint64_t *Lr = reinterpret_cast<uint64_t *>(Ls + KP);
+    for (int m = lane; m < KP; m += 64) {
+        Ls[m] = INF;
+        Lr[m] = ~0ull;
+    }
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_wave_barrier();
+    double theta_pub = INF;
+    unsigned offered = 0;
+    const double theta0 = theta0_from_prepass(c, a.L, KP);
+    const int64_t S = c.S;
+    const int64_t nb = s4_nblocks(S);
+    const uint64_t ntiles = tcum[nb];
+    const int64_t nt = c.Gnt;
+    const double *__restrict__ Gb = c.G;
+    const int64_t gw = (int64_t)blockIdx.x * SEARCH_WAVES + wave;
+    const double *__restrict__ inv_st = c.inv_s;
+
+    // tiles dealt round-robin, XCD-aware, as in search3_kernel
+    const bool xa = (gridDim.x % S3_XCDS) == 0;
+    const uint64_t xcd = xa ? blockIdx.x % S3_XCDS : 0;
+    const uint64_t nx = xa ? S3_XCDS : 1;
+    const uint64_t U = (uint64_t)gridDim.x / nx * SEARCH_WAVES;
+    const uint64_t u0 = (uint64_t)blockIdx.x / nx * SEARCH_WAVES + wave;
+    // a wave takes S4_WRUN consecutive tiles (the column chunks of one pair
+    // group and row block share its record rows, which then come from the
+    // scalar cache); runs are dealt round-robin and XCD-aware as tiles are in
+    // search3_kernel
+    for (uint64_t sx = u0;; sx += U) {
+        const uint64_t run = ((sx / S3_XCD_RUN) * nx + xcd) * S3_XCD_RUN + sx % S3_XCD_RUN;
+        if (run * S4_WRUN >= ntiles) break;
+        const uint64_t tend = run * S4_WRUN + S4_WRUN < ntiles ? run * S4_WRUN + S4_WRUN : ntiles;
+        for (uint64_t t = run * S4_WRUN; t < tend; ++t) {
+        int64_t lo = 0, hi = nb - 1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (tcum[mid] <= t) lo = mid; else hi = mid - 1;
+        }
+        const int64_t jb = lo;
+        int64_t kc0, ng;
+        s4_block(S, jb, kc0, ng);
+        const int64_t nkb = s4_nchunks(S) - kc0;
+        const int64_t rem = (int64_t)(t - tcum[jb]);
+        const int64_t kcx = kc0 + rem % nkb;
+        const int64_t grp = uni(rem / nkb);
+        const int64_t i2 = uni(s4_group_i2(S, grp));
+        const int64_t hh = grp - s4_groups_below(i2);
+        const int64_t j0 = jb * S4_JR;
+        const int64_t jlo = j0 > i2 + 1 ? j0 : i2 + 1;
+        const int64_t jhi = (j0 + S4_JR - 1 < S - 2) ? j0 + S4_JR - 1 : S - 2;
+        const int nrow = (int)(jhi - jlo);  // steps 0..nrow (>= 0: i2 < jhi)
+        const int64_t kb = kcx * S4_KC;
+        const int64_t k0 = kb + 2 * lane, k1 = k0 + 1;
+        const bool kv0 = k0 < S, kv1 = k1 < S;
+        const int64_t kk = kv0 ? k0 : ((S - 1) & ~(int64_t)1);
+        const bool diag = kb <= jhi;
+
+        double th = fmin(theta0, theta_load(c.theta_bits));
+        th = fmin(th, Ls[KP - 1]);
+        const double theta_f = th < INF ? th * (1.0 + THETA_SLACK) : INF;
+
+        // k-dependent part of each pair's solve, for both columns of the lane
+        double w0[S4_NR][2], w1[S4_NR][2], dq[S4_NR][2], zq[S4_NR][2];
+        {
+            const int64_t kd1 = kv1 ? k1 : kk;
+            const double gd0 = inv_st[kk] > 0.0 ? 1.0 : 0.0;
+            const double gd1 = inv_st[kd1] > 0.0 ? 1.0 : 0.0;
+            const double b0 = c.bhat[kk], b1 = c.bhat[kd1];
+            const double2 w2v = *reinterpret_cast<const double2 *>(Gb + gidx(i2, kk, nt, 1, 0));
+            const double zb2 = c.bhat[i2];
+            const bool live2 = inv_st[i2] > 0.0;
+#pragma unroll
+            for (int r = 0; r < S4_NR; ++r) {
+                int64_t i1 = S4_NR * hh + r;
+                const bool pin = i1 < i2;
+                if (!pin) i1 = i2;  // a void pair reads valid memory and never passes
+                const double rr = Gb[gidx(i1, i2, nt, 1, 0)];
+                const double s2 = (live2 ? 1.0 : 0.0) - rr * rr;
+                const bool pv = pin && inv_st[i1] > 0.0 && s2 > RANK_EPS;
+                const double isp = pv ? 1.0 / sqrt(s2) : 0.0;
+                const double z0 = c.bhat[i1];
+                const double z1 = (zb2 - rr * z0) * isp;
+                const double2 w1v = *reinterpret_cast<const double2 *>(Gb + gidx(i1, kk, nt, 1, 0));
+                const double a0 = w1v.x, a1 = w1v.y;
+                const double c0 = (w2v.x - rr * a0) * isp, c1 = (w2v.y - rr * a1) * isp;
+                w0[r][0] = a0;
+                w0[r][1] = a1;
+                w1[r][0] = c0;
+                w1[r][1] = c1;
+                // a lane past S, a constant column or a void pair never passes
+                dq[r][0] = (pv && kv0 && gd0 > RANK_EPS) ? gd0 - a0 * a0 - c0 * c0 : __builtin_nan("");
+                dq[r][1] = (pv && kv1 && gd1 > RANK_EPS) ? gd1 - a1 * a1 - c1 * c1 : __builtin_nan("");
+                zq[r][0] = b0 - a0 * z0 - c0 * z1;
+                zq[r][1] = b1 - a1 * z0 - c1 * z1;
+            }
+        }
+        const char *__restrict__ gtile = reinterpret_cast<const char *>(Gb + (((j0 >> 6) * nt) << 12));
+        const uint32_t voff = (uint32_t)((((kk >> 6) << 12) + (kk & 63) + ((jlo & 63) << 6)) * 8);
+        // records of row jlo + x are S4_ROW doubles at recj + S4_ROW x (uniform)
+        const double *__restrict__ recj =
+            rec + (size_t)(c.r4off[i2] + hh * (S - 2 - i2) + (jlo - i2 - 1)) * S4_ROW;
+        int nq = 0;
+        auto sweep = [&](auto diagc) {
+            constexpr bool DIAG = decltype(diagc)::value;
+            constexpr int JG = S3_JG;
+            double2 ga[JG], gb[JG];
+            auto fetch = [&](double2 (&dst)[JG], int jg) {
+#pragma unroll
+                for (int x = 0; x < JG; ++x) {
+                    const uint32_t jr = (uint32_t)(jg + x < nrow ? jg + x : nrow);
+                    dst[x] = *reinterpret_cast<const double2 *>(gtile + (voff + jr * 512u));
+                }
+            };
+            // records of one step: two halves of two pairs (10 doubles each),
+            // each loaded while the other is scored (scalar loads return out of
+            // order, so the half in flight is waited for before the next issue)
+            constexpr int HW = 2 * S4_RECW;
+            auto load_half = [&](double (&rv)[HW], int jr, int h) {
+                const double *rp = recj + (size_t)jr * S4_ROW + h * HW;
+#pragma unroll
+                for (int e = 0; e < HW; ++e) rv[e] = rp[e];
+            };
+            auto score_half = [&](const double (&rv)[HW], const double2 gv, int h, unsigned long long &m0,
+                                  unsigned long long &m1) {
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const int r = 2 * h + q;
+                    const double *x = rv + q * S4_RECW;
+                    const double pi = x[4] - theta_f;
+                    {
+                        const double u = fma(-x[1], w1[r][0], fma(-x[0], w0[r][0], gv.x));
+                        const double d = fma(-x[2], u * u, dq[r][0]);
+                        const double z = fma(-x[3], u, zq[r][0]);
+                        m0 |= __ballot(z * z >= pi * d);
+                    }
+                    {
+                        const double u = fma(-x[1], w1[r][1], fma(-x[0], w0[r][1], gv.y));
+                        const double d = fma(-x[2], u * u, dq[r][1]);
+                        const double z = fma(-x[3], u, zq[r][1]);
+                        m1 |= __ballot(z * z >= pi * d);
+                    }
+                }
+            };
+            double ra[HW], rb[HW];
+            load_half(ra, 0, 0);
+            auto score = [&](const double2 (&src)[JG], int jg) {
+#pragma unroll
+                for (int x = 0; x < JG; ++x) {
+                    const int jr = jg + x;
+                    const int jc = jr <= nrow ? jr : nrow;
+                    unsigned long long m0 = 0, m1 = 0;
+                    __builtin_amdgcn_s_waitcnt(0xC07F);
+                    load_half(rb, jc, 1);
+                    __builtin_amdgcn_sched_barrier(0);
+                    score_half(ra, src[x], 0, m0, m1);
+                    __builtin_amdgcn_s_waitcnt(0xC07F);
+                    load_half(ra, jr + 1 <= nrow ? jr + 1 : nrow, 0);
+                    __builtin_amdgcn_sched_barrier(0);
+                    score_half(rb, src[x], 1, m0, m1);
+                    if (DIAG) {
+                        const int64_t j = jlo + jr;
+                        m0 &= __ballot(k0 > j);
+                        m1 &= __ballot(k1 > j);
+                    }
+                    if (jr > nrow) m0 = m1 = 0;
+                    if (m0 | m1) {
+                        if (lane == 0) {
+                            s_q[wave][nq][0] = m0;
+                            s_q[wave][nq][1] = m1;
+                            s_qj[wave][nq] = jr;
+                        }
+                        ++nq;
+                    }
+                }
+            };
+            __builtin_amdgcn_s_waitcnt(0x0F70);
+            fetch(ga, 0);
+            for (int jg = 0;; jg += 2 * JG) {
+                fetch(gb, jg + JG);
+                score(ga, jg);
+                fetch(ga, jg + 2 * JG);
+                score(gb, jg + JG);
+                if (jg + 2 * JG > nrow) break;
+            }
+        };
+        if (diag) sweep(std::true_type{});
+        else sweep(std::false_type{});
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_wave_barrier();
+
+        // exact scoring of the flagged steps (rare): the same terms, a true
+        // division, the rank test and the current bound
+        auto pick = [&](const double (&arr)[S4_NR][2], int r, int sl) {
+            double v = arr[0][0];
+#pragma unroll
+            for (int q = 0; q < S4_NR; ++q)
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+                    if (q == r && h == sl) v = arr[q][h];
+            return v;
+        };
+        for (int e = 0; e < nq; ++e) {
+            const int jr = s_qj[wave][e];
+            const int64_t j = jlo + jr;
+            const unsigned long long fm[2] = {s_q[wave][e][0], s_q[wave][e][1]};
+            const double *rp = recj + (size_t)jr * S4_ROW;
+            const double2 gv = *reinterpret_cast<const double2 *>(gtile + (voff + (uint32_t)jr * 512u));
+            for (int r = 0; r < S4_NR; ++r) {
+                const double *x = rp + r * S4_RECW;
+                const double v0 = x[0], v1 = x[1], al = x[2], zs = x[3], p = x[4];
+                for (int sl = 0; sl < 2; ++sl) {
+                    const double gg = sl ? gv.y : gv.x;
+                    const int64_t k = sl ? k1 : k0;
+                    const double u = fma(-v1, pick(w1, r, sl), fma(-v0, pick(w0, r, sl), gg));
+                    const double d = fma(-al, u * u, pick(dq, r, sl));
+                    const double z = fma(-zs, u, pick(zq, r, sl));
+                    const int32_t tup[4] = {(int32_t)(S4_NR * hh + r), (int32_t)i2, (int32_t)j, (int32_t)k};
+                    const double es = (d > RANK_EPS) ? p - z * z / d : INF;
+                    bool take = ((fm[sl] >> lane) & 1ull) && k < S && k > j && es <= fmin(theta_f, Ls[KP - 1]);
+                    if (take && a.ranged) {
+                        const uint64_t lr = lex_rank(BinomTab{c.btab, c.S}, c.S, 4, tup);
+                        if (lr < a.r0 || lr >= a.r1) take = false;
+                    }
+                    unsigned long long m = __ballot(take);
+                    const uint64_t rk = take ? pack_tuple(tup, 4) : 0;
+                    offered += (unsigned)__popcll(m);
+                    while (m) {
+                        const int src = __ffsll((long long)m) - 1;
+                        m &= m - 1;
+                        const double cs = __shfl(es, src);
+                        const uint64_t cr = (uint64_t)__shfl((long long)rk, src);
+                        list_insert(Ls, Lr, KP, cs, cr);
+                    }
+                }
+            }
+        }
+        const double tw = Ls[KP - 1];
+        if (tw < theta_pub) {
+            theta_pub = tw;
+            if (lane == 0) theta_publish(c.theta_bits, tw);
+        }
+        }
+    }
+    if (lane == 0 && offered) atomicAdd(c.cand_counter, offered);
+    list_store(c.list_sse + gw * KP, c.list_rank + gw * KP, Ls, Lr, KP);
 }
 
 // Several tasks, D = 3: exclusive prefix of the queued chunks' counts (one
@@ -1744,10 +2271,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S3_WPE))) v
     const int64_t nw = (int64_t)gridDim.x * SEARCH_WAVES;
     double *Ls = smem + (size_t)wave * KP * 2;
     uint64_t *Lr = reinterpret_cast<uint64_t *>(Ls + KP);
-    for (int m = lane; m < KP; m += 64) {
-        Ls[m] = c.list_sse[gw * KP + m];
-        Lr[m] = c.list_rank[gw * KP + m];
-    }
+    list_load(Ls, Lr, c.list_sse + gw * KP, c.list_rank + gw * KP, KP);
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     __builtin_amdgcn_wave_barrier();
     const int nreg = (int)min(*c.mtq_taken + (unsigned)nown, (unsigned)c.mtq_chunks);
@@ -1780,10 +2304,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S3_WPE))) v
         if (nbuf > 0) offered += mt_flush(c, Ls, Lr, KP, bk, be, nbuf, theta_f);
     }
     if (lane == 0 && offered) atomicAdd(c.cand_counter, offered);
-    for (int m = lane; m < KP; m += 64) {
-        c.list_sse[gw * KP + m] = Ls[m];
-        c.list_rank[gw * KP + m] = Lr[m];
-    }
+    list_store(c.list_sse + gw * KP, c.list_rank + gw * KP, Ls, Lr, KP);
 }
 
 // D = 1: every feature is a tuple; SSE = sum_t (c_t - b_t^2) over full-rank columns.
@@ -1821,10 +2342,7 @@ __global__ __launch_bounds__(256) void search_d1_kernel(Ctx c, SearchArgs a) {
             list_insert(Ls, Lr, KP, __shfl(s, src), (uint64_t)(kb + src));
         }
     }
-    for (int m = lane; m < KP; m += 64) {
-        c.list_sse[gw * KP + m] = Ls[m];
-        c.list_rank[gw * KP + m] = Lr[m];
-    }
+    list_store(c.list_sse + gw * KP, c.list_rank + gw * KP, Ls, Lr, KP);
 }
 
 // ------------------------------------------------- prefix-list evaluation
@@ -2063,10 +2581,7 @@ __global__ __launch_bounds__(256) void list_search_kernel(Ctx c, const int32_t *
     }
     if (fill < KP) wave_sort_list(Ls, Lr, KP);  // unused slots hold +inf and sort last
     if (lane == 0 && offered) atomicAdd(c.cand_counter, offered);
-    for (int m = lane; m < KP; m += 64) {
-        c.list_sse[gw * KP + m] = Ls[m];
-        c.list_rank[gw * KP + m] = Lr[m];
-    }
+    list_store(c.list_sse + gw * KP, c.list_rank + gw * KP, Ls, Lr, KP);
 }
 
 // Per-prefix features for the learned proposal (FP32, PROP_NF per prefix),
@@ -2181,18 +2696,28 @@ __device__ inline double merge_bound(const Ctx &c, int L, int KP, int use_pre) {
     return bound < INF ? bound * (1.0 + THETA_SLACK) : INF;
 }
 
+// nl_dev (may be null): the number of lists written, read on the device (at
+// most nlists; the batched search writes a variable number per problem)
 __global__ __launch_bounds__(MERGE_THREADS) void merge_compact_kernel(Ctx c, int nlists, int KP, int L,
-                                                                      int use_pre) {
+                                                                      int use_pre, const uint32_t *nl_dev) {
     const int lane = threadIdx.x & 63;
     const int64_t l = (int64_t)blockIdx.x * (MERGE_THREADS / 64) + (threadIdx.x >> 6);
-    if (l >= nlists) return;
+    const int64_t nl = nl_dev ? (int64_t)min(*nl_dev, (uint32_t)nlists) : (int64_t)nlists;
+    if (l >= nl) return;
     const double bound = merge_bound(c, L, KP, use_pre);
     const double *ls = c.list_sse + l * KP;
     const uint64_t *lr = c.list_rank + l * KP;
+    // sorted: the entries at or below the bound are a prefix, which ends at
+    // the list's terminator at the latest
     int n = 0;
     for (int m = 0; m < KP; m += 64) {
         const double v = ls[m + lane];
-        n += __popcll(__ballot(v < INF && v <= bound));
+        const unsigned long long b = __ballot(v < INF && v <= bound);
+        if (b != ~0ull) {
+            n += __builtin_ctzll(~b);  // the prefix before the first entry that fails
+            break;
+        }
+        n += 64;
     }
     if (n == 0) return;
     unsigned base = 0;
@@ -2610,11 +3135,50 @@ static void launch_one(const Ctx &c, const SearchArgs &a, size_t lds, hipStream_
     hipLaunchKernelGGL((search_kernel<D, MT>), dim3(c.search_wgs), dim3(SEARCH_WG), lds, st, c, a);
 }
 
-static void launch_merge(const Ctx &c, int nlists, int L, int use_pre, hipStream_t st, int dedupe = 0) {
+static void launch_merge(const Ctx &c, int nlists, int L, int use_pre, hipStream_t st, int dedupe = 0,
+                         const uint32_t *nl_dev = nullptr) {
     const int per = MERGE_THREADS / 64;
     hipLaunchKernelGGL(merge_compact_kernel, dim3((nlists + per - 1) / per), dim3(MERGE_THREADS), 0, st, c, nlists,
-                       c.KP, L, use_pre);
+                       c.KP, L, use_pre, nl_dev);
     hipLaunchKernelGGL(merge_select_kernel, dim3(1), dim3(MERGE_THREADS), 0, st, c, c.KP, L, use_pre, dedupe);
+}
+
+// The one-task D = 3 record-table path applies (it also needs the table in
+// the workspace and fewer than 2^31 tiles).
+bool s3_batchable(const Ctx &c, int D) {
+    return D == 3 && c.T == 1 && c.rec3 != nullptr && s3_tiles_host(c.S) < (1ull << 31);
+}
+
+// record table + initialisation + pre-pass selection (one launch), then the
+// pre-pass extension: everything before the sweep of the one-task D = 3 path
+static void s3_prologue(const Ctx &c, const SearchCall &sc, int L, hipStream_t st) {
+    const unsigned init_blocks = (unsigned)(((SISSO_MAX_D + 1) * (c.S + 1) + 255) / 256);
+    const int64_t ngr = (c.S - 3) / S3_NR + 1;
+    int64_t bx = ((c.S - 2) * S3_NR + PRE_WG - 1) / PRE_WG;
+    const int64_t ninit = (int64_t)init_blocks * 256;
+    if (bx * PRE_WG * ngr < ninit) bx = (ninit / ngr + PRE_WG - 1) / PRE_WG + 1;
+    // one more column: its first workgroup runs the pre-pass selection
+    hipLaunchKernelGGL(rec3_kernel, dim3((unsigned)(bx + 1), (unsigned)ngr), dim3(PRE_WG), 0, st, c, c.rec3);
+    launch_prepass<3>(c, sc, L, st, false);
+}
+
+int launch_batch_prologue(const Ctx &c, const SearchCall &sc, hipStream_t st) {
+    s3_prologue(c, sc, (c.KP + PRE_Q - 1) / PRE_Q, st);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_batch_search3(const BatchSearchArgs &b, int wgs, hipStream_t st) {
+    // one resident round: S3B_WPE waves on each of the 4 SIMDs of 256 CUs
+    if (wgs <= 0 || wgs > S3B_WPE * 256) wgs = S3B_WPE * 256;
+    const size_t lds = (size_t)SEARCH_WAVES * b.KPmax * 2 * sizeof(double);
+    hipLaunchKernelGGL(search3_batch_kernel, dim3((unsigned)wgs), dim3(SEARCH_WG), lds, st, b);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_batch_epilogue(const Ctx &c, const SearchCall &sc, hipStream_t st) {
+    launch_merge(c, c.nwaves, (c.KP + PRE_Q - 1) / PRE_Q, 1, st, 0, c.flags + FLAG_NLISTS);
+    launch_rescore_final(c, 3, sc.k, st);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 int launch_search(const Ctx &c, const SearchCall &sc, hipStream_t st) {
@@ -2657,7 +3221,12 @@ int launch_search(const Ctx &c, const SearchCall &sc, hipStream_t st) {
         // there are several tasks
         const bool s3 = D == 3 && c.rec3 != nullptr && s3_tiles_host(c.S) < (1ull << 31) &&
                         (!MT || c.mtq_chunks > 0);
-        if (s3) {
+        // one task, D = 4: the pair-group record table (sized at create only
+        // while it stays within S4_TABLE_MAX and 2^31 tiles)
+        const bool s4 = D == 4 && !MT && c.rec4 != nullptr;
+        if (s4) {
+            hipLaunchKernelGGL(s4_init_kernel, dim3(init_blocks), dim3(256), 0, st, c);
+        } else if (s3) {
             // record table + initialisation in one launch (its grid covers the binomial table)
             // x: the rows of one group (j, r); y: groups; the grid also covers
             // the binomial table of the initialisation
@@ -2679,7 +3248,14 @@ int launch_search(const Ctx &c, const SearchCall &sc, hipStream_t st) {
         phase_begin(c, SISSO_PHASE_SEARCH, st);
         const size_t nrec = MT ? (size_t)a.JB * c.TP : (size_t)SEARCH_WG;
         const size_t lds = lds_lists + nrec * RECW * sizeof(double) + (size_t)64 * SUBW * sizeof(double);
-        if (s3 && MT) {
+        if (s4) {
+            const int64_t ngr = s4_groups_below(c.S - 2);
+            const unsigned bx = (unsigned)(((c.S - 3) * S4_NR + 255) / 256);  // rows j = i2 + 1 .. S - 2
+            const unsigned by = (unsigned)(ngr < 65535 ? ngr : 65535);
+            hipLaunchKernelGGL(rec4_kernel, dim3(bx, by), dim3(256), 0, st, c, c.rec4);
+            hipLaunchKernelGGL(search4_kernel, dim3(c.search_wgs), dim3(SEARCH_WG), lds_lists, st, c, a,
+                               (const double *)c.rec4, (const uint64_t *)c.cum);
+        } else if (s3 && MT) {
             hipLaunchKernelGGL(search3_kernel<true>, dim3(c.search_wgs), dim3(SEARCH_WG), lds_lists, st, c, a,
                                (const double *)c.rec3, (const uint64_t *)c.cum);
             const int nown = c.search_wgs * SEARCH_WAVES;  // the sweep waves' own chunks

@@ -15,18 +15,28 @@ from paper_2502_20072_amd import _binding as B
 import paper_2502_20072_amd as P
 
 
-def _declared_functions():
-    text = open(B.HEADER).read()
+def _declared_functions(header):
+    text = open(header).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(sisso_\w+)\s*\(", text)))
 
 
+def _headers():
+    inc = os.path.dirname(B.HEADER)
+    return sorted(os.path.join(inc, f) for f in os.listdir(inc) if f.endswith(".h"))
+
+
 def test_exports_every_declared_symbol():
     lib = B.load()
-    names = _declared_functions()
-    assert len(names) >= 12
-    for n in names:
-        assert hasattr(lib, n), f"{n} declared in include/sisso_l0.h but not exported"
+    heads = _headers()
+    assert len(heads) >= 3
+    total = 0
+    for h in heads:
+        names = _declared_functions(h)
+        total += len(names)
+        for n in names:
+            assert hasattr(lib, n), f"{n} declared in {os.path.basename(h)} but not exported"
+    assert total >= 40
 
 
 def _desc(n=100, S=20, offsets=None, D_max=3, k_max=10, ws=0, wsb=0, F=0, y=0):
@@ -129,7 +139,10 @@ def test_precision_modes_size_the_workspace():
     # three BF16 slices of every padded column plus one exponent per 256-sample chunk
     n_chunks = (5000 + 255) // 256 + 1
     assert bf16 - fp64 >= 3 * 300 * n_chunks * 256 * 2 + 300 * n_chunks * 4
-    assert ws(B.SISSO_PREC_FP16_COMP) == 0      # reserved mode, not built
+    # two FP16 slices: less slice memory than three BF16 slices, more than none
+    fp16 = ws(B.SISSO_PREC_FP16_COMP)
+    assert fp16 - fp64 >= 2 * 300 * n_chunks * 256 * 2 + 300 * n_chunks * 4
+    assert fp16 < bf16
     assert ws(7) == 0
 
 
@@ -162,3 +175,35 @@ def test_several_task_d3_workspace_holds_filter_matrix_and_step_queue():
         ng = (jmax - 1) // 4 + 1 if jmax >= 1 else 0
         tiles += ((S + 127) // 128 - kc0) * ng
     assert extra_two - extra_one >= Sp * Sp * 8 + tiles * 32 * 24
+
+
+def test_sis_host_checks_without_a_device():
+    lib = B._slib()
+    # workspace sizes are pure functions of the shape and reject bad shapes
+    offs = np.array([0, 50, 120], dtype=np.int64)
+    d = B.sisso_sis_desc(None, offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), 120, 2, 3, None, 0, None)
+    a = lib.sisso_sis_workspace_bytes(ctypes.byref(d))
+    assert a == lib.sisso_sis_workspace_bytes(ctypes.byref(d)) and a >= 120 * 3 * 8
+    d.nres = 17
+    assert lib.sisso_sis_workspace_bytes(ctypes.byref(d)) == 0
+    assert lib.sisso_topm_workspace_bytes(1000, 10) > 0
+    assert lib.sisso_topm_workspace_bytes(0, 10) == 0
+    assert lib.sisso_topm_workspace_bytes(1000, 0) == 0
+    assert lib.sisso_topm_workspace_bytes(1000, (1 << 20) + 1) == 0
+    f = B.sisso_fit_desc(None, None, offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), 120, 200, 2, 3, 10, 4, 8,
+                         None, 0, None)
+    assert lib.sisso_fit_workspace_bytes(ctypes.byref(f)) > 0
+    f.k = 11                      # k > m_sis: the first dimension has only m_sis models
+    assert lib.sisso_fit_workspace_bytes(ctypes.byref(f)) == 0
+    f.k, f.M = 8, 29              # M < D_max * m_sis
+    assert lib.sisso_fit_workspace_bytes(ctypes.byref(f)) == 0
+    # argument errors are returned before any device work
+    assert lib.sisso_fc_eval(99, 1, 10, 2, 1, 1, 0.0, 1.0, None, 1, None) == B.SISSO_EINVAL
+    assert lib.sisso_fc_eval(0, 1, 10, 2, 1, 1, 2.0, 1.0, None, 1, None) == B.SISSO_EINVAL
+    cnt = ctypes.c_int32(0)
+    assert lib.sisso_topm(None, 10, 2, 1, None, ctypes.byref(cnt), 1, 1 << 20, None) == B.SISSO_EINVAL
+    assert lib.sisso_residuals(1, 1, 10, 2, 1, 1, 1, 1, 0, 1, 1, None) == B.SISSO_EINVAL
+    h = ctypes.c_void_p()
+    assert lib.sisso_sis_create(None, ctypes.byref(h)) == B.SISSO_EINVAL
+    rc = lib.sisso_fit(ctypes.byref(f), None, None, None, None)
+    assert rc == B.SISSO_EINVAL and lib.sisso_fit_last_error()

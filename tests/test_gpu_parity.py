@@ -377,3 +377,51 @@ def test_d3_many_tasks():
     gidx, gsse, gcoef = _run(p, 3, k)
     oidx, osse, _ = oracle.topk(p.F, p.y, 3, k, p.task_offsets)
     compare_topk(p, 3, k, gidx, gsse, oidx, osse, gcoef=gcoef)
+
+
+@pytest.mark.parametrize("S,n,seed", [(4, 10, 60), (5, 12, 61), (6, 14, 62), (33, 30, 63), (35, 20, 64),
+                                      (66, 24, 65), (129, 22, 66), (131, 20, 67)])
+def test_d4_record_table_edges_vs_oracle(S, n, seed):
+    """D = 4, one task: the pair-group record-table sweep at sizes around its
+    group (4 pairs), row-block (32) and column-chunk (128) edges."""
+    _say(f"d4 table edges S={S} n={n}")
+    p = tiny_problem(seed, S=S, n=n, D=4, sigma=0.4)
+    k = min(40, math.comb(S, 4))
+    gidx, gsse, gcoef = _run(p, 4, k)
+    oidx, osse, _ = oracle.topk(p.F, p.y, 4, k, p.task_offsets)
+    compare_topk(p, 4, k, gidx, gsse, oidx, osse, gcoef=gcoef)
+
+
+def test_d4_range_split_equals_full():
+    _say("d4 range split S=40 n=60")
+    p = tiny_problem(78, S=40, n=60, D=4, sigma=0.4)
+    N = math.comb(40, 4)
+    k = 30
+    fidx, fsse, _ = _run(p, 4, k)
+    parts = []
+    cuts = [0, 1, 20000, 54321, N]
+    for a, b in zip(cuts, cuts[1:]):
+        i, s, _ = _run(p, 4, min(k, b - a), k_max=k, rng=(a, b))
+        for t, v in zip(i, s):
+            if np.isfinite(v):
+                from paper_2502_20072_amd import rank_of
+                assert a <= rank_of(40, t) < b
+                parts.append((float(v), tuple(int(x) for x in t)))
+    parts.sort()
+    assert [t for _, t in parts[:k]] == [tuple(int(x) for x in t) for t in fidx]
+    np.testing.assert_array_equal([v for v, _ in parts[:k]], fsse)
+
+
+def test_d4_constant_and_collinear_columns_never_returned():
+    _say("d4 constant / collinear columns")
+    p = tiny_problem(79, S=24, n=40, D=4, sigma=0.3)
+    F = p.F.copy()
+    F[5] = 2.0                        # constant column
+    F[9] = 3.0 * F[2] - 1.0           # exactly collinear with column 2 (with the intercept)
+    p.F = F
+    gidx, gsse, _ = _run(p, 4, 25)
+    for t in gidx:
+        t = [int(v) for v in t]
+        assert 5 not in t and not (2 in t and 9 in t)
+    oidx, osse, _ = oracle.topk(p.F, p.y, 4, 25, p.task_offsets)
+    compare_topk(p, 4, 25, gidx, gsse, oidx, osse)
