@@ -287,7 +287,7 @@ def bench_exhaustive(args, p, name: str, prec: int, steps: int, warmup: int, sea
     search_s = acc["search"] * 1e-3
     flop, pruned = performed_flop(D, p.T, ntup)
     achieved = flop / search_s
-    kname = "search3_kernel" if D == 3 else "search_kernel"
+    kname = {3: "search3_kernel", 4: "search4_kernel" if p.T == 1 else "search_kernel"}.get(D, "search_kernel")
     roofline = dict(bound="alu", kernel=kname, achieved=achieved / 1e12, peak=FP64_PEAK / 1e12,
                     unit="TFLOP/s", frac=achieved / FP64_PEAK, traffic=measured_traffic(kname, name),
                     flop_per_tuple=flop / ntup, issued_flop_per_tuple=issued_flop_per_tuple(D, p.T),

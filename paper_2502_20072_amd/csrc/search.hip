@@ -1852,8 +1852,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S3B_WPE))) 
 // row of j against the pair is built once per search into a table
 // (rec4_kernel); the sweep reads the rows of one pair group (four i1 with
 // the same i2) for one j with scalar loads, so the records enter the FP64
-// instructions as scalar operands.  A work tile is (pair group, S4_JR rows j,
-// S4_KC columns k), two adjacent k per lane.  Per tuple, with the pair's
+// instructions as scalar operands.  A work tile is (pair group, S4_JR rows j
+// from j0, S4_KC columns k from j0 + 1 + S4_KC c): lane l takes k = kb + l and
+// kb + 64 + l, so only chunk 0 holds tuples with k <= j (in its first half),
+// and a last chunk with at most 64 columns left runs its first half only.
+// Per tuple, with the pair's
 // k-dependent terms w0 = G[i1][k], w1 = (G[i2][k] - r w0) / s (r = G[i1][i2],
 // s = sqrt(1 - r^2)), d' = G[k][k] - w0^2 - w1^2 and zeta' = b_k - w0 z0 -
 // w1 z1 held in registers for the tile:
@@ -1873,15 +1876,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S3B_WPE))) 
 #ifndef S4_WRUN
 #define S4_WRUN 4                     // consecutive tiles per wave
 #endif
-__host__ __device__ inline void s4_block(int64_t S, int64_t jb, int64_t &kc0, int64_t &ng) {
+// row block jb: nkb column chunks (k from j0 + 1 to S - 1) and ng pair groups
+__host__ __device__ inline void s4_block(int64_t S, int64_t jb, int64_t &nkb, int64_t &ng) {
     const int64_t j0 = jb * S4_JR;
     int64_t jmax = j0 + S4_JR - 1;
     if (jmax > S - 2) jmax = S - 2;
-    kc0 = (j0 + 1) / S4_KC;
+    nkb = (S - j0 - 1 + S4_KC - 1) / S4_KC;
     ng = jmax >= 2 ? s4_groups_below(jmax) : 0;  // groups with i2 < jmax
 }
 __host__ __device__ inline int64_t s4_nblocks(int64_t S) { return S >= 4 ? (S - 2) / S4_JR + 1 : 0; }
-__host__ __device__ inline int64_t s4_nchunks(int64_t S) { return (S + S4_KC - 1) / S4_KC; }
 
 // pair group index -> (i2, h): i2 is the largest index whose groups start at or before g
 __device__ inline int64_t s4_group_i2(int64_t S, int64_t g) {
@@ -1897,13 +1900,13 @@ __device__ inline int64_t s4_group_i2(int64_t S, int64_t g) {
 // groups with i2 < i (serial, leader thread of the initialisation)
 __device__ void s4_tables(const Ctx &c) {
     const int64_t S = c.S;
-    const int64_t nb = s4_nblocks(S), nkc = s4_nchunks(S);
+    const int64_t nb = s4_nblocks(S);
     uint64_t acc = 0;
     c.cum[0] = 0;
     for (int64_t b = 0; b < nb; ++b) {
-        int64_t kc0, ng;
-        s4_block(S, b, kc0, ng);
-        acc += (uint64_t)((nkc - kc0) * ng);
+        int64_t nkb, ng;
+        s4_block(S, b, nkb, ng);
+        acc += (uint64_t)(nkb * ng);
         c.cum[b + 1] = acc;
     }
     c.stats[1] = acc;
@@ -1915,14 +1918,35 @@ __device__ void s4_tables(const Ctx &c) {
 }
 
 uint64_t s4_tiles_host(int64_t S) {
-    const int64_t nb = s4_nblocks(S), nkc = s4_nchunks(S);
+    const int64_t nb = s4_nblocks(S);
     uint64_t acc = 0;
     for (int64_t b = 0; b < nb; ++b) {
-        int64_t kc0, ng;
-        s4_block(S, b, kc0, ng);
-        acc += (uint64_t)((nkc - kc0) * ng);
+        int64_t nkb, ng;
+        s4_block(S, b, nkb, ng);
+        acc += (uint64_t)(nkb * ng);
     }
     return acc;
+}
+
+// first record row and row count of tile t
+__device__ inline void s4_tile_rows(const Ctx &c, const uint64_t *__restrict__ tcum, int64_t nb, uint64_t t,
+                                    int64_t &row, int64_t &nrows) {
+    const int64_t S = c.S;
+    int64_t lo = 0, hi = nb - 1;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (tcum[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    int64_t nkb, ng;
+    s4_block(S, lo, nkb, ng);
+    const int64_t grp = (int64_t)(t - tcum[lo]) / nkb;
+    const int64_t i2 = s4_group_i2(S, grp);
+    const int64_t hh = grp - s4_groups_below(i2);
+    const int64_t j0 = lo * S4_JR;
+    const int64_t jlo = j0 > i2 + 1 ? j0 : i2 + 1;
+    const int64_t jhi = (j0 + S4_JR - 1 < S - 2) ? j0 + S4_JR - 1 : S - 2;
+    row = c.r4off[i2] + hh * (S - 2 - i2) + (jlo - i2 - 1);
+    nrows = jhi - jlo + 1;
 }
 
 __global__ void s4_init_kernel(Ctx c) {
@@ -1930,54 +1954,59 @@ __global__ void s4_init_kernel(Ctx c) {
     search_init_body(c, e, e == 0, 4, SUBP, JBLK, 4);
 }
 
-// Grid: x over (row, r) (S4_NR threads per row j = i2 + 1 + row), y over
-// pair groups (strided).  zs = z_j / s_j = e / d_j and z_j^2 = e^2 / d_j with
-// e = b_j - v0 z0 - v1 z1, so a record takes one division and no root.
-__global__ __launch_bounds__(256) void rec4_kernel(Ctx c, double *__restrict__ rec) {
+// One thread per record, over the table in storage order: the row's pair
+// group comes from a search of r4off (the threads of a workgroup share it
+// but for the workgroups that straddle two values of i2).
+// zs = z_j / s_j = e / d_j and z_j^2 = e^2 / d_j with e = b_j - v0 z0 - v1 z1,
+// so a record takes one division and no root.
+__global__ __launch_bounds__(256) void rec4_kernel(Ctx c, double *__restrict__ rec, int64_t nrec) {
     const int64_t S = c.S;
-    const int64_t ex = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int r = (int)(ex % S4_NR);
-    const int64_t row = ex / S4_NR;
-    const int64_t ngr = s4_groups_below(S - 2);  // groups with i2 <= S - 3
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nrec) return;
+    const int r = (int)(e & (S4_NR - 1));
+    const int64_t row = e / S4_NR;
+    // i2: the largest index in [1, S - 3] whose rows start at or before row
+    int64_t lo = 1, hi = S - 3;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (c.r4off[mid] <= row) lo = mid; else hi = mid - 1;
+    }
+    const int64_t i2 = lo;
+    const int64_t nrow = S - 2 - i2;
+    const int64_t loc = row - c.r4off[i2];
+    const int64_t h = loc / nrow;
+    const int64_t j = i2 + 1 + (loc - h * nrow);
+    const int64_t i1 = S4_NR * h + r;
     const int64_t nt = c.Gnt;
     const double *__restrict__ G = c.G;
-    const double cy = c.cyy[0];
-    for (int64_t g = blockIdx.y; g < ngr; g += gridDim.y) {
-        const int64_t i2 = s4_group_i2(S, g);
-        const int64_t j = i2 + 1 + row;
-        if (j > S - 2) continue;
-        const int64_t h = g - s4_groups_below(i2);
-        const int64_t i1 = S4_NR * h + r;
-        double v0 = 0.0, v1 = 0.0, al = 0.0, zs = 0.0, p = __builtin_nan("");
-        if (i1 < i2 && G[gidx(i1, i1, nt, 1, 0)] > RANK_EPS) {
-            const double rr = G[gidx(i1, i2, nt, 1, 0)];
-            const double s2 = G[gidx(i2, i2, nt, 1, 0)] - rr * rr;
-            if (s2 > RANK_EPS) {
-                const double isp = 1.0 / sqrt(s2);
-                const double z0 = c.bhat[i1];
-                const double z1 = (c.bhat[i2] - rr * z0) * isp;
-                const double a0 = G[gidx(i1, j, nt, 1, 0)];
-                const double a1 = (G[gidx(i2, j, nt, 1, 0)] - rr * a0) * isp;
-                const double d = G[gidx(j, j, nt, 1, 0)] - a0 * a0 - a1 * a1;
-                if (d > RANK_EPS) {
-                    const double id = 1.0 / d;
-                    const double e = c.bhat[j] - a0 * z0 - a1 * z1;
-                    v0 = a0;
-                    v1 = a1;
-                    al = id;
-                    zs = e * id;
-                    p = cy - z0 * z0 - z1 * z1 - e * zs;
-                }
+    double v0 = 0.0, v1 = 0.0, al = 0.0, zs = 0.0, p = __builtin_nan("");
+    if (i1 < i2 && G[gidx(i1, i1, nt, 1, 0)] > RANK_EPS) {
+        const double rr = G[gidx(i1, i2, nt, 1, 0)];
+        const double s2 = G[gidx(i2, i2, nt, 1, 0)] - rr * rr;
+        if (s2 > RANK_EPS) {
+            const double isp = 1.0 / sqrt(s2);
+            const double z0 = c.bhat[i1];
+            const double z1 = (c.bhat[i2] - rr * z0) * isp;
+            const double a0 = G[gidx(i1, j, nt, 1, 0)];
+            const double a1 = (G[gidx(i2, j, nt, 1, 0)] - rr * a0) * isp;
+            const double d = G[gidx(j, j, nt, 1, 0)] - a0 * a0 - a1 * a1;
+            if (d > RANK_EPS) {
+                const double id = 1.0 / d;
+                const double ee = c.bhat[j] - a0 * z0 - a1 * z1;
+                v0 = a0;
+                v1 = a1;
+                al = id;
+                zs = ee * id;
+                p = c.cyy[0] - z0 * z0 - z1 * z1 - ee * zs;
             }
         }
-        const int64_t row = c.r4off[i2] + h * (S - 2 - i2) + (j - i2 - 1);
-        double *o = rec + (row * S4_NR + r) * S4_RECW;
-        o[0] = v0;
-        o[1] = v1;
-        o[2] = al;
-        o[3] = zs;
-        o[4] = p;
     }
+    double *o = rec + e * S4_RECW;
+    o[0] = v0;
+    o[1] = v1;
+    o[2] = al;
+    o[3] = zs;
+    o[4] = p;
 }
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S4_WPE))) void search4_kernel(
@@ -2014,8 +2043,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S4_WPE))) v
     const uint64_t U = (uint64_t)gridDim.x / nx * SEARCH_WAVES;
     const uint64_t u0 = (uint64_t)blockIdx.x / nx * SEARCH_WAVES + wave;
     // a wave takes S4_WRUN consecutive tiles (the column chunks of one pair
-    // group and row block share its record rows, which then come from the
-    // scalar cache); runs are dealt round-robin and XCD-aware as tiles are in
+    // group and row block share its record rows, which the later ones find in
+    // L2); runs are dealt round-robin and XCD-aware as tiles are in
     // search3_kernel
     for (uint64_t sx = u0;; sx += U) {
         const uint64_t run = ((sx / S3_XCD_RUN) * nx + xcd) * S3_XCD_RUN + sx % S3_XCD_RUN;
@@ -2028,11 +2057,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S4_WPE))) v
             if (tcum[mid] <= t) lo = mid; else hi = mid - 1;
         }
         const int64_t jb = lo;
-        int64_t kc0, ng;
-        s4_block(S, jb, kc0, ng);
-        const int64_t nkb = s4_nchunks(S) - kc0;
+        int64_t nkb, ng;
+        s4_block(S, jb, nkb, ng);
         const int64_t rem = (int64_t)(t - tcum[jb]);
-        const int64_t kcx = kc0 + rem % nkb;
+        const int64_t kcx = rem % nkb;
         const int64_t grp = uni(rem / nkb);
         const int64_t i2 = uni(s4_group_i2(S, grp));
         const int64_t hh = grp - s4_groups_below(i2);
@@ -2040,11 +2068,34 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S4_WPE))) v
         const int64_t jlo = j0 > i2 + 1 ? j0 : i2 + 1;
         const int64_t jhi = (j0 + S4_JR - 1 < S - 2) ? j0 + S4_JR - 1 : S - 2;
         const int nrow = (int)(jhi - jlo);  // steps 0..nrow (>= 0: i2 < jhi)
-        const int64_t kb = kcx * S4_KC;
-        const int64_t k0 = kb + 2 * lane, k1 = k0 + 1;
+        // the next tile of this wave that starts a new pair group: touch each
+        // 128-byte line of its record rows now, so that its scalar loads find
+        // them in L2
+        double pf = 0.0;
+        {
+            uint64_t tn = ~0ull;
+            if (t + 1 < tend) {
+                if ((rem + 1) % nkb == 0) tn = t + 1;
+            } else {
+                const uint64_t sn = sx + U;
+                const uint64_t rn = ((sn / S3_XCD_RUN) * nx + xcd) * S3_XCD_RUN + sn % S3_XCD_RUN;
+                if (rn * S4_WRUN < ntiles) tn = rn * S4_WRUN;
+            }
+            if (tn != ~0ull) {
+                int64_t prow, pn;
+                s4_tile_rows(c, tcum, nb, tn, prow, pn);
+                const int64_t bytes = pn * S4_ROW * 8;
+                if ((int64_t)lane * 128 < bytes)
+                    pf = rec[(size_t)prow * S4_ROW + (size_t)lane * 16];
+            }
+        }
+        const int64_t kb = j0 + 1 + kcx * S4_KC;
+        const int64_t k0 = kb + lane, k1 = kb + 64 + lane;
         const bool kv0 = k0 < S, kv1 = k1 < S;
-        const int64_t kk = kv0 ? k0 : ((S - 1) & ~(int64_t)1);
-        const bool diag = kb <= jhi;
+        // columns read for lanes past S: any valid one (never passes)
+        const int64_t kk0 = kv0 ? k0 : S - 1, kk1 = kv1 ? k1 : S - 1;
+        const bool diag = kcx == 0;            // k <= j only in chunk 0, first half
+        const bool half = S - kb <= 64;        // no column in the second half
 
         double th = fmin(theta0, theta_load(c.theta_bits));
         th = fmin(th, Ls[KP - 1]);
@@ -2053,11 +2104,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S4_WPE))) v
         // k-dependent part of each pair's solve, for both columns of the lane
         double w0[S4_NR][2], w1[S4_NR][2], dq[S4_NR][2], zq[S4_NR][2];
         {
-            const int64_t kd1 = kv1 ? k1 : kk;
-            const double gd0 = inv_st[kk] > 0.0 ? 1.0 : 0.0;
-            const double gd1 = inv_st[kd1] > 0.0 ? 1.0 : 0.0;
-            const double b0 = c.bhat[kk], b1 = c.bhat[kd1];
-            const double2 w2v = *reinterpret_cast<const double2 *>(Gb + gidx(i2, kk, nt, 1, 0));
+            const double gd0 = inv_st[kk0] > 0.0 ? 1.0 : 0.0;
+            const double gd1 = inv_st[kk1] > 0.0 ? 1.0 : 0.0;
+            const double b0 = c.bhat[kk0], b1 = c.bhat[kk1];
+            const double w2x = Gb[gidx(i2, kk0, nt, 1, 0)], w2y = Gb[gidx(i2, kk1, nt, 1, 0)];
             const double zb2 = c.bhat[i2];
             const bool live2 = inv_st[i2] > 0.0;
 #pragma unroll
@@ -2071,9 +2121,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S4_WPE))) v
                 const double isp = pv ? 1.0 / sqrt(s2) : 0.0;
                 const double z0 = c.bhat[i1];
                 const double z1 = (zb2 - rr * z0) * isp;
-                const double2 w1v = *reinterpret_cast<const double2 *>(Gb + gidx(i1, kk, nt, 1, 0));
-                const double a0 = w1v.x, a1 = w1v.y;
-                const double c0 = (w2v.x - rr * a0) * isp, c1 = (w2v.y - rr * a1) * isp;
+                const double a0 = Gb[gidx(i1, kk0, nt, 1, 0)], a1 = Gb[gidx(i1, kk1, nt, 1, 0)];
+                const double c0 = (w2x - rr * a0) * isp, c1 = (w2y - rr * a1) * isp;
                 w0[r][0] = a0;
                 w0[r][1] = a1;
                 w1[r][0] = c0;
@@ -2086,20 +2135,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S4_WPE))) v
             }
         }
         const char *__restrict__ gtile = reinterpret_cast<const char *>(Gb + (((j0 >> 6) * nt) << 12));
-        const uint32_t voff = (uint32_t)((((kk >> 6) << 12) + (kk & 63) + ((jlo & 63) << 6)) * 8);
+        // byte offsets of (jlo, k) in the 64 x 64 tile row of j0 (rows jlo .. jhi stay in it)
+        const uint32_t voff0 = (uint32_t)((((kk0 >> 6) << 12) + (kk0 & 63) + ((jlo & 63) << 6)) * 8);
+        const uint32_t voff1 = (uint32_t)((((kk1 >> 6) << 12) + (kk1 & 63) + ((jlo & 63) << 6)) * 8);
         // records of row jlo + x are S4_ROW doubles at recj + S4_ROW x (uniform)
         const double *__restrict__ recj =
             rec + (size_t)(c.r4off[i2] + hh * (S - 2 - i2) + (jlo - i2 - 1)) * S4_ROW;
         int nq = 0;
-        auto sweep = [&](auto diagc) {
+        auto sweep = [&](auto diagc, auto halfc) {
             constexpr bool DIAG = decltype(diagc)::value;
+            constexpr bool HALF = decltype(halfc)::value;
             constexpr int JG = S3_JG;
-            double2 ga[JG], gb[JG];
+            double2 ga[JG], gb[JG];  // g(j, k0), g(j, k1)
             auto fetch = [&](double2 (&dst)[JG], int jg) {
 #pragma unroll
                 for (int x = 0; x < JG; ++x) {
                     const uint32_t jr = (uint32_t)(jg + x < nrow ? jg + x : nrow);
-                    dst[x] = *reinterpret_cast<const double2 *>(gtile + (voff + jr * 512u));
+                    dst[x].x = *reinterpret_cast<const double *>(gtile + (voff0 + jr * 512u));
+                    dst[x].y = HALF ? 0.0 : *reinterpret_cast<const double *>(gtile + (voff1 + jr * 512u));
                 }
             };
             // records of one step: two halves of two pairs (10 doubles each),
@@ -2124,7 +2177,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S4_WPE))) v
                         const double z = fma(-x[3], u, zq[r][0]);
                         m0 |= __ballot(z * z >= pi * d);
                     }
-                    {
+                    if (!HALF) {
                         const double u = fma(-x[1], w1[r][1], fma(-x[0], w0[r][1], gv.y));
                         const double d = fma(-x[2], u * u, dq[r][1]);
                         const double z = fma(-x[3], u, zq[r][1]);
@@ -2148,11 +2201,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S4_WPE))) v
                     load_half(ra, jr + 1 <= nrow ? jr + 1 : nrow, 0);
                     __builtin_amdgcn_sched_barrier(0);
                     score_half(rb, src[x], 1, m0, m1);
-                    if (DIAG) {
-                        const int64_t j = jlo + jr;
-                        m0 &= __ballot(k0 > j);
-                        m1 &= __ballot(k1 > j);
-                    }
+                    if (DIAG) m0 &= __ballot(k0 > jlo + jr);  // k1 > j0 + 64 > j
                     if (jr > nrow) m0 = m1 = 0;
                     if (m0 | m1) {
                         if (lane == 0) {
@@ -2174,8 +2223,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S4_WPE))) v
                 if (jg + 2 * JG > nrow) break;
             }
         };
-        if (diag) sweep(std::true_type{});
-        else sweep(std::false_type{});
+        if (diag) {
+            if (half) sweep(std::true_type{}, std::true_type{});
+            else sweep(std::true_type{}, std::false_type{});
+        } else {
+            if (half) sweep(std::false_type{}, std::true_type{});
+            else sweep(std::false_type{}, std::false_type{});
+        }
+        asm volatile("; prefetched %0" ::"v"(pf));  // the load stays (its value is not needed)
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
         __builtin_amdgcn_wave_barrier();
 
@@ -2195,12 +2250,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S4_WPE))) v
             const int64_t j = jlo + jr;
             const unsigned long long fm[2] = {s_q[wave][e][0], s_q[wave][e][1]};
             const double *rp = recj + (size_t)jr * S4_ROW;
-            const double2 gv = *reinterpret_cast<const double2 *>(gtile + (voff + (uint32_t)jr * 512u));
+            const double gv0 = *reinterpret_cast<const double *>(gtile + (voff0 + (uint32_t)jr * 512u));
+            const double gv1 = *reinterpret_cast<const double *>(gtile + (voff1 + (uint32_t)jr * 512u));
             for (int r = 0; r < S4_NR; ++r) {
                 const double *x = rp + r * S4_RECW;
                 const double v0 = x[0], v1 = x[1], al = x[2], zs = x[3], p = x[4];
                 for (int sl = 0; sl < 2; ++sl) {
-                    const double gg = sl ? gv.y : gv.x;
+                    const double gg = sl ? gv1 : gv0;
                     const int64_t k = sl ? k1 : k0;
                     const double u = fma(-v1, pick(w1, r, sl), fma(-v0, pick(w0, r, sl), gg));
                     const double d = fma(-al, u * u, pick(dq, r, sl));
@@ -3244,15 +3300,16 @@ int launch_search(const Ctx &c, const SearchCall &sc, hipStream_t st) {
             case 3: launch_prepass<3>(c, sc, a.L, st, !s3); break;
             default: launch_prepass<4>(c, sc, a.L, st); break;
         }
+        if (s4) {
+            // the pair-group record table (part of the set-up, like rec3 above)
+            const int64_t nrec = s4_rows_below(c.S, c.S - 2) * S4_NR;
+            hipLaunchKernelGGL(rec4_kernel, dim3((unsigned)((nrec + 255) / 256)), dim3(256), 0, st, c, c.rec4, nrec);
+        }
         phase_end(c, SISSO_PHASE_PREPASS, st);
         phase_begin(c, SISSO_PHASE_SEARCH, st);
         const size_t nrec = MT ? (size_t)a.JB * c.TP : (size_t)SEARCH_WG;
         const size_t lds = lds_lists + nrec * RECW * sizeof(double) + (size_t)64 * SUBW * sizeof(double);
         if (s4) {
-            const int64_t ngr = s4_groups_below(c.S - 2);
-            const unsigned bx = (unsigned)(((c.S - 3) * S4_NR + 255) / 256);  // rows j = i2 + 1 .. S - 2
-            const unsigned by = (unsigned)(ngr < 65535 ? ngr : 65535);
-            hipLaunchKernelGGL(rec4_kernel, dim3(bx, by), dim3(256), 0, st, c, c.rec4);
             hipLaunchKernelGGL(search4_kernel, dim3(c.search_wgs), dim3(SEARCH_WG), lds_lists, st, c, a,
                                (const double *)c.rec4, (const uint64_t *)c.cum);
         } else if (s3 && MT) {
