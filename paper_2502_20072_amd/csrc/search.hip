@@ -1183,15 +1183,17 @@ __global__ __launch_bounds__(256) void search_kernel(Ctx c, SearchArgs a) {
 // once per search into a table (rec3_kernel), and the sweep reads the rows
 // of four consecutive i1 for one j with scalar loads: lanes run over the
 // last index k, so a record is the same for every lane and enters the FP64
-// instructions as a scalar operand, at no LDS or vector-memory cost.  Each
-// lane handles two adjacent k (one 16-byte load of G[j][k..k+1] serves
-// 2 x 4 tuples).  A work tile is (group of four i1, S3_JR rows j, S3_KC
-// columns k); tiles are dealt to single waves round-robin, so no wave waits
-// on another.  Per tuple the arithmetic is the same as search_kernel's
+// instructions as a scalar operand, at no LDS or vector-memory cost.  A
+// work tile is (group of four i1, S3_JR rows j from j0, S3_KC columns k from
+// j0 + 1 + S3_KC c); lane l takes k = kb + l and kb + 64 + l (one load of
+// G[j][k] each serves 4 tuples), so only chunk 0 holds tuples with k <= j
+// (in its first half), and a last chunk with at most 64 columns left runs
+// its first half only.  Tiles are dealt to single waves round-robin, so no
+// wave waits on another.  Per tuple the arithmetic is the same as search_kernel's
 // single-task path: u = g - v w', d = d' - alpha u^2, zeta = zeta' - zs u,
 // pass iff zeta^2 >= (p - theta) d.
 constexpr int S3_NR = 4;              // i1 per tile (a group)
-constexpr int S3_KC = 128;            // k per tile: two adjacent per lane
+constexpr int S3_KC = 128;            // k per tile: two per lane, 64 apart
 #ifndef S3_JR
 #define S3_JR 32                      // j rows per tile (divides 64)
 #endif
@@ -1266,39 +1268,38 @@ __global__ __launch_bounds__(PRE_WG) void rec3_kernel(Ctx c, double *__restrict_
 }
 
 // Tiles of j-block jb (j in [S3_JR jb, S3_JR jb + S3_JR) and j <= S - 2):
-// column chunks kc >= kc0 (the chunk reaches past the block's first j) times
-// groups g < ng (the group's first i1 lies below the block's last j).
-__host__ __device__ inline void s3_block(int64_t S, int64_t jb, int64_t &kc0, int64_t &ng) {
+// nkb column chunks (k from j0 + 1 to S - 1) times groups g < ng (the
+// group's first i1 lies below the block's last j).
+__host__ __device__ inline void s3_block(int64_t S, int64_t jb, int64_t &nkb, int64_t &ng) {
     const int64_t j0 = jb * S3_JR;
     int64_t jmax = j0 + S3_JR - 1;
     if (jmax > S - 2) jmax = S - 2;
-    kc0 = (j0 + 1) / S3_KC;
+    nkb = (S - j0 - 1 + S3_KC - 1) / S3_KC;
     ng = jmax >= 1 ? (jmax - 1) / S3_NR + 1 : 0;
 }
 __host__ __device__ inline int64_t s3_nblocks(int64_t S) { return S >= 3 ? (S - 2) / S3_JR + 1 : 0; }
-__host__ __device__ inline int64_t s3_nchunks(int64_t S) { return (S + S3_KC - 1) / S3_KC; }
 
 // tcum[jb] = tiles of the blocks before jb (tcum[nblocks] = all tiles)
 __device__ void s3_tile_table(const Ctx &c) {
-    const int64_t nb = s3_nblocks(c.S), nkc = s3_nchunks(c.S);
+    const int64_t nb = s3_nblocks(c.S);
     uint64_t acc = 0;
     c.cum[0] = 0;
     for (int64_t b = 0; b < nb; ++b) {
-        int64_t kc0, ng;
-        s3_block(c.S, b, kc0, ng);
-        acc += (uint64_t)((nkc - kc0) * ng);
+        int64_t nkb, ng;
+        s3_block(c.S, b, nkb, ng);
+        acc += (uint64_t)(nkb * ng);
         c.cum[b + 1] = acc;
     }
     c.stats[1] = acc;
 }
 
 uint64_t s3_tiles_host(int64_t S) {
-    const int64_t nb = s3_nblocks(S), nkc = s3_nchunks(S);
+    const int64_t nb = s3_nblocks(S);
     uint64_t acc = 0;
     for (int64_t b = 0; b < nb; ++b) {
-        int64_t kc0, ng;
-        s3_block(S, b, kc0, ng);
-        acc += (uint64_t)((nkc - kc0) * ng);
+        int64_t nkb, ng;
+        s3_block(S, b, nkb, ng);
+        acc += (uint64_t)(nkb * ng);
     }
     return acc;
 }
@@ -1389,11 +1390,11 @@ __device__ __forceinline__ unsigned mt_step(const Ctx &c, const SearchArgs &a, c
     const int TP = c.TP, ts = c.tstar[0];
     const double *__restrict__ G1 = c.G1;
     const double *__restrict__ inv_st = c.inv_s + (int64_t)ts * S;
-    const int64_t k0 = kcx * S3_KC + 2 * lane, k1 = k0 + 1;
+    const int64_t kb = j - j % S3_JR + 1 + kcx * S3_KC;  // the tile's first column
+    const int64_t k0 = kb + lane, k1 = kb + 64 + lane;
     const bool kv0 = k0 < S, kv1 = k1 < S;
-    const int64_t kk = kv0 ? k0 : ((S - 1) & ~(int64_t)1);
-    const int64_t kd1 = kv1 ? k1 : kk;
-    const double2 gv = *reinterpret_cast<const double2 *>(G1 + gidx(j, kk, nt, 1, 0));
+    const int64_t kk = kv0 ? k0 : S - 1, kd1 = kv1 ? k1 : S - 1;
+    const double gvx = G1[gidx(j, kk, nt, 1, 0)], gvy = G1[gidx(j, kd1, nt, 1, 0)];
     const double gd0 = inv_st[kk] > 0.0 ? 1.0 : 0.0, gd1 = inv_st[kd1] > 0.0 ? 1.0 : 0.0;
     const double b0 = c.bhat[kk * TP + ts], b1 = c.bhat[kd1 * TP + ts];
     const double *rp = rec + (s3_rowoff(S, g) + j - S3_NR * g - 1) * (S3_NR * 4);
@@ -1403,10 +1404,10 @@ __device__ __forceinline__ unsigned mt_step(const Ctx &c, const SearchArgs &a, c
         const int64_t i1 = S3_NR * g + r, i1c = i1 < S ? i1 : S - 1;
         const double v = rp[4 * r], al = rp[4 * r + 1], zs = rp[4 * r + 2], p = rp[4 * r + 3];
         const double zp = c.bhat[i1c * TP + ts];
-        const double2 wv = *reinterpret_cast<const double2 *>(G1 + gidx(i1c, kk, nt, 1, 0));
+        const double wvx = G1[gidx(i1c, kk, nt, 1, 0)], wvy = G1[gidx(i1c, kd1, nt, 1, 0)];
 #pragma unroll
         for (int sl = 0; sl < 2; ++sl) {
-            const double w = sl ? wv.y : wv.x, gg = sl ? gv.y : gv.x, gd = sl ? gd1 : gd0;
+            const double w = sl ? wvy : wvx, gg = sl ? gvy : gvx, gd = sl ? gd1 : gd0;
             const int64_t k = sl ? k1 : k0;
             const double dq = ((sl ? kv1 : kv0) && gd > RANK_EPS) ? gd - w * w : __builtin_nan("");
             const double zq = (sl ? b1 : b0) - w * zp;
@@ -1486,26 +1487,26 @@ __device__ __forceinline__ void s3_tile(const CtxT &c, const SearchArgs &a, cons
             if (tcum[mid] <= t) lo = mid; else hi = mid - 1;
         }
         const int64_t jb = lo;
-        int64_t kc0, ng;
-        s3_block(S, jb, kc0, ng);
+        int64_t nkb, ng;
+        s3_block(S, jb, nkb, ng);
         // column chunk fastest: the waves of a workgroup usually take chunks
         // of one (block, group) and share its records in the scalar cache;
         // a run of tiles on one XCD covers a few groups over the same chunks
         // of G
-        const int64_t nkb = s3_nchunks(S) - kc0;
         const int64_t rem = (int64_t)(t - tcum[jb]);
-        const int64_t kcx = kc0 + rem % nkb;
+        const int64_t kcx = rem % nkb;
         const int64_t g = rem / nkb;
         const int64_t j0 = jb * S3_JR;
         const int64_t jlo = j0 > S3_NR * g + 1 ? j0 : S3_NR * g + 1;
         const int64_t jhi = (j0 + S3_JR - 1 < S - 2) ? j0 + S3_JR - 1 : S - 2;
         const int nrow = (int)(jhi - jlo);  // steps 0..nrow
-        const int64_t kb = kcx * S3_KC;
-        const int64_t k0 = kb + 2 * lane, k1 = k0 + 1;
+        const int64_t kb = j0 + 1 + kcx * S3_KC;
+        const int64_t k0 = kb + lane, k1 = kb + 64 + lane;
         const bool kv0 = k0 < S, kv1 = k1 < S;
-        // even column < S: the pair (kk, kk + 1) lies inside the padded tile row
-        const int64_t kk = kv0 ? k0 : ((S - 1) & ~(int64_t)1);
-        const bool diag = kb <= jhi;
+        // columns read for lanes past S: any valid one (never passes)
+        const int64_t kk0 = kv0 ? k0 : S - 1, kk1 = kv1 ? k1 : S - 1;
+        const bool diag = kcx == 0;            // k <= j only in chunk 0, first half
+        const bool half = S - kb <= 64;        // no column in the second half
 
         double th = fmin(theta0, theta_load(c.theta_bits));
         th = fmin(th, Ls[KP - 1]);
@@ -1516,16 +1517,15 @@ __device__ __forceinline__ void s3_tile(const CtxT &c, const SearchArgs &a, cons
         {
             // G[k][k] is 1 for a live column and 0 for a constant one; the
             // contiguous 1/|x - mean| row says which (0 = constant)
-            const int64_t kd1 = kv1 ? k1 : kk;
-            const double gd0 = inv_st[kk] > 0.0 ? 1.0 : 0.0;
-            const double gd1 = inv_st[kd1] > 0.0 ? 1.0 : 0.0;
-            const double b0 = c.bhat[kk * TP + ts], b1 = c.bhat[kd1 * TP + ts];
+            const double gd0 = inv_st[kk0] > 0.0 ? 1.0 : 0.0;
+            const double gd1 = inv_st[kk1] > 0.0 ? 1.0 : 0.0;
+            const double b0 = c.bhat[kk0 * TP + ts], b1 = c.bhat[kk1 * TP + ts];
 #pragma unroll
             for (int r = 0; r < S3_NR; ++r) {
                 int64_t i1 = S3_NR * g + r;
                 if (i1 > S - 1) i1 = S - 1;
                 const double zp = c.bhat[i1 * TP + ts];
-                const double2 wv = *reinterpret_cast<const double2 *>(Gb + gidx(i1, kk, nt, 1, 0));
+                const double2 wv = {Gb[gidx(i1, kk0, nt, 1, 0)], Gb[gidx(i1, kk1, nt, 1, 0)]};
                 w[r][0] = wv.x;
                 w[r][1] = wv.y;
                 // a lane past S or on a constant column never passes
@@ -1535,25 +1535,28 @@ __device__ __forceinline__ void s3_tile(const CtxT &c, const SearchArgs &a, cons
                 zq[r][1] = b1 - wv.y * zp;
             }
         }
-        // G[j][kk..kk+1] for the block's rows: j >> 6 is the same for the whole
-        // block (S3_JR divides 64), so one uniform tile-row base plus a 32-bit
-        // per-lane byte offset (column part + row j & 63) addresses every step
+        // G[j][k] for the block's rows: j >> 6 is the same for the whole block
+        // (S3_JR divides 64), so one uniform tile-row base plus 32-bit per-lane
+        // byte offsets (column part + row j & 63) address every step
         const char *__restrict__ gtile =
             reinterpret_cast<const char *>(Gb + (((j0 >> 6) * nt) << 12));
-        const uint32_t voff = (uint32_t)((((kk >> 6) << 12) + (kk & 63) + ((jlo & 63) << 6)) * 8);
+        const uint32_t voff0 = (uint32_t)((((kk0 >> 6) << 12) + (kk0 & 63) + ((jlo & 63) << 6)) * 8);
+        const uint32_t voff1 = (uint32_t)((((kk1 >> 6) << 12) + (kk1 & 63) + ((jlo & 63) << 6)) * 8);
         // records of row jlo + x are 128 bytes at recj + 128 x (uniform)
         const char *__restrict__ recj =
             reinterpret_cast<const char *>(rec + (size_t)(s3_rowoff(S, g) + jlo - S3_NR * g - 1) * (S3_NR * 4));
         int nq = 0;
-        auto sweep = [&](auto diagc) {
+        auto sweep = [&](auto diagc, auto halfc) {
             constexpr bool DIAG = decltype(diagc)::value;
+            constexpr bool HALF = decltype(halfc)::value;
             constexpr int JG = S3_JG;
-            double2 ga[JG], gb[JG];
+            double2 ga[JG], gb[JG];  // g(j, k0), g(j, k1)
             auto fetch = [&](double2 (&dst)[JG], int jg) {
 #pragma unroll
                 for (int x = 0; x < JG; ++x) {
                     const uint32_t jr = (uint32_t)(jg + x < nrow ? jg + x : nrow);
-                    dst[x] = *reinterpret_cast<const double2 *>(gtile + (voff + jr * 512u));
+                    dst[x].x = *reinterpret_cast<const double *>(gtile + (voff0 + jr * 512u));
+                    dst[x].y = HALF ? 0.0 : *reinterpret_cast<const double *>(gtile + (voff1 + jr * 512u));
                 }
             };
             // records of one step are two halves of 64 bytes (i1 = 4g, 4g+1 and
@@ -1577,7 +1580,7 @@ __device__ __forceinline__ void s3_tile(const CtxT &c, const SearchArgs &a, cons
                         const double z = fma(-rv[4 * rr + 2], u, zq[r][0]);
                         m0 |= __ballot(z * z >= pi * d);
                     }
-                    {
+                    if (!HALF) {
                         const double u = fma(-rv[4 * rr], w[r][1], gv.y);
                         const double d = fma(-rv[4 * rr + 1], u * u, dq[r][1]);
                         const double z = fma(-rv[4 * rr + 2], u, zq[r][1]);
@@ -1601,11 +1604,7 @@ __device__ __forceinline__ void s3_tile(const CtxT &c, const SearchArgs &a, cons
                     load_half(ra, jr + 1 <= nrow ? jr + 1 : nrow, 0);
                     __builtin_amdgcn_sched_barrier(0);
                     score_half(rb, src[x], 1, m0, m1);
-                    if (DIAG) {
-                        const int64_t j = jlo + jr;
-                        m0 &= __ballot(k0 > j);
-                        m1 &= __ballot(k1 > j);
-                    }
+                    if (DIAG) m0 &= __ballot(k0 > jlo + jr);  // k1 > j0 + 64 > j
                     if (jr > nrow) m0 = m1 = 0;
                     if (m0 | m1) {
                         if (lane == 0) {
@@ -1627,8 +1626,13 @@ __device__ __forceinline__ void s3_tile(const CtxT &c, const SearchArgs &a, cons
                 if (jg + 2 * JG > nrow) break;
             }
         };
-        if (diag) sweep(std::true_type{});
-        else sweep(std::false_type{});
+        if (diag) {
+            if (half) sweep(std::true_type{}, std::true_type{});
+            else sweep(std::true_type{}, std::false_type{});
+        } else {
+            if (half) sweep(std::false_type{}, std::true_type{});
+            else sweep(std::false_type{}, std::false_type{});
+        }
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
         __builtin_amdgcn_wave_barrier();
 
@@ -1663,7 +1667,8 @@ __device__ __forceinline__ void s3_tile(const CtxT &c, const SearchArgs &a, cons
                 continue;
             }
             const double *rp = reinterpret_cast<const double *>(recj + (size_t)jr * 128);
-            const double2 gv = *reinterpret_cast<const double2 *>(gtile + (voff + (uint32_t)jr * 512u));
+            const double2 gv = {*reinterpret_cast<const double *>(gtile + (voff0 + (uint32_t)jr * 512u)),
+                                *reinterpret_cast<const double *>(gtile + (voff1 + (uint32_t)jr * 512u))};
             // (r, sl) are wave-uniform here: pick the k-data by selects, so
             // the arrays stay in registers (an indexed read would move them to
             // scratch memory, stored on every tile)
