@@ -1195,7 +1195,7 @@ __global__ __launch_bounds__(256) void search_kernel(Ctx c, SearchArgs a) {
 constexpr int S3_NR = 4;              // i1 per tile (a group)
 constexpr int S3_KC = 128;            // k per tile: two per lane, 64 apart
 #ifndef S3_JR
-#define S3_JR 32                      // j rows per tile (divides 64)
+#define S3_JR 64                      // j rows per tile (divides 64)
 #endif
 #ifndef S3_JG
 #define S3_JG 2                       // G rows per prefetch group (two groups in flight)
