@@ -129,8 +129,9 @@ def main() -> int:
     ap.add_argument("--workload", default="plain_s1000_d3")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--precision", choices=("fp64", "bf16", "fp16"), default="fp64",
-                    help="Gram precision form (the search and the re-score are FP64 either way)")
+    ap.add_argument("--precision", choices=("fp64", "bf16", "fp16", "fp32"), default="fp64",
+                    help="precision form: bf16/fp16 slice the Gram (FP64 search), fp32 runs the "
+                         "per-tuple solves in FP32 (FP64 Gram); the re-score is FP64 in every form")
     ap.add_argument("--tune-cache", default=os.environ.get("SISSO_AUTOTUNE_CACHE"),
                     help="JSON cache of the search-grid autotuner (default: tune every run)")
     ap.add_argument("--form", choices=("exhaustive", "learned"), default="exhaustive",
@@ -172,7 +173,8 @@ def main() -> int:
     p = make_config(args.workload)
     if args.form == "learned":
         return bench_learned(args, p)
-    prec = {"fp64": B.SISSO_PREC_FP64, "bf16": B.SISSO_PREC_BF16_COMP, "fp16": B.SISSO_PREC_FP16_COMP}[args.precision]
+    prec = {"fp64": B.SISSO_PREC_FP64, "bf16": B.SISSO_PREC_BF16_COMP, "fp16": B.SISSO_PREC_FP16_COMP,
+            "fp32": B.SISSO_PREC_FP32_SOLVE}[args.precision]
     res = bench_exhaustive(args, p, args.workload, prec, args.steps, args.warmup, args.search_grid)
     res = {"metric": METRIC, **res}
     if args.chosen_form and args.workload != args.chosen_form:
@@ -285,13 +287,20 @@ def bench_exhaustive(args, p, name: str, prec: int, steps: int, warmup: int, sea
             acc[ph] += ms[ph] / steps
     B.sisso_l0_profile(s.handle, False)
     search_s = acc["search"] * 1e-3
-    flop, pruned = performed_flop(D, p.T, ntup)
+    f32 = prec == B.SISSO_PREC_FP32_SOLVE
+    # the FP32 form runs the general kernel for every D and (with a plain
+    # sweep, no filter task) solves every tuple in every task
+    flop, pruned = (ALG_FLOP[D] * p.T * ntup, False) if f32 else performed_flop(D, p.T, ntup)
     achieved = flop / search_s
-    kname = {3: "search3_kernel", 4: "search4_kernel" if p.T == 1 else "search_kernel"}.get(D, "search_kernel")
+    kname = "search_kernel" if f32 else {3: "search3_kernel",
+                                         4: "search4_kernel" if p.T == 1 else "search_kernel"}.get(D, "search_kernel")
     roofline = dict(bound="alu", kernel=kname, achieved=achieved / 1e12, peak=FP64_PEAK / 1e12,
                     unit="TFLOP/s", frac=achieved / FP64_PEAK, traffic=measured_traffic(kname, name),
                     flop_per_tuple=flop / ntup, issued_flop_per_tuple=issued_flop_per_tuple(D, p.T),
                     search_ms=acc["search"], search_tuples_per_s=ntup / search_s)
+    if f32:
+        roofline["note"] = ("FP32 solves without packed FP32 instructions (the build disables them): "
+                            "the vector FP32 rate equals the FP64 one, 256 CU x 64 lanes x 2 x 2.4 GHz")
     if pruned:
         roofline["pruned"] = ("several tasks at D=3: the sweep solves every tuple in the task of largest "
                               "|y_t - mean|^2 only (an exact lower bound of the sum); the survivors' "
@@ -306,14 +315,16 @@ def bench_exhaustive(args, p, name: str, prec: int, steps: int, warmup: int, sea
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32 (solves; f64 Gram and re-score)" if f32 else "f64",
         "data": "synthetic",
         "config": {"workload": name, "n": p.n, "S": p.S, "T": p.T, "D": D, "k": k,
                    "tuples": ntup, "form": {B.SISSO_PREC_FP64: "plain FP64",
                                             B.SISSO_PREC_BF16_COMP: "precision form (Gram from three BF16 slices, "
                                                                     "FP64 search and re-score)",
                                             B.SISSO_PREC_FP16_COMP: "precision form (Gram from two FP16 slices, "
-                                                                    "FP64 search and re-score)"}[prec],
+                                                                    "FP64 search and re-score)",
+                                            B.SISSO_PREC_FP32_SOLVE: "FP32 per-tuple solves (FP64 Gram, "
+                                                                     "FP64 re-score)"}[prec],
                    "search_grid": grid},
         "topk_matches_oracle": matches,
         "oracle_check": note,

@@ -65,7 +65,20 @@ enum {
      * the FP32 chunk sums round (they are not exact as in the BF16 form);
      * the FP64 accumulation of the chunk sums compensates across chunks.
      * Gram error ~4x that of the BF16 form, reported the same way. */
-    SISSO_PREC_FP16_COMP = 2
+    SISSO_PREC_FP16_COMP = 2,
+    /* FP32 per-tuple solve (the precision option of section
+     * "l0-regularization"): the Gram is the FP64 one; the search's solves --
+     * prefix factors, records, the incremental last-index terms, the filter
+     * and the candidate SSEs -- run in FP32 from the FP64 correlations
+     * rounded to FP32, and the 2 (k + 16) best candidates by FP32 SSE are
+     * re-scored exactly in FP64 from F, so the returned SSEs are the FP64
+     * ones.  FP32 resolves pivot ratios only down to ~1e-5 (below that a
+     * tuple counts as rank deficient here, against 1e-10 in FP64), and the
+     * filter bound is widened by 1e-5 sum_t c_t.  sisso_l0_precision_report's
+     * out[2] gives the FP32 SSEs' error over the returned tuples.  Runs the
+     * general search kernels for every D >= 2 (not the FP64 record-table
+     * sweeps); D = 1 is solved in FP64. */
+    SISSO_PREC_FP32_SOLVE = 3
 };
 
 #define SISSO_MAX_D 4      /* largest descriptor dimension compiled in */

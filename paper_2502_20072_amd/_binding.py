@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libsisso_l0.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "sisso_l0.h")
 
 SISSO_OK, SISSO_EINVAL, SISSO_ESTATE, SISSO_ENOMEM, SISSO_EDEVICE, SISSO_ENOTSUP = 0, -1, -2, -3, -4, -5
-SISSO_PREC_FP64, SISSO_PREC_BF16_COMP, SISSO_PREC_FP16_COMP = 0, 1, 2
+SISSO_PREC_FP64, SISSO_PREC_BF16_COMP, SISSO_PREC_FP16_COMP, SISSO_PREC_FP32_SOLVE = 0, 1, 2, 3
 
 
 def _header_int(name: str) -> int:

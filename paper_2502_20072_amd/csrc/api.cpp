@@ -52,13 +52,15 @@ static int precision_slices(int32_t precision) {
         case SISSO_PREC_FP64: return 0;
         case SISSO_PREC_BF16_COMP: return 3;
         case SISSO_PREC_FP16_COMP: return 2;
+        case SISSO_PREC_FP32_SOLVE: return 0;
         default: return -1;
     }
 }
 
-static Layout compute_layout(int64_t n_total, int64_t S, int T, int D_max, int k_max, int lp_ns) {
+static Layout compute_layout(int64_t n_total, int64_t S, int T, int D_max, int k_max, int lp_ns, bool fp32) {
     Layout L{};
     L.lp_ns = lp_ns > 0 ? lp_ns : 0;
+    L.fp32 = fp32 ? 1 : 0;
     // chunks of LP_XC samples per task; bounded without reading the offsets
     L.lp_nchunk = L.lp_ns ? (int)((n_total + LP_XC - 1) / LP_XC + T) : 0;
     L.TP = next_pow2(T);
@@ -93,10 +95,10 @@ static Layout compute_layout(int64_t n_total, int64_t S, int T, int D_max, int k
     }
     L.nsplit = (int)ns;
     // candidates re-scored exactly: k + 16 leaves a margin for FP64
-    // normal-equation rounding at the k-th position; the precision form ranks
-    // by SSEs from an approximate Gram (relative error ~1e-6..1e-5), so it
-    // keeps twice as many candidates for the exact re-score
-    L.KP = next_pow2(L.lp_ns > 0 ? 2 * (k_max + 16) : k_max + 16);
+    // normal-equation rounding at the k-th position; the precision forms rank
+    // by SSEs from an approximate Gram (relative error ~1e-6..1e-5) or from
+    // FP32 solves, so they keep twice as many candidates for the exact re-score
+    L.KP = next_pow2((L.lp_ns > 0 || fp32) ? 2 * (k_max + 16) : k_max + 16);
     if (L.KP > KP_MAX) L.KP = KP_MAX;
     if (L.KP < 64) L.KP = 64;
     L.search_wgs = SEARCH_WGS_DEFAULT;
@@ -134,7 +136,7 @@ static Layout compute_layout(int64_t n_total, int64_t S, int T, int D_max, int k
     {
         const int64_t ng3 = S >= 3 ? (S - 3) / 4 + 1 : 0;
         const int64_t rows3 = ng3 * (S - 2) - 4 * (ng3 * (ng3 - 1) / 2);
-        L.rec3_bytes = (D_max >= 3 && S >= 3) ? (size_t)rows3 * 16 * d : 0;
+        L.rec3_bytes = (D_max >= 3 && S >= 3 && !fp32) ? (size_t)rows3 * 16 * d : 0;
     }
     L.rec3 = take(L.rec3_bytes);
     // D = 4, one task: a record row per (pair group, j); kept only while the
@@ -142,7 +144,7 @@ static Layout compute_layout(int64_t n_total, int64_t S, int T, int D_max, int k
     {
         const int64_t rows4 = S >= 4 ? s4_rows_below(S, S - 2) : 0;
         const size_t b4 = (size_t)rows4 * S4_ROW * d;
-        L.rec4_bytes = (D_max >= 4 && T == 1 && S >= 4 && b4 <= S4_TABLE_MAX && s4_tiles_host(S) < (1ull << 31)) ? b4 : 0;
+        L.rec4_bytes = (D_max >= 4 && T == 1 && S >= 4 && !fp32 && b4 <= S4_TABLE_MAX && s4_tiles_host(S) < (1ull << 31)) ? b4 : 0;
     }
     L.rec4 = take(L.rec4_bytes);
     L.r4off = take(L.rec4_bytes ? (size_t)(S + 1) * sizeof(int64_t) : 0);
@@ -187,7 +189,8 @@ extern "C" size_t sisso_l0_workspace_bytes(const sisso_l0_desc *d) {
     if (!shape_ok(d)) return 0;
     const int ns = precision_slices(d->precision);
     if (ns < 0) return 0;
-    return compute_layout(d->n_total, d->S, d->T, d->D_max, d->k_max, ns).total + 256;
+    return compute_layout(d->n_total, d->S, d->T, d->D_max, d->k_max, ns, d->precision == SISSO_PREC_FP32_SOLVE).total +
+           256;
 }
 
 static void carve(sisso_l0 *h) {
@@ -217,6 +220,7 @@ static void carve(sisso_l0 *h) {
     c.lp_slices = (__bf16 *)(base + L.lp_slices);
     c.err_bits = (unsigned long long *)(base + L.stat_bits);
     c.lp_ns = L.lp_ns;
+    c.fp32 = L.fp32;
     char *p = base + L.pre;
     c.theta_bits = (unsigned long long *)p;
     c.work_counter = (unsigned int *)(p + 8);
@@ -290,7 +294,8 @@ extern "C" int32_t sisso_l0_create(const sisso_l0_desc *d, sisso_l0 **out) {
     h->desc = *d;
     h->offsets.assign(o, o + d->T + 1);
     h->desc.task_offsets = h->offsets.data();
-    h->lay = compute_layout(d->n_total, d->S, d->T, d->D_max, d->k_max, precision_slices(d->precision));
+    h->lay = compute_layout(d->n_total, d->S, d->T, d->D_max, d->k_max, precision_slices(d->precision),
+                            d->precision == SISSO_PREC_FP32_SOLVE);
     h->stream = (hipStream_t)d->stream;
     carve(h);
     if (hipHostMalloc((void **)&h->stage, h->lay.res_bytes, hipHostMallocDefault) != hipSuccess) {

@@ -11,6 +11,7 @@ namespace sl0 {
 
 constexpr int WAVE = 64;               // CDNA wavefront width
 constexpr double RANK_EPS = 1e-10;     // pivot ratio at or below which a tuple is rank-deficient
+constexpr double RANK_EPS_F32 = 1e-5;  // the same for the FP32 solve form (a few hundred units of 2^-23)
 constexpr int GRAM_TILE = 128;         // Gram output tile (rows = cols)
 #ifndef GRAM_KC_SAMPLES
 #define GRAM_KC_SAMPLES 16
@@ -266,6 +267,7 @@ struct Layout {
     int nwaves;        // persistent search waves
     int search_wgs;    // persistent search workgroups
     int lp_ns;         // precision form: slices per value (0 = FP64 Gram)
+    int fp32;          // FP32 solve form (FP64 Gram, per-tuple solves in FP32)
     int lp_nchunk;     // precision form: chunks over all tasks
 };
 

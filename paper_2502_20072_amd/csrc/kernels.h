@@ -58,6 +58,7 @@ struct Ctx {
     double *res_coef;                // [k_max][T][D_max+1]
     int nsplit, KP, nwaves, search_wgs, D_max, k_max;
     int lp_ns, lp_nchunk;            // precision form: slices per value (0 = FP64), chunks
+    int fp32;                        // FP32 solve form: the sweep's per-tuple solves in FP32
     // host-side: start/stop events per phase when profiling is on (else null)
     hipEvent_t *ev;
 };

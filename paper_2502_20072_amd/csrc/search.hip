@@ -47,6 +47,7 @@ namespace sl0 {
 constexpr int MAXD = SISSO_MAX_D;
 constexpr double INF = __builtin_huge_val();
 constexpr double THETA_SLACK = 1e-9;  // relative slack of the filter bound
+constexpr double THETA_SLACK_F32 = 1e-5;  // FP32 solve form: absolute slack, in units of sum_t c_t
 #ifndef SEARCH_JG
 #define SEARCH_JG 8  // G rows per prefetch group (two groups in flight)
 #endif
@@ -83,6 +84,26 @@ __device__ inline double dpp_f64(double v) {
     const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, true);
     return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
+
+// the same lane permutation for the FP32 form's sums
+template <int CTRL>
+__device__ inline float dpp_r(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL>
+__device__ inline double dpp_r(double v) { return dpp_f64<CTRL>(v); }
+__device__ inline float rcp_r(float d) {
+    const float r = __builtin_amdgcn_rcpf(d);
+    return fmaf(r, fmaf(-d, r, 1.0f), r);
+}
+__device__ inline double rcp_r(double d) {
+    const double r = __builtin_amdgcn_rcp(d);
+    return fma(r, fma(-d, r, 1.0), r);
+}
+// pivot ratio at or below which the solve of type R calls a tuple rank
+// deficient: FP32 resolves 1 - |w|^2 only to a few units of 2^-23
+template <typename R>
+__device__ constexpr R rank_eps_r() { return sizeof(R) == 8 ? (R)RANK_EPS : (R)RANK_EPS_F32; }
 
 __device__ inline int next_pow2_dev(int x) {
     int p = 1;
@@ -664,28 +685,28 @@ struct SearchArgs {
 //   w' = R_{P'}^{-1} G[P', kc],  d' = 1 - |w'|^2,  zeta' = b_kc - w'.z'
 // (sub-prefix factors read from LDS).  One set per sub-prefix (one task) or
 // for the lane's task (many tasks).
-template <int D, int NR, bool MT>
-__device__ inline void hoist_k(const Ctx &c, const double *subf, const int32_t *sub, int64_t kc, int myt,
-                               double (&wq)[NR][(D - 2) > 0 ? (D - 2) : 1], double (&dq)[NR], double (&zq)[NR]) {
+template <int D, int NR, bool MT, typename R>
+__device__ inline void hoist_k(const Ctx &c, const R *subf, const int32_t *sub, int64_t kc, int myt,
+                               R (&wq)[NR][(D - 2) > 0 ? (D - 2) : 1], R (&dq)[NR], R (&zq)[NR]) {
     constexpr int q = D - 2;
     constexpr int QA = q > 0 ? q : 1;
     constexpr int SUBW = QA * QA + QA + 2;
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         const int sid = MT ? myt : r;
-        const double *f = subf + sid * SUBW;
+        const R *f = subf + sid * SUBW;
         const int tt = MT ? myt : 0;
-        double g[QA];
+        R g[QA];
 #pragma unroll
         for (int m = 0; m < q; ++m) {
             const int32_t pm = sub[(MT ? 0 : r) * QA + m];
-            g[m] = (pm >= 0 && tt < c.T) ? Gat(c, pm, kc, tt) : 0.0;
+            g[m] = (pm >= 0 && tt < c.T) ? (R)Gat(c, pm, kc, tt) : (R)0;
         }
-        double dd = (tt < c.T) ? Gat(c, kc, kc, tt) : 1.0;
-        double zz = (tt < c.T) ? c.bhat[kc * c.TP + tt] : 0.0;
+        R dd = (tt < c.T) ? (R)Gat(c, kc, kc, tt) : (R)1;
+        R zz = (tt < c.T) ? (R)c.bhat[kc * c.TP + tt] : (R)0;
 #pragma unroll
         for (int m = 0; m < q; ++m) {
-            double s = 0.0;
+            R s = 0;
 #pragma unroll
             for (int l = 0; l <= m; ++l) s += f[m * QA + l] * g[l];
             wq[r][m] = s;
@@ -702,9 +723,9 @@ __device__ inline void hoist_k(const Ctx &c, const double *subf, const int32_t *
 // with a true division, applies the rank test and the current bound, and
 // inserts the survivors into the wave's list.  Kept out of line so the fast
 // loop's registers are not shaped by it.  Returns the wave's published bound.
-template <int D, int NR, bool MT>
+template <int D, int NR, bool MT, typename R>
 __device__ inline double slow_path(const Ctx &c, const SearchArgs &a, double *Ls, uint64_t *Lr,
-                                         const double *recs, const double *subf, const int32_t *sub,
+                                         const R *recs, const R *subf, const int32_t *sub,
                                          const unsigned long long *smask, int64_t j, int jj, int64_t k,
                                          bool kin, bool flagged, int myt, int TL, double theta_f,
                                          double theta_pub, unsigned &offered) {
@@ -714,27 +735,27 @@ __device__ inline double slow_path(const Ctx &c, const SearchArgs &a, double *Ls
     const int KP = a.KP;
     const int lane = threadIdx.x & 63;
     const int64_t kc = kin ? k : c.S - 1;
-    double wq[NR][QA], dq[NR], zq[NR];
-    hoist_k<D, NR, MT>(c, subf, sub, kc, myt, wq, dq, zq);
+    R wq[NR][QA], dq[NR], zq[NR];
+    hoist_k<D, NR, MT, R>(c, subf, sub, kc, myt, wq, dq, zq);
     const bool lane_ok = kin && (k > j) && (MT || flagged);
     for (int r = 0; r < NR; ++r) {
         if (!MT && !((smask[r] >> jj) & 1ull)) continue;
-        const double *rr = MT ? recs + (jj * TL + myt) * RECW : recs + (jj * NR + r) * RECW;
-        const double g = Gat(c, j, kc, MT ? myt : 0);
-        double u = g;
+        const R *rr = MT ? recs + (jj * TL + myt) * RECW : recs + (jj * NR + r) * RECW;
+        const R g = (R)Gat(c, j, kc, MT ? myt : 0);
+        R u = g;
         for (int x = 0; x < q; ++x) u = fma(-rr[x], wq[r][x], u);
-        const double d = fma(-rr[q], u * u, dq[r]);
-        const double z = fma(-rr[q + 1], u, zq[r]);
+        const R d = fma(-rr[q], u * u, dq[r]);
+        const R z = fma(-rr[q + 1], u, zq[r]);
         double es;
         bool pass;
         if (MT) {
-            double ex = 0.0;
-            if (myt < c.T) ex = (d > RANK_EPS) ? rr[q + 3] - z * z / d : INF;
-            es = ex;
-            for (int o = 1; o < TL; o <<= 1) es += __shfl_xor(es, o);
+            R ex = 0;
+            if (myt < c.T) ex = (d > rank_eps_r<R>()) ? rr[q + 3] - z * z / d : (R)INF;
+            for (int o = 1; o < TL; o <<= 1) ex += __shfl_xor(ex, o);
+            es = (double)ex;
             pass = (myt == 0);
         } else {
-            es = (d > RANK_EPS) ? rr[q + 3] - z * z / d : INF;
+            es = (d > rank_eps_r<R>()) ? (double)(rr[q + 3] - z * z / d) : INF;
             pass = true;
         }
         const double thc = fmin(theta_f, Ls[KP - 1]);
@@ -769,11 +790,11 @@ __device__ inline double slow_path(const Ctx &c, const SearchArgs &a, double *Ls
     return theta_pub;
 }
 
-template <int D, bool MT>
+template <int D, bool MT, typename R>
 __global__ __launch_bounds__(256) void search_kernel(Ctx c, SearchArgs a) {
     constexpr int q = D - 2;
     constexpr int QA = q > 0 ? q : 1;               // array extent
-    constexpr int RECW = q + 4;                      // doubles per record
+    constexpr int RECW = q + 4;                      // values per record
     constexpr int SUBW = QA * QA + QA + 2;           // Linv (QA x QA), z', p', valid
     constexpr int NR = MT ? 1 : SUBP;                // sub-prefixes per item
 
@@ -786,8 +807,8 @@ __global__ __launch_bounds__(256) void search_kernel(Ctx c, SearchArgs a) {
     // LDS carve: per-wave lists, records [256][RECW], sub-prefix factors
     double *Ls = smem + (size_t)wave * KP * 2;
     uint64_t *Lr = reinterpret_cast<uint64_t *>(Ls + KP);
-    double *recs = smem + (size_t)SEARCH_WAVES * KP * 2;
-    double *subf = recs + (MT ? a.JB * a.TL : SEARCH_WG) * RECW;  // [64][SUBW] (per r, or per task)
+    R *recs = reinterpret_cast<R *>(smem + (size_t)SEARCH_WAVES * KP * 2);
+    R *subf = recs + (MT ? a.JB * a.TL : SEARCH_WG) * RECW;  // [64][SUBW] (per r, or per task)
     __shared__ int32_t s_sub[SUBP][QA];                // sub-prefix indices per r
     __shared__ int s_iq[SUBP];                         // last sub-prefix index (or -1)
     __shared__ unsigned long long s_mask[SUBP > 64 ? SUBP : 64];  // record validity per r (ST) / per jj (MT)
@@ -803,6 +824,12 @@ __global__ __launch_bounds__(256) void search_kernel(Ctx c, SearchArgs a) {
     double theta_pub = INF;  // last value this wave published
     unsigned offered = 0;    // tuples offered to the list (diagnostics; one atomic per wave)
     const double theta0 = theta0_from_prepass(c, a.L, KP);
+    // the FP32 form's filter bound is widened by an absolute margin (a
+    // multiple of the FP32 rounding of SSEs of size up to c)
+    double ctot = 0.0;
+    if (sizeof(R) < 8)
+        for (int t = 0; t < c.T; ++t) ctot += c.cyy[t];
+    const double abs_slack = sizeof(R) < 8 ? THETA_SLACK_F32 * ctot : 0.0;
 
     const int TL = MT ? a.TL : 1;         // lanes per last index
     const int KL = 64 / TL;               // last indices per wave chunk
@@ -823,7 +850,8 @@ __global__ __launch_bounds__(256) void search_kernel(Ctx c, SearchArgs a) {
         const uint64_t item = uni(s_item);
         if (item >= nitems) break;
         const double theta_item = uni(s_theta);
-        const double theta_f = theta_item < INF ? theta_item * (1.0 + THETA_SLACK) : INF;
+        const double theta_f = theta_item < INF ? theta_item * (1.0 + THETA_SLACK) + abs_slack : INF;
+        const R theta_r = (R)theta_f;
 
         // item -> (j-block, sub-prefix group) by bisection on the cumulative table
         int64_t lo = 0, hi = (c.S - 1 + JB - 1) / JB - 1;
@@ -858,35 +886,35 @@ __global__ __launch_bounds__(256) void search_kernel(Ctx c, SearchArgs a) {
                 if (q > 0) colex_unrank_small(sr, q, Nj - 1, P);
             }
             // sub-prefix factorisation (normalised: unit diagonal)
-            double Li[QA][QA], zp[QA], pp = 0.0;
+            R Li[QA][QA], zp[QA], pp = 0;
             bool pvalid = rvalid && t < c.T;
             if (pvalid) {
-                pp = c.cyy[t];
-                double Lf[QA][QA];
+                pp = (R)c.cyy[t];
+                R Lf[QA][QA];
                 for (int m = 0; m < q; ++m) {
                     for (int jx = 0; jx < m; ++jx) {
-                        double s = Gat(c, P[m], P[jx], t);
+                        R s = (R)Gat(c, P[m], P[jx], t);
                         for (int l = 0; l < jx; ++l) s -= Lf[m][l] * Lf[jx][l];
                         Lf[m][jx] = s / Lf[jx][jx];
                     }
-                    double d = Gat(c, P[m], P[m], t);
+                    R d = (R)Gat(c, P[m], P[m], t);
                     for (int l = 0; l < m; ++l) d -= Lf[m][l] * Lf[m][l];
-                    if (!(d > RANK_EPS)) pvalid = false;
-                    Lf[m][m] = sqrt(fmax(d, 0.0));
+                    if (!(d > rank_eps_r<R>())) pvalid = false;
+                    Lf[m][m] = sqrt(fmax(d, (R)0));
                 }
                 if (pvalid) {
                     // Li = Lf^{-1} (lower), z' = Li b_P', p' = c - |z'|^2
                     for (int m = 0; m < q; ++m) {
                         for (int jx = 0; jx <= m; ++jx) {
-                            double s = (m == jx) ? 1.0 : 0.0;
+                            R s = (m == jx) ? (R)1 : (R)0;
                             for (int l = jx; l < m; ++l) s -= Lf[m][l] * Li[l][jx];
                             Li[m][jx] = s / Lf[m][m];
                         }
-                        for (int jx = m + 1; jx < QA; ++jx) Li[m][jx] = 0.0;
+                        for (int jx = m + 1; jx < QA; ++jx) Li[m][jx] = 0;
                     }
                     for (int m = 0; m < q; ++m) {
-                        double s = 0.0;
-                        for (int l = 0; l <= m; ++l) s += Li[m][l] * c.bhat[(int64_t)P[l] * c.TP + t];
+                        R s = 0;
+                        for (int l = 0; l <= m; ++l) s += Li[m][l] * (R)c.bhat[(int64_t)P[l] * c.TP + t];
                         zp[m] = s;
                         pp -= s * s;
                     }
@@ -896,12 +924,12 @@ __global__ __launch_bounds__(256) void search_kernel(Ctx c, SearchArgs a) {
             const int sid = MT ? t : r;
             const bool writer = MT ? (jj == 0 && t < 64) : (jj == 0 && r < NR);
             if (writer) {
-                double *f = subf + sid * SUBW;
+                R *f = subf + sid * SUBW;
                 for (int m = 0; m < QA; ++m)
-                    for (int l = 0; l < QA; ++l) f[m * QA + l] = (pvalid && m < q) ? Li[m][l] : 0.0;
-                for (int m = 0; m < QA; ++m) f[QA * QA + m] = (pvalid && m < q) ? zp[m] : 0.0;
-                f[QA * QA + QA] = pvalid ? pp : 0.0;
-                f[QA * QA + QA + 1] = pvalid ? 1.0 : 0.0;
+                    for (int l = 0; l < QA; ++l) f[m * QA + l] = (pvalid && m < q) ? Li[m][l] : (R)0;
+                for (int m = 0; m < QA; ++m) f[QA * QA + m] = (pvalid && m < q) ? zp[m] : (R)0;
+                f[QA * QA + QA] = pvalid ? pp : (R)0;
+                f[QA * QA + QA + 1] = pvalid ? (R)1 : (R)0;
                 if (!MT) {
                     for (int m = 0; m < QA; ++m) s_sub[r][m] = (rvalid && m < q) ? P[m] : -1;
                     s_iq[r] = (rvalid && q > 0) ? P[q - 1] : (rvalid ? -1 : 1 << 30);
@@ -914,28 +942,28 @@ __global__ __launch_bounds__(256) void search_kernel(Ctx c, SearchArgs a) {
             const int64_t j = j0 + jj;
             const int iq = (q > 0 && rvalid) ? P[q - 1] : -1;
             bool jvalid = rvalid && (j > iq) && (j < Nj);
-            double rec[RECW];
-            for (int m = 0; m < RECW; ++m) rec[m] = 0.0;
+            R rec[RECW];
+            for (int m = 0; m < RECW; ++m) rec[m] = 0;
             bool ok = false;
             if (jvalid && t < c.T && pvalid) {
-                double v[QA];
-                double d = Gat(c, j, j, t);
+                R v[QA];
+                R d = (R)Gat(c, j, j, t);
                 for (int m = 0; m < q; ++m) {
-                    double s = 0.0;
-                    for (int l = 0; l <= m; ++l) s += Li[m][l] * Gat(c, P[l], j, t);
+                    R s = 0;
+                    for (int l = 0; l <= m; ++l) s += Li[m][l] * (R)Gat(c, P[l], j, t);
                     v[m] = s;
                     d -= s * s;
                 }
-                if (d > RANK_EPS) {
-                    const double sj = sqrt(d);
-                    double zn = c.bhat[j * c.TP + t];
+                if (d > rank_eps_r<R>()) {
+                    const R sj = sqrt(d);
+                    R zn = (R)c.bhat[j * c.TP + t];
                     for (int m = 0; m < q; ++m) zn -= v[m] * zp[m];
                     zn /= sj;
-                    const double p = pp - zn * zn;
+                    const R p = pp - zn * zn;
                     for (int m = 0; m < q; ++m) rec[m] = v[m];
-                    rec[q] = 1.0 / d;
+                    rec[q] = (R)1 / d;
                     rec[q + 1] = zn / sj;
-                    rec[q + 2] = p - theta_f;
+                    rec[q + 2] = p - theta_r;
                     rec[q + 3] = p;
                     ok = true;
                 }
@@ -943,12 +971,12 @@ __global__ __launch_bounds__(256) void search_kernel(Ctx c, SearchArgs a) {
                 ok = true;  // padding task: contributes exactly zero
             }
             if (!ok) {
-                rec[q + 2] = __builtin_nan("");
-                rec[q + 3] = __builtin_nan("");
+                rec[q + 2] = (R)__builtin_nan("");
+                rec[q + 3] = (R)__builtin_nan("");
             }
             const int slot = MT ? (jj * TL + t) : (jj * NR + r);
             if (MT ? (jj < JB) : true) {
-                double *dst = recs + slot * RECW;
+                R *dst = recs + slot * RECW;
                 for (int m = 0; m < RECW; ++m) dst[m] = rec[m];
             }
             // validity masks: ST per r over jj; MT per jj over all tasks
@@ -966,7 +994,7 @@ __global__ __launch_bounds__(256) void search_kernel(Ctx c, SearchArgs a) {
             if (tid < JB) {
                 bool all = true;
                 for (int t = 0; t < c.T; ++t) {
-                    const double *rr = recs + (tid * TL + t) * RECW;
+                    const R *rr = recs + (tid * TL + t) * RECW;
                     all &= !__builtin_isnan(rr[q + 3]);
                 }
                 s_mask[tid] = all ? 1ull : 0ull;
@@ -986,8 +1014,8 @@ __global__ __launch_bounds__(256) void search_kernel(Ctx c, SearchArgs a) {
             const int64_t k = kb + kl;
             const bool kin = k < c.S;
             const int64_t kc = kin ? k : c.S - 1;
-            double wq[NR][QA], dq[NR], zq[NR];
-            hoist_k<D, NR, MT>(c, subf, &s_sub[0][0], kc, myt, wq, dq, zq);
+            R wq[NR][QA], dq[NR], zq[NR];
+            hoist_k<D, NR, MT, R>(c, subf, &s_sub[0][0], kc, myt, wq, dq, zq);
             const bool check = (kb <= jhi) || (kb + KL > c.S);
             // G rows of the tile (j-block, k-chunk): a uniform pointer to row j0
             // plus 32-bit row and lane offsets (one task: TP = 1).  Rows are
@@ -1005,43 +1033,41 @@ __global__ __launch_bounds__(256) void search_kernel(Ctx c, SearchArgs a) {
             auto sweep = [&](auto checkc) {
                 constexpr bool CHECK = decltype(checkc)::value;
                 // records of one step: (P', j) for every sub-prefix (one task)
-                typedef double RecSet[NR][q + 3];
+                typedef R RecSet[NR][q + 3];
                 auto load_rv = [&](RecSet &rv, int jj) {
-                    const double *rj = recs + jj * (NR * RECW);
+                    const R *rj = recs + jj * (NR * RECW);
 #pragma unroll
                     for (int r = 0; r < NR; ++r)
 #pragma unroll
                         for (int x = 0; x < q + 3; ++x) rv[r][x] = rj[r * RECW + x];
                 };
-                auto body = [&](int jj, double g, bool live, const RecSet &rvs) {
+                auto body = [&](int jj, R g, bool live, const RecSet &rvs) {
                     unsigned long long m = 0;
                     if (MT) {
                         // a j whose record is invalid in some task has p = NaN
                         // there, so its task sum fails the comparison
-                        const double *rr = recs + (jj * TL + myt) * RECW;
-                        double rv[q + 4];
+                        const R *rr = recs + (jj * TL + myt) * RECW;
+                        R rv[q + 4];
 #pragma unroll
                         for (int x = 0; x < q + 4; ++x) rv[x] = rr[x];
                         __asm__ volatile("" ::: "memory");
-                        double u = g;
+                        R u = g;
 #pragma unroll
                         for (int x = 0; x < q; ++x) u = fma(-rv[x], wq[0][x], u);
-                        const double d = fma(-rv[q], u * u, dq[0]);
-                        const double z = fma(-rv[q + 1], u, zq[0]);
+                        const R d = fma(-rv[q], u * u, dq[0]);
+                        const R z = fma(-rv[q + 1], u, zq[0]);
                         // p - z^2/d with a reciprocal refined by one Newton step
-                        double rc = __builtin_amdgcn_rcp(d);
-                        rc = fma(rc, fma(-d, rc, 1.0), rc);
-                        double sum = fma(-(z * z), rc, rv[q + 3]);
+                        R sum = fma(-(z * z), rcp_r(d), rv[q + 3]);
                         for (int o = 1; o < TL; o <<= 1) sum += __shfl_xor(sum, o);
-                        m = __ballot(sum <= theta_f && tl == 0);
+                        m = __ballot(sum <= theta_r && tl == 0);
                     } else {
 #pragma unroll
                         for (int r = 0; r < NR; ++r) {
-                            double u = g;
+                            R u = g;
 #pragma unroll
                             for (int x = 0; x < q; ++x) u = fma(-rvs[r][x], wq[r][x], u);
-                            const double d = fma(-rvs[r][q], u * u, dq[r]);
-                            const double z = fma(-rvs[r][q + 1], u, zq[r]);
+                            const R d = fma(-rvs[r][q], u * u, dq[r]);
+                            const R z = fma(-rvs[r][q + 1], u, zq[r]);
                             m |= __ballot(z * z >= rvs[r][q + 2] * d);
                         }
                     }
@@ -1059,57 +1085,55 @@ __global__ __launch_bounds__(256) void search_kernel(Ctx c, SearchArgs a) {
                 // register sets, so JG loads per wave are in flight while a
                 // group is scored
                 constexpr int JG = SEARCH_JG;
-                double ga[JG], gb[JG];
+                R ga[JG], gb[JG];
                 // a uniform 64-bit base plus a 32-bit byte offset per load
                 // (uniform row part + per-lane column part)
                 const char *__restrict__ gpc = reinterpret_cast<const char *>(gp);
                 const uint32_t ko8 = (uint32_t)ko * 8u;
-                auto fetch = [&](double (&dst)[JG], int jg) {
+                auto fetch = [&](R (&dst)[JG], int jg) {
 #pragma unroll
                     for (int x = 0; x < JG; ++x) {
                         const int jr = jg + x < nrow ? jg + x : nrow;
                         const uint32_t ro = (uint32_t)(jr * rs) * 8u;
-                        dst[x] = *reinterpret_cast<const double *>(gpc + (ro + ko8));
+                        dst[x] = (R)*reinterpret_cast<const double *>(gpc + (ro + ko8));
                     }
                 };
                 // every fetched row is scored (rows past the block repeat its
                 // last row and are masked out), so no load is left pending on
                 // a skipped path
-                auto score = [&](const double (&src)[JG], int jg) {
+                auto score = [&](const R (&src)[JG], int jg) {
                     if (MT) {
                         // many tasks: the task terms of all JG rows first (independent
                         // chains), then their sums over the TL task lanes of each last
                         // index, all rows at once (row-local DPP steps; wider groups
                         // by lane shuffles)
-                        double sm[JG];
+                        R sm[JG];
 #pragma unroll
                         for (int x = 0; x < JG; ++x) {
                             const int jj = jg + x <= nrow ? jg + x : nrow;
-                            const double *rr = recs + (jj * TL + myt) * RECW;
-                            double u = src[x];
+                            const R *rr = recs + (jj * TL + myt) * RECW;
+                            R u = src[x];
 #pragma unroll
                             for (int xx = 0; xx < q; ++xx) u = fma(-rr[xx], wq[0][xx], u);
-                            const double d = fma(-rr[q], u * u, dq[0]);
-                            const double z = fma(-rr[q + 1], u, zq[0]);
-                            double rc = __builtin_amdgcn_rcp(d);
-                            rc = fma(rc, fma(-d, rc, 1.0), rc);
-                            sm[x] = fma(-(z * z), rc, rr[q + 3]);
+                            const R d = fma(-rr[q], u * u, dq[0]);
+                            const R z = fma(-rr[q + 1], u, zq[0]);
+                            sm[x] = fma(-(z * z), rcp_r(d), rr[q + 3]);
                         }
                         if (TL >= 2) {
 #pragma unroll
-                            for (int x = 0; x < JG; ++x) sm[x] += dpp_f64<0xB1>(sm[x]);  // lane ^ 1
+                            for (int x = 0; x < JG; ++x) sm[x] += dpp_r<0xB1>(sm[x]);  // lane ^ 1
                         }
                         if (TL >= 4) {
 #pragma unroll
-                            for (int x = 0; x < JG; ++x) sm[x] += dpp_f64<0x4E>(sm[x]);  // lane ^ 2
+                            for (int x = 0; x < JG; ++x) sm[x] += dpp_r<0x4E>(sm[x]);  // lane ^ 2
                         }
                         if (TL >= 8) {
 #pragma unroll
-                            for (int x = 0; x < JG; ++x) sm[x] += dpp_f64<0x141>(sm[x]);  // mirror in 8
+                            for (int x = 0; x < JG; ++x) sm[x] += dpp_r<0x141>(sm[x]);  // mirror in 8
                         }
                         if (TL >= 16) {
 #pragma unroll
-                            for (int x = 0; x < JG; ++x) sm[x] += dpp_f64<0x140>(sm[x]);  // mirror in 16
+                            for (int x = 0; x < JG; ++x) sm[x] += dpp_r<0x140>(sm[x]);  // mirror in 16
                         }
                         if (TL >= 32) {
 #pragma unroll
@@ -1122,7 +1146,7 @@ __global__ __launch_bounds__(256) void search_kernel(Ctx c, SearchArgs a) {
 #pragma unroll
                         for (int x = 0; x < JG; ++x) {
                             const int jj = jg + x <= nrow ? jg + x : nrow;
-                            unsigned long long m = __ballot(sm[x] <= theta_f && tl == 0);
+                            unsigned long long m = __ballot(sm[x] <= theta_r && tl == 0);
                             if (CHECK) m &= __ballot(kin && kr > jj);
                             m = (jg + x <= nrow) ? m : 0ull;
                             if (m) {
@@ -1166,7 +1190,7 @@ __global__ __launch_bounds__(256) void search_kernel(Ctx c, SearchArgs a) {
             for (int e = 0; e < nq; ++e) {
                 const int jj = qj[e];
                 const unsigned long long lm = qmask[e];
-                theta_pub = slow_path<D, NR, MT>(c, a, Ls, Lr, recs, subf, &s_sub[0][0], s_mask, j0 + jj, jj, k,
+                theta_pub = slow_path<D, NR, MT, R>(c, a, Ls, Lr, recs, subf, &s_sub[0][0], s_mask, j0 + jj, jj, k,
                                                  kin, (lm >> lane) & 1ull, myt, TL, theta_f, theta_pub, offered);
             }
         }
@@ -3193,7 +3217,10 @@ static void launch_prepass(const Ctx &c, const SearchCall &sc, int L, hipStream_
 
 template <int D, bool MT>
 static void launch_one(const Ctx &c, const SearchArgs &a, size_t lds, hipStream_t st) {
-    hipLaunchKernelGGL((search_kernel<D, MT>), dim3(c.search_wgs), dim3(SEARCH_WG), lds, st, c, a);
+    if (c.fp32)
+        hipLaunchKernelGGL((search_kernel<D, MT, float>), dim3(c.search_wgs), dim3(SEARCH_WG), lds, st, c, a);
+    else
+        hipLaunchKernelGGL((search_kernel<D, MT, double>), dim3(c.search_wgs), dim3(SEARCH_WG), lds, st, c, a);
 }
 
 static void launch_merge(const Ctx &c, int nlists, int L, int use_pre, hipStream_t st, int dedupe = 0,
@@ -3207,7 +3234,7 @@ static void launch_merge(const Ctx &c, int nlists, int L, int use_pre, hipStream
 // The one-task D = 3 record-table path applies (it also needs the table in
 // the workspace and fewer than 2^31 tiles).
 bool s3_batchable(const Ctx &c, int D) {
-    return D == 3 && c.T == 1 && c.rec3 != nullptr && s3_tiles_host(c.S) < (1ull << 31);
+    return D == 3 && c.T == 1 && !c.fp32 && c.rec3 != nullptr && s3_tiles_host(c.S) < (1ull << 31);
 }
 
 // record table + initialisation + pre-pass selection (one launch), then the
@@ -3280,11 +3307,11 @@ int launch_search(const Ctx &c, const SearchCall &sc, hipStream_t st) {
         // one task, D = 3: record table + tile sweep (tile count within the 32-bit work counter)
         // D = 3: the record-table sweep, on the filter task's matrix when
         // there are several tasks
-        const bool s3 = D == 3 && c.rec3 != nullptr && s3_tiles_host(c.S) < (1ull << 31) &&
+        const bool s3 = D == 3 && !c.fp32 && c.rec3 != nullptr && s3_tiles_host(c.S) < (1ull << 31) &&
                         (!MT || c.mtq_chunks > 0);
         // one task, D = 4: the pair-group record table (sized at create only
         // while it stays within S4_TABLE_MAX and 2^31 tiles)
-        const bool s4 = D == 4 && !MT && c.rec4 != nullptr;
+        const bool s4 = D == 4 && !MT && !c.fp32 && c.rec4 != nullptr;
         if (s4) {
             hipLaunchKernelGGL(s4_init_kernel, dim3(init_blocks), dim3(256), 0, st, c);
         } else if (s3) {

@@ -146,6 +146,21 @@ def test_precision_modes_size_the_workspace():
     assert ws(7) == 0
 
 
+def test_fp32_solve_form_drops_the_record_tables():
+    """The FP32 solve form keeps the FP64 Gram (no slices) and runs the
+    general kernels, so it holds no D = 3 / D = 4 record table; its lists are
+    twice as long (2 (k + 16) candidates for the FP64 re-score)."""
+    def ws(prec, D):
+        d = B.make_desc(0, 0, np.array([0, 2000], dtype=np.int64), 2000, 300, D, 100, precision=prec)
+        return B.sisso_l0_workspace_bytes(d)
+    # D_max = 2: no table in either form, only the longer lists
+    assert ws(B.SISSO_PREC_FP32_SOLVE, 2) > ws(B.SISSO_PREC_FP64, 2)
+    # D_max = 4: the FP64 form carries the D = 3 and D = 4 record tables
+    # (C(300, 3) / 6 x 160 bytes of D = 4 records alone), the FP32 form none
+    rec4 = (300 ** 3 // 24) * 160
+    assert ws(B.SISSO_PREC_FP64, 4) - ws(B.SISSO_PREC_FP32_SOLVE, 4) > rec4 // 2
+
+
 def test_several_task_d3_workspace_holds_filter_matrix_and_step_queue():
     """With several tasks and D_max >= 3 the workspace also holds the filter
     task's matrix alone (S^2 doubles, one-task tiled, so padded to 64) and

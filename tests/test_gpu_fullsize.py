@@ -86,14 +86,27 @@ def test_precision_workload_fp64_full():
     assert tuple(int(v) for v in gi[0]) == tuple(p.planted)
 
 
-@pytest.mark.parametrize("form", ["bf16", "fp16"])
+@pytest.mark.parametrize("form", ["bf16", "fp16", "fp32"])
 def test_precision_workload_sliced_gram_full(form):
     from paper_2502_20072_amd import _binding as B
     # the FP64 tie band: the precision forms re-score 2 (k + 16) candidates
     # exactly, so only a ranked-SSE error larger than the gap between the k-th
     # and the 2 (k + 16)-th SSE could change the list
-    prec = B.SISSO_PREC_BF16_COMP if form == "bf16" else B.SISSO_PREC_FP16_COMP
+    prec = {"bf16": B.SISSO_PREC_BF16_COMP, "fp16": B.SISSO_PREC_FP16_COMP, "fp32": B.SISSO_PREC_FP32_SOLVE}[form]
     _check("precision_s4096_d2", precision=prec)
+
+
+@pytest.mark.parametrize("name,rng", [
+    ("multitask_t16_s1500_d3", (0, 2)),
+    ("learned_s600_d4", (0, 1)),
+    ("batch64_d3.63", None), ("batch64_d3.14", (0, 2)),
+])
+def test_fp32_solve_form_against_stored_oracle(name, rng):
+    """The FP32 per-tuple solve form (FP32 ranking of 2 (k + 16) candidates,
+    FP64 re-score) returns the oracle's top-k on the multi-task, D = 4 and
+    batch workloads (with C3 above: every stored result)."""
+    from paper_2502_20072_amd import _binding as B
+    _check(name, rng, precision=B.SISSO_PREC_FP32_SOLVE)
 
 
 def test_batch_of_64_equals_unbatched_bitwise():
