@@ -400,7 +400,8 @@ def bench_learned(args, p) -> int:
 
     from synth import make_problem
     from paper_2502_20072_amd import L0Search
-    from paper_2502_20072_amd.learned import ProposalNet, training_set, propose_and_search, r2_scorer, recall
+    from paper_2502_20072_amd.learned import (ProposalNet, training_set, propose_and_search, propose_two_stage,
+                                              r2_scorer, recall)
 
     D, k = p.D, p.k
     beta = (1.5, -0.8, 0.6)
@@ -442,6 +443,15 @@ def bench_learned(args, p) -> int:
     rec = recall(li, ei)
     propose_and_search(s, D, k, r2_scorer, budget_frac=args.budget)
     rec_r2 = recall(s.topk()[0], ei)
+    # sub-enumeration: (D-2)-prefixes first, then the extensions of the best
+    info2 = {}
+
+    def prop2():
+        info2.update(propose_two_stage(s, D, k, net.predict, budget_frac=args.budget))
+    t_two = timed(prop2, max(1, args.steps // 4))
+    rec_two = recall(s.topk()[0], ei)
+    propose_two_stage(s, D, k, r2_scorer, budget_frac=args.budget)
+    rec_two_r2 = recall(s.topk()[0], ei)
     s.close()
     ntup = math.comb(p.S, D)
     res = {
@@ -453,6 +463,8 @@ def bench_learned(args, p) -> int:
                    "form": "learned proposal", **info},
         f"recall_at_{k}": rec, f"recall_at_{k}_r2_only": rec_r2,
         "exhaustive_ms": t_exh, "proposal_ms": t_prop, "speedup_vs_exhaustive": t_exh / t_prop,
+        "two_stage": {"ms": t_two, "speedup_vs_exhaustive": t_exh / t_two, f"recall_at_{k}": rec_two,
+                      f"recall_at_{k}_r2_only": rec_two_r2, **info2},
         "train": {"prefixes": int(X.shape[0]), "seconds": train_s, "loss_first_epoch": hist[0],
                   "loss_last_epoch": hist[-1]},
     }

@@ -197,6 +197,16 @@ int32_t sisso_l0_search_list(sisso_l0 *h, int32_t D, int32_t k, const int32_t *p
  * rules and errors as sisso_l0_prefix_best, plus EINVAL for a null target. */
 int32_t sisso_l0_prefix_target(sisso_l0 *h, int32_t m, const int32_t *prefixes, int64_t n, double *best,
                                float *target);
+/* Every one-index extension of each listed prefix, for a proposal that
+ * scores short prefixes first and only the extensions of the best ones
+ * (sub-enumeration): out (DEVICE int32 [n (S - m)][m + 1]) row p (S - m) + t
+ * is the sorted tuple P_p + {j}, j the t-th index in {0..S-1} not in P_p,
+ * ascending; a malformed row of prefixes (not strictly increasing indices in
+ * [0, S)) gives rows of -1, which sisso_l0_prefix_features and
+ * sisso_l0_search_list treat as malformed.  1 <= m <= SISSO_MAX_D - 1
+ * (ENOTSUP above); asynchronous; ESTATE before sisso_gram, EINVAL for null
+ * pointers, a negative count or more than 2^40 output rows. */
+int32_t sisso_l0_prefix_extend(sisso_l0 *h, int32_t m, const int32_t *prefixes, int64_t n, int32_t *out);
 /* Features (as sisso_l0_prefix_features) of the m-subsets of {0..S-1}
  * (1 <= m <= 3) with colexicographic ranks r0 .. r0 + n - 1, i.e. ordered
  * by largest element, then by the rest in the same order; feat: DEVICE

@@ -331,6 +331,7 @@ def _prop_sigs(lib):
                        ("sisso_l0_prefix_target", [V, I32, V, I64, V, V]),
                        ("sisso_l0_prefix_features", [V, I32, V, I64, V]),
                        ("sisso_l0_prefix_features_range", [V, I32, U64, I64, V]),
+                       ("sisso_l0_prefix_extend", [V, I32, V, I64, V]),
                        ("sisso_l0_search_list", [V, I32, I32, V, I64]),
                        ("sisso_mlp_forward", [V, V, I64, V, V, SZ, V]),
                        ("sisso_mlp_backward", [V, V, V, I64, V, V, V, SZ, V]),
@@ -378,6 +379,10 @@ def sisso_l0_prefix_target(h: int, m: int, prefixes, best, target) -> None:
 
 def sisso_l0_prefix_features(h: int, m: int, prefixes, feat) -> None:
     _check(_plib().sisso_l0_prefix_features(h, m, _ptr(prefixes), prefixes.shape[0], _ptr(feat)), h)
+
+
+def sisso_l0_prefix_extend(h: int, m: int, prefixes, out) -> None:
+    _check(_plib().sisso_l0_prefix_extend(h, m, _ptr(prefixes), prefixes.shape[0], _ptr(out)), h)
 
 
 def sisso_l0_prefix_features_range(h: int, m: int, r0: int, n: int, feat) -> None:

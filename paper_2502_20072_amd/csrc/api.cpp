@@ -432,6 +432,19 @@ extern "C" int32_t sisso_l0_prefix_features(sisso_l0 *h, int32_t m, const int32_
     return SISSO_OK;
 }
 
+extern "C" int32_t sisso_l0_prefix_extend(sisso_l0 *h, int32_t m, const int32_t *prefixes, int64_t n, int32_t *out) {
+    int32_t rc = check_prefixes(h, m, prefixes, n);
+    if (rc != SISSO_OK) return rc;
+    if (m + 1 > SISSO_MAX_D) return fail(h, SISSO_ENOTSUP, "prefix length + 1 exceeds SISSO_MAX_D");
+    if (m >= h->desc.S) return fail(h, SISSO_EINVAL, "a prefix of length S has no extension");
+    if (n > 0 && !out) return fail(h, SISSO_EINVAL, "null output");
+    if (n > (int64_t(1) << 40) / (h->desc.S - m)) return fail(h, SISSO_EINVAL, "too many extensions");
+    if (n == 0) return SISSO_OK;
+    if (launch_prefix_extend(h->ctx, m, prefixes, n, out, h->stream))
+        return fail(h, SISSO_EDEVICE, hipGetErrorString(hipGetLastError()));
+    return SISSO_OK;
+}
+
 extern "C" int32_t sisso_l0_prefix_features_range(sisso_l0 *h, int32_t m, uint64_t r0, int64_t n, float *feat) {
     if (!h) return SISSO_EINVAL;
     h->err.clear();

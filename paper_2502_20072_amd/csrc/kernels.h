@@ -88,6 +88,7 @@ int launch_search(const Ctx &c, const SearchCall &sc, hipStream_t st);
 int launch_prefix_best(const Ctx &c, int M, const int32_t *pre, int64_t n, double *best, hipStream_t st);
 int launch_prefix_target(const Ctx &c, const double *best, int64_t n, float *target, hipStream_t st);
 int launch_prefix_features(const Ctx &c, int M, const int32_t *pre, int64_t n, float *out, hipStream_t st);
+int launch_prefix_extend(const Ctx &c, int M, const int32_t *pre, int64_t n, int32_t *out, hipStream_t st);
 int launch_prefix_features_range(const Ctx &c, int M, uint64_t r0, int64_t n, float *out, hipStream_t st);
 int launch_list_search(const Ctx &c, int D, int k, const int32_t *pre, int64_t n, hipStream_t st);
 

@@ -3405,6 +3405,48 @@ int launch_prefix_target(const Ctx &c, const double *best, int64_t n, float *tar
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+// Every extension of each listed prefix: thread (p, t) writes the sorted
+// (M + 1)-tuple P + {j}, j the t-th index of {0..S-1} not in P (walking the
+// sorted prefix: each member at or below the running index pushes it up by
+// one).  A malformed prefix row gives rows of -1.
+template <int M>
+__global__ __launch_bounds__(256) void prefix_extend_kernel(int64_t S, const int32_t *__restrict__ pre, int64_t n,
+                                                            int32_t *__restrict__ out) {
+    const int64_t w = S - M;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * w) return;
+    const int64_t p = e / w, t = e - p * w;
+    int32_t P[M];
+    bool ok = true;
+    for (int q = 0; q < M; ++q) {
+        P[q] = pre[p * M + q];
+        ok &= P[q] >= 0 && P[q] < S && (q == 0 || P[q] > P[q - 1]);
+    }
+    int32_t *o = out + e * (M + 1);
+    if (!ok) {
+        for (int q = 0; q <= M; ++q) o[q] = -1;
+        return;
+    }
+    int64_t j = t;
+    for (int q = 0; q < M; ++q) j += P[q] <= j ? 1 : 0;
+    int q = 0, x = 0;
+    for (; q < M && P[q] < j; ++q) o[x++] = P[q];
+    o[x++] = (int32_t)j;
+    for (; q < M; ++q) o[x++] = P[q];
+}
+
+int launch_prefix_extend(const Ctx &c, int M, const int32_t *pre, int64_t n, int32_t *out, hipStream_t st) {
+    const int64_t tot = n * (c.S - M);
+    const unsigned blocks = (unsigned)((tot + 255) / 256);
+    switch (M) {
+        case 1: hipLaunchKernelGGL((prefix_extend_kernel<1>), dim3(blocks), dim3(256), 0, st, c.S, pre, n, out); break;
+        case 2: hipLaunchKernelGGL((prefix_extend_kernel<2>), dim3(blocks), dim3(256), 0, st, c.S, pre, n, out); break;
+        case 3: hipLaunchKernelGGL((prefix_extend_kernel<3>), dim3(blocks), dim3(256), 0, st, c.S, pre, n, out); break;
+        default: return -1;
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 int launch_prefix_features(const Ctx &c, int M, const int32_t *pre, int64_t n, float *out, hipStream_t st) {
     const unsigned blocks = (unsigned)((n + 255) / 256);
     switch (M) {

@@ -6,7 +6,9 @@ the correlations of its features with y and with each other:
 sisso_l0_prefix_features).  The prefixes with the best scores are extended
 by every feature and those tuples are evaluated exactly
 (sisso_l0_search_list), so a D-search touches a chosen fraction of the
-C(S, D) tuples.  Exhaustive search stays the reference: recall@k is measured
+C(S, D) tuples.  The two-stage form scores the (D-2)-prefixes first and
+only the extensions of the best of them (sub-enumeration), so the network
+runs on C(S, D-2) + a few thousand prefixes instead of C(S, D-1).  Exhaustive search stays the reference: recall@k is measured
 against it.
 
 Training data come from exhaustive evaluation at a smaller dimension: for
@@ -161,6 +163,51 @@ def propose_and_search(search, D: int, k: int, scorer, budget_frac: float = 0.01
     search.last_D, search.last_k = D, k
     return dict(prefixes_scored=npre, prefixes_kept=cnt, prefix_budget=K,
                 tuples_evaluated=cnt * (S - m), tuples_total=math.comb(S, D))
+
+
+def propose_two_stage(search, D: int, k: int, scorer, budget_frac: float = 0.01, keep_factor: float = 32.0,
+                      min_keep: int = 256, chunk: int = 1 << 24) -> Dict:
+    """Sub-enumeration: score every (D-2)-prefix (every pair at D = 4),
+    keep the best, score every one-index extension of the kept ones
+    (sisso_l0_prefix_extend), keep the best (D-1)-prefixes for a budget of
+    budget_frac * C(S, D) tuples and search their extensions exactly.  The
+    scorer sees C(S, D-2) + kept (S - D + 2) prefixes instead of
+    C(S, D-1).  The first stage keeps enough prefixes for keep_factor times
+    the second stage's count, and at least min_keep: the first stage's
+    extensions are cheap to score, and too few kept prefixes is what loses
+    recall at small budgets.  D >= 3."""
+    import torch
+    S, m1, m2 = search.S, D - 2, D - 1
+    if m1 < 1:
+        raise ValueError("the two-stage proposal needs D >= 3")
+    dev = search.F.device
+    n1 = math.comb(S, m1)
+    scores1 = torch.empty(n1, dtype=torch.float32, device=dev)
+    st = _stream(scores1)
+    feat = torch.empty((min(chunk, n1), B.PROP_NF), dtype=torch.float32, device=dev)
+    for r0 in range(0, n1, chunk):
+        n = min(chunk, n1 - r0)
+        B.sisso_l0_prefix_features_range(search.handle, m1, r0, n, feat[:n])
+        scores1[r0:r0 + n] = scorer(feat[:n])
+    K2 = max(1, min(math.comb(S, m2), math.ceil(budget_frac * math.comb(S, D) / (S - m2))))
+    K1 = max(1, min(n1, max(int(min_keep), math.ceil(keep_factor * K2 / (S - m1)))))
+    ws = torch.empty(B.sisso_select_workspace_bytes(), dtype=torch.uint8, device=dev)
+    ranks1 = torch.empty(min(n1, 2 * K1 + 4096), dtype=torch.int64, device=dev)
+    cnt1 = B.sisso_select_top(scores1, K1, ranks1, ws, st)
+    pre1 = torch.empty((cnt1, m1), dtype=torch.int32, device=dev)
+    B.sisso_colex_unrank(m1, ranks1[:cnt1], pre1, st)
+    ext = torch.empty((cnt1 * (S - m1), m2), dtype=torch.int32, device=dev)
+    B.sisso_l0_prefix_extend(search.handle, m1, pre1, ext)
+    feat2 = torch.empty((ext.shape[0], B.PROP_NF), dtype=torch.float32, device=dev)
+    B.sisso_l0_prefix_features(search.handle, m2, ext, feat2)
+    scores2 = scorer(feat2)
+    rows = torch.empty(min(ext.shape[0], 2 * K2 + 4096), dtype=torch.int64, device=dev)
+    cnt2 = B.sisso_select_top(scores2, K2, rows, ws, st)
+    pre2 = ext[rows[:cnt2]].contiguous()
+    B.sisso_l0_search_list(search.handle, D, k, pre2)
+    search.last_D, search.last_k = D, k
+    return dict(stage1_scored=n1, stage1_kept=cnt1, stage2_scored=int(ext.shape[0]), prefixes_kept=cnt2,
+                tuples_evaluated=cnt2 * (S - m2), tuples_total=math.comb(S, D))
 
 
 def r2_scorer(feat):
