@@ -304,7 +304,9 @@ int32_t sisso_l0_phase_ms(sisso_l0 *h, double *ms);
  * a search. */
 int32_t sisso_l0_search_stats(sisso_l0 *h, uint64_t *out);
 
-/* Release the handle (NULL-safe).  Does not free caller memory. */
+/* Wait for the work enqueued on the handle's stream, then release the
+ * handle (NULL-safe).  Does not free caller memory; the workspace may be
+ * released once this returns. */
 void sisso_l0_destroy(sisso_l0 *h);
 
 /* Message for the last error on h ("" if none); valid until the next call on

@@ -62,6 +62,16 @@ class L0Search:
         self._desc = B.make_desc(self.F.data_ptr(), self.y.data_ptr(), self.offsets, self.n, self.S,
                                  self.D_max, self.k_max, aligned, nbytes, self.stream.cuda_stream,
                                  precision=self.precision)
+        cur = torch.cuda.current_stream(self.F.device)
+        if self.stream.cuda_stream != cur.cuda_stream:
+            # the inputs (uploads, contiguous copies) and the workspace were
+            # made on the current stream: the handle's stream waits for that
+            # work, and the allocator is told that the handle's stream uses
+            # these blocks (so it does not hand them out again while the
+            # handle's work may still touch them)
+            self.stream.wait_stream(cur)
+            for t in (self.F, self.y, self._ws):
+                t.record_stream(self.stream)
         self.handle = B.sisso_l0_create(self._desc)
         self.last_D = None
         self.last_k = None

@@ -32,6 +32,9 @@ struct sisso_l0 {
     char *stage = nullptr;  // pinned host copy of the result block (one transfer per readout)
     const void *btab_owner = nullptr;  // the batch whose search table this handle's workspace holds
     ~sisso_l0() {
+        // the caller may release the workspace once destroy returns: let the
+        // handle's enqueued work finish first
+        (void)hipStreamSynchronize(stream);
         for (auto &e : ev)
             if (e) (void)hipEventDestroy(e);
         if (stage) (void)hipHostFree(stage);
@@ -155,7 +158,7 @@ static Layout compute_layout(int64_t n_total, int64_t S, int T, int D_max, int k
     // 1 GiB of records the several-task search keeps its general kernel
     L.mtq_chunks = 0;
     if (L.G1_bytes) {
-        const uint64_t steps = s3_tiles_host(S) * 32;
+        const uint64_t steps = s3_tiles_host(S) * (uint64_t)s3_rows_per_tile();
         const uint64_t chunks = (steps + MTQ_CHUNK - 1) / MTQ_CHUNK + (uint64_t)nlists;
         if (chunks * MTQ_CHUNK * 3 * sizeof(uint64_t) <= (1ull << 30)) L.mtq_chunks = (int)chunks;
     }

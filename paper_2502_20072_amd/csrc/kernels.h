@@ -78,6 +78,7 @@ struct SearchCall {
 };
 
 uint64_t s3_tiles_host(int64_t S);  // tiles of the D = 3 record-table sweep
+int s3_rows_per_tile();             // rows j per tile of that sweep (its steps per tile, at most)
 uint64_t s4_tiles_host(int64_t S);  // tiles of the D = 4 record-table sweep
 int launch_stats(const Ctx &c, hipStream_t st);
 int launch_gram(const Ctx &c, hipStream_t st);  // FP64 MFMA or precision form, then finish

@@ -1317,6 +1317,8 @@ __device__ void s3_tile_table(const Ctx &c) {
     c.stats[1] = acc;
 }
 
+int s3_rows_per_tile() { return S3_JR; }
+
 uint64_t s3_tiles_host(int64_t S) {
     const int64_t nb = s3_nblocks(S);
     uint64_t acc = 0;
