@@ -134,9 +134,10 @@ def main() -> int:
                          "per-tuple solves in FP32 (FP64 Gram); the re-score is FP64 in every form")
     ap.add_argument("--tune-cache", default=os.environ.get("SISSO_AUTOTUNE_CACHE"),
                     help="JSON cache of the search-grid autotuner (default: tune every run)")
-    ap.add_argument("--form", choices=("exhaustive", "learned"), default="exhaustive",
+    ap.add_argument("--form", choices=("exhaustive", "learned", "screen"), default="exhaustive",
                     help="learned: train the proposal network (untimed), then time proposal + exact "
-                         "evaluation against exhaustive search on the same GPU")
+                         "evaluation against exhaustive search on the same GPU; screen: one screening "
+                         "pass over a created rung (--workload sis_s1000_n2000 or sis_t2_s1000_n156)")
     ap.add_argument("--budget", type=float, default=0.01, help="learned form: fraction of C(S, D) evaluated")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="before the timed region, copy a buffer of this many MiB three times with torch "
@@ -170,6 +171,8 @@ def main() -> int:
 
     if args.workload == "batch64_d3":
         return bench_batch(args)
+    if args.form == "screen":
+        return bench_screen(args)
     p = make_config(args.workload)
     if args.form == "learned":
         return bench_learned(args, p)
@@ -468,6 +471,191 @@ def bench_learned(args, p) -> int:
         "train": {"prefixes": int(X.shape[0]), "seconds": train_s, "loss_first_epoch": hist[0],
                   "loss_last_epoch": hist[-1]},
     }
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+def screen_flop_per_sample(nres: int) -> int:
+    """Algorithmic FP64 operations per sample of one created feature in a
+    screening pass (FMA = 2): the operator 1, the task sum 1, the centring 1,
+    the centred and the raw sums of squares 2 + 2, one product sum per
+    residual 2 nres."""
+    return 7 + 2 * nres
+
+
+def screen_cpu_baseline(w, target_s: float):
+    """The oracle (one process) creating and scoring the first candidates of
+    the workload's first operator, as many as fit in about target_s."""
+    import numpy as np
+    from oracle import sisso_ref as R
+
+    res = list(w.R)
+    done, t0 = 0, time.perf_counter()
+    while done < w.P and time.perf_counter() - t0 < target_s:
+        q = min(done + 256, w.P)
+        vals, ok = R.create(w.ops[0], w.X, w.pairs[done:q], w.lower, w.upper)
+        for v, good in zip(vals, ok):
+            if good:
+                R.sis_score(v, res, w.task_offsets)
+        done = q
+    dt = time.perf_counter() - t0
+    return dict(value=done / dt, unit="candidates/s", cores=1, kind="oracle",
+                sample=f"the first {done} '{w.ops[0]}' candidates of {w.meta['name']}, created, checked and "
+                       f"scored against {len(res)} residuals in {dt:.1f} s (numpy, one process)")
+
+
+def screen_golden_check(w, idx, score):
+    """Compare a top-m with the stored oracle result of the workload: the
+    same candidates except those tied with the m-th score within 1e-12,
+    scores to 1e-12 position by position."""
+    import numpy as np
+    from synth import screen_digest
+
+    path = os.path.join(ROOT, "tests", "golden", f"oracle_sis_{w.meta['name']}.json")
+    if not os.path.exists(path):
+        return None, f"no stored oracle result {os.path.basename(path)}"
+    g = json.load(open(path))
+    if g.get("input_sha256") != screen_digest(w):
+        return None, "regenerated inputs differ from the stored result's (sha256)"
+    gi, gs = [int(v) for v in idx], np.asarray(score, dtype=np.float64)
+    oi, osc = g["idx"], np.array(g["score"])
+    if len(gi) != len(oi):
+        return False, f"{len(gi)} selected against the oracle's {len(oi)}"
+    diff = float(np.max(np.abs(gs - osc))) if len(gi) else 0.0
+    sm = float(osc[-1]) if len(oi) else 0.0
+    gsc, osd = dict(zip(gi, gs)), dict(zip(oi, osc))
+    stray = [c for c in set(gi) - set(oi) if abs(gsc[c] - sm) > 1e-12] + \
+            [c for c in set(oi) - set(gi) if abs(osd[c] - sm) > 1e-12]
+    ok = bool(not stray and diff <= 1e-12)
+    order = "same order" if gi == oi else "same set up to near-ties" if set(gi) == set(oi) else "sets differ"
+    return ok, f"{os.path.basename(path)}: {order}, {len(stray)} outside the m-th tie band, max score diff {diff:.1e}"
+
+
+def bench_screen(args) -> int:
+    """One screening pass over a created rung (one GPU).
+
+    Step (the paper's form, features never stored): for each binary operator,
+    sisso_sis_score_op creates every child-pair candidate sample by sample,
+    applies the value rules and scores it against the residuals; then
+    sisso_topm selects the m best of all candidates (and synchronises).
+    Beside it, the stored form: the valid candidates are first written out
+    (sisso_fc_eval, untimed), then sisso_sis_score reads them from HBM and
+    sisso_topm selects.  Both forms must select the same candidates; the
+    fused form's selection is checked against the stored oracle result.
+    """
+    import numpy as np
+    import torch
+
+    from synth import make_screen_workload
+    from paper_2502_20072_amd import _binding as B
+
+    w = make_screen_workload(args.workload)
+    dev = "cuda:0"
+    X = torch.from_numpy(w.X).to(dev)
+    Rr = torch.from_numpy(w.R).to(dev)
+    pairs = torch.from_numpy(w.pairs).to(dev)
+    h = B.SisScreen(Rr, w.task_offsets)
+    P, nops, m = w.P, len(w.ops), w.m
+    M = P * nops
+    scores = torch.empty(M, dtype=torch.float64, device=dev)
+    out_idx = torch.empty(m, dtype=torch.int64, device=dev)
+    out_sc = torch.empty(m, dtype=torch.float64, device=dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * nops + 2)]
+    steps, warm = args.steps, args.warmup
+    kern_ms = np.zeros(nops)
+
+    def fused(record):
+        for o, op in enumerate(w.ops):
+            if record:
+                ev[2 * o].record()
+            h.score_op(op, X, pairs, w.lower, w.upper, scores[o * P:(o + 1) * P])
+            if record:
+                ev[2 * o + 1].record()
+        return B.sisso_topm(scores, m, out_idx, out_sc)
+
+    for _ in range(warm):
+        fused(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        cnt = fused(True)
+        kern_ms += [ev[2 * o].elapsed_time(ev[2 * o + 1]) for o in range(nops)]
+    torch.cuda.synchronize()
+    fused_ms = (time.perf_counter() - t0) * 1e3 / steps
+    kern_ms /= steps
+    f_idx, f_sc = out_idx[:cnt].cpu().numpy(), out_sc[:cnt].cpu().numpy()
+    n_valid = int(torch.isfinite(scores).sum())
+    ok, note = screen_golden_check(w, f_idx, f_sc)
+
+    # the stored form over the same candidates: the valid ones written out
+    valid = torch.empty(P, dtype=torch.uint8, device=dev)
+    cand = []
+    for o, op in enumerate(w.ops):
+        B.sisso_fc_eval(op, X, pairs, w.lower, w.upper, None, valid)
+        cand.append(torch.nonzero(valid, as_tuple=False).flatten() + o * P)
+    cand = torch.cat(cand)
+    Mv = int(cand.numel())
+    Xs = torch.empty((Mv, w.n), dtype=torch.float64, device=dev)
+    vtmp = torch.empty(Mv, dtype=torch.uint8, device=dev)
+    at = 0
+    for o, op in enumerate(w.ops):
+        sel = cand[(cand >= o * P) & (cand < (o + 1) * P)] - o * P
+        pv = pairs[sel].contiguous()
+        B.sisso_fc_eval(op, X, pv, w.lower, w.upper, Xs[at:at + pv.shape[0]], vtmp[at:at + pv.shape[0]])
+        at += pv.shape[0]
+    sscores = torch.empty(Mv, dtype=torch.float64, device=dev)
+    s_idx = torch.empty(m, dtype=torch.int64, device=dev)
+    s_sc = torch.empty(m, dtype=torch.float64, device=dev)
+
+    def stored(record):
+        if record:
+            ev[-2].record()
+        h.score(Xs, sscores)
+        if record:
+            ev[-1].record()
+        return B.sisso_topm(sscores, m, s_idx, s_sc)
+
+    for _ in range(warm):
+        stored(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    skern = 0.0
+    for _ in range(steps):
+        scnt = stored(True)
+        skern += ev[-2].elapsed_time(ev[-1])
+    torch.cuda.synchronize()
+    stored_ms = (time.perf_counter() - t0) * 1e3 / steps
+    skern /= steps
+    s_sel = cand[s_idx[:scnt]].cpu().numpy()
+    same = bool(np.array_equal(s_sel, f_idx) and np.array_equal(s_sc[:scnt].cpu().numpy(), f_sc))
+    h.close()
+
+    nres = int(w.R.shape[0])
+    flop = screen_flop_per_sample(nres) * w.n
+    fused_kern = float(kern_ms.sum())
+    achieved = M * flop / (fused_kern * 1e-3)
+    sbytes = Mv * (w.n * 8 + 8)
+    res = {
+        "metric": "SIS candidates screened/sec (created on the fly, scored against residuals, top-m)",
+        "value": M / (fused_ms * 1e-3), "unit": "candidates/s", "n_gpus": 1, "steps": steps, "warmup": warm,
+        "ms_per_step": fused_ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.meta["name"], "n": w.n, "T": w.meta["T"], "children": w.meta["Mc"],
+                   "ops": list(w.ops), "candidates": M, "nres": nres, "m": m},
+        "valid_candidates": n_valid, "topm_matches_oracle": ok, "oracle_check": note,
+        "kernel_ms": {op: float(t) for op, t in zip(w.ops, kern_ms)},
+        "roofline": {"bound": "alu", "kernel": "score_kernel (created)", "achieved": achieved / 1e12,
+                     "peak": FP64_PEAK / 1e12, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK, "traffic": None,
+                     "flop_per_sample": screen_flop_per_sample(nres), "kernel_ms": fused_kern},
+        "stored": {"ms_per_step": stored_ms, "candidates_per_s": Mv / (stored_ms * 1e-3), "features": Mv,
+                   "same_selection_as_fused": same,
+                   "roofline": {"bound": "hbm", "kernel": "score_kernel (stored)",
+                                "achieved": sbytes / (skern * 1e-3) / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                                "frac": sbytes / (skern * 1e-3) / HBM_PEAK, "traffic": None,
+                                "bytes_per_feature": w.n * 8 + 8, "kernel_ms": skern}},
+    }
+    if not args.no_cpu:
+        res["cpu_baseline"] = screen_cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(res), flush=True)
     return 0
 

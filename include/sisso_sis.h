@@ -72,7 +72,8 @@ enum {
  * so the order is the order of |r|; in general it is the share of the total
  * variation explained by a one-feature fit with an intercept per task.  A
  * feature that is constant on some task (|x_t - mean|^2 <= 1e-10 |x_t|^2,
- * the l0 search's rule) scores NaN and is never selected. */
+ * the l0 search's rule) or has a non-finite value scores NaN and is never
+ * selected. */
 typedef struct sisso_sis sisso_sis;
 
 typedef struct {

@@ -16,8 +16,8 @@ What it computes (paper, section "SISSO" and "Feature generation and SIS"):
   residuals (the paper keeps the residuals of the best few models of the
   previous dimension) a feature scores its best (largest) value over them.
   A feature that is constant on some task (centred sum of squares <= 1e-10
-  of its raw sum of squares there, the l0 search's rule) has no score (NaN)
-  and is never selected; a task where the residual is identically zero
+  of its raw sum of squares there, the l0 search's rule) or has a
+  non-finite value has no score (NaN) and is never selected; a task where the residual is identically zero
   contributes nothing.
 * Top-m selection: the m largest finite scores, ties by lower index, listed
   by (score descending, index ascending).
@@ -76,6 +76,8 @@ def sis_score(x, residuals: Sequence, offsets=None) -> float:
     on some task."""
     x = np.asarray(x, dtype=np.float64)
     offs = _offsets(len(x), offsets)
+    if not np.all(np.isfinite(x)):
+        return float("nan")  # eq. (1) is undefined for a non-finite value
     for a, b in zip(offs[:-1], offs[1:]):
         xt = x[a:b]
         c = xt - xt.sum() / len(xt)

@@ -8,6 +8,8 @@
 // is independent of the launch configuration.
 #include <hip/hip_runtime.h>
 #include <math.h>
+
+#include <algorithm>
 #include <stdint.h>
 
 #include "../../include/sisso_l0.h"
@@ -130,91 +132,198 @@ __global__ void __launch_bounds__(256) fc_eval_kernel(const double *__restrict__
 }
 
 // ------------------------------------------------------------- screening
-// One wave per feature.  Per task: pass A sums the feature's values (and,
-// for created features, the value-rule statistics); pass B accumulates the
-// centred sum of squares, the raw sum of squares and the centred cross
-// products with every (already centred) residual.  The score accumulates
-// sum_t cross_t^2 / xss_t per residual (= sum_t c_t r_t^2), divided by the
-// residual's total c at the end, maximum over residuals.
+// One lane per candidate feature, 64 candidates (a group) per wave.  The
+// wave walks the samples of each task in tiles of SC_TS: its lanes load the
+// group's 64 columns cooperatively (16 consecutive lanes read 16 consecutive
+// samples of one column, a 128-byte segment), create the values (the
+// operator, for created features) and write them transposed into a
+// wave-private LDS tile; each lane then reads its own feature's samples back
+// from the tile.  The residuals come from a sample-major copy whose address
+// is uniform across the wave, so they are scalar operands.  No cross-lane
+// reduction is needed: every sum is one lane's own.
+//
+// Per task, a feature's sums are shifted by its first sample K (u = v - K):
+// su = sum u, suu = sum u^2, sur_r = sum u rho_r over the task's rows.  Then
+// mean = K + su / n_t, the centred sum of squares is xss = suu - su^2 / n_t,
+// and since every residual is centred over the task, the centred cross
+// product is sur_r - (su / n_t) sum rho_r (the last sum is zero up to
+// rounding).  The shift keeps the cancellation in xss to the ratio suu / xss
+// = 1 + (mean - K)^2 / variance; where that ratio exceeds SC_REDO the task's
+// sums are taken again around the mean (a second pass over the task, which
+// every lane of the wave runs and only the lanes that need it keep).
+constexpr int SC_TS = 16;     // samples per tile
+constexpr int SC_LD = 66;     // LDS row stride of a tile (doubles): conflict-free writes and reads
+constexpr int SC_WPB = 4;     // waves per workgroup
+constexpr double SC_REDO = 1024.0;
+
+// The residual count of a kernel instantiation: nres rounded up to one of
+// these (the extra residuals are zero).
+__host__ __device__ constexpr int nr_pad(int nres) {
+    return nres <= 1 ? 1 : nres <= 2 ? 2 : nres <= 4 ? 4 : nres <= 8 ? 8 : nres <= 10 ? 10 : 16;
+}
+
+template <int OP, int NR>
+struct ScreenAcc {
+    double K, su, suu;
+    double sur[NR];
+};
+
+// Load one tile: samples [s0, s0 + cnt) of the group's 64 columns.  Lane l
+// fills sample s0 + (l & 15) of slot (l >> 4) + 4 q, q = 0..15.
 template <int OP>
-__global__ void __launch_bounds__(256) score_kernel(const double *__restrict__ X, int64_t n, int64_t Mc,
-                                                    const int32_t *__restrict__ pairs, int64_t P,
-                                                    const int64_t *__restrict__ off, int T,
-                                                    const double *__restrict__ Rc, const double *__restrict__ Ctot,
-                                                    int nres, double lower, double upper,
-                                                    double *__restrict__ scores, uint8_t *__restrict__ valid) {
-    const int lane = threadIdx.x & (WAVE - 1);
-    const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
-    const int64_t nw = (int64_t)gridDim.x * blockDim.x / WAVE;
-    for (int64_t f = wid; f < P; f += nw) {
-        Src<OP> s;
-        if (!source<OP>(X, n, Mc, pairs, f, s)) {
-            if (lane == 0) {
-                scores[f] = __builtin_nan("");
-                if (valid) valid[f] = 0;
-            }
-            continue;
-        }
-        double num[SISSO_SIS_MAX_RES];
+__device__ inline void screen_load(const double *__restrict__ X, const int64_t *__restrict__ ca,
+                                   const int64_t *__restrict__ cb, int64_t s0, int cnt, double *tile, int lane) {
+    const int s = lane & (SC_TS - 1);
+    if (s >= cnt) return;
 #pragma unroll
-        for (int r = 0; r < SISSO_SIS_MAX_RES; ++r) num[r] = 0.0;
-        bool fin = true, flat = false;
+    for (int q = 0; q < 16; ++q) {
+        const int slot = (lane >> 4) + 4 * q;
+        const double a = X[ca[slot] + s0 + s];
+        double v;
+        if constexpr (OP == OP_STORED) v = a;
+        else if constexpr (is_binary(OP)) v = apply<OP>(a, X[cb[slot] + s0 + s]);
+        else v = apply<OP>(a, 0.0);
+        tile[s * SC_LD + slot] = v;
+    }
+}
+
+__device__ inline void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One task's shifted sums over the tile samples [0, cnt) (REDO: only the
+// lanes with `keep` accumulate).  The value rules are tracked on the first
+// pass of created features.
+template <int OP, int NR, bool RULES, bool REDO, bool FULL>
+__device__ inline void screen_tile(const double *tile, int lane, const double *__restrict__ rt, int cnt,
+                                   ScreenAcc<OP, NR> &A, bool keep, bool &fin, double &amax, double &vmin,
+                                   double &vmax) {
+#pragma unroll
+    for (int j = 0; j < SC_TS; ++j) {
+        if (FULL || j < cnt) {
+            const double v = tile[j * SC_LD + lane];
+            const double u = REDO ? (keep ? v - A.K : 0.0) : v - A.K;
+            A.su += u;
+            A.suu = fma(u, u, A.suu);
+#pragma unroll
+            for (int r = 0; r < NR; ++r) A.sur[r] = fma(u, rt[j * NR + r], A.sur[r]);
+            if constexpr (RULES) {
+                fin = fin && isfinite(v);
+                amax = fmax(amax, fabs(v));
+                vmin = fmin(vmin, v);
+                vmax = fmax(vmax, v);
+            }
+        }
+    }
+}
+
+template <int OP, int NR>
+__global__ void __launch_bounds__(256) screen_kernel(const double *__restrict__ X, int64_t n, int64_t Mc,
+                                                     const int32_t *__restrict__ pairs, int64_t P,
+                                                     const int64_t *__restrict__ off, int T,
+                                                     const double *__restrict__ Rt, const double *__restrict__ Rsum,
+                                                     const double *__restrict__ Ctot, int nres, double lower,
+                                                     double upper, double *__restrict__ scores,
+                                                     uint8_t *__restrict__ valid) {
+    constexpr bool RULES = OP != OP_STORED;
+    __shared__ double tiles[SC_WPB][SC_TS * SC_LD];
+    __shared__ int64_t cols[SC_WPB][2][WAVE];
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    double *tile = tiles[wv];
+    int64_t *ca = cols[wv][0], *cb = cols[wv][1];
+    const int64_t groups = (P + WAVE - 1) / WAVE;
+    const int64_t nwaves = (int64_t)gridDim.x * SC_WPB;
+    for (int64_t g = (int64_t)blockIdx.x * SC_WPB + wv; g < groups; g += nwaves) {
+        const int64_t f = g * WAVE + lane;
+        // the lane's columns; a lane past P or with an index out of range
+        // loads column 0 (Mc >= 1) and is not scored
+        bool live = f < P, good = live;
+        int64_t oa = 0, ob = 0;
+        if (live) {
+            if constexpr (OP == OP_STORED) {
+                oa = f * n;
+            } else {
+                const int32_t ia = pairs[2 * f], ib = pairs[2 * f + 1];
+                good = ia >= 0 && ia < Mc && (!is_binary(OP) || (ib >= 0 && ib < Mc));
+                if (good) {
+                    oa = (int64_t)ia * n;
+                    ob = is_binary(OP) ? (int64_t)ib * n : 0;
+                }
+            }
+        }
+        ca[lane] = oa;
+        cb[lane] = ob;
+        wave_lds_sync();
+        double num[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) num[r] = 0.0;
+        bool fin = true, flat = false, nonfinite = false;
         double amax = 0.0, vmin = INFINITY, vmax = -INFINITY;
         for (int t = 0; t < T; ++t) {
             const int64_t r0 = off[t], r1 = off[t + 1];
-            double sum = 0.0;
-            for (int64_t i = r0 + lane; i < r1; i += WAVE) {
-                const double v = s.at(i);
-                sum += v;
-                if constexpr (OP != OP_STORED) {
-                    fin = fin && isfinite(v);
-                    amax = fmax(amax, fabs(v));
-                    vmin = fmin(vmin, v);
-                    vmax = fmax(vmax, v);
+            ScreenAcc<OP, NR> A;
+            A.su = A.suu = 0.0;
+#pragma unroll
+            for (int r = 0; r < NR; ++r) A.sur[r] = 0.0;
+            for (int64_t s0 = r0; s0 < r1; s0 += SC_TS) {
+                const int cnt = (int)(r1 - s0 < SC_TS ? r1 - s0 : SC_TS);
+                screen_load<OP>(X, ca, cb, s0, cnt, tile, lane);
+                wave_lds_sync();
+                if (s0 == r0) A.K = tile[lane];
+                if (cnt == SC_TS)
+                    screen_tile<OP, NR, RULES, false, true>(tile, lane, Rt + s0 * NR, cnt, A, true, fin, amax, vmin,
+                                                            vmax);
+                else
+                    screen_tile<OP, NR, RULES, false, false>(tile, lane, Rt + s0 * NR, cnt, A, true, fin, amax,
+                                                             vmin, vmax);
+                wave_lds_sync();
+            }
+            const double nt = (double)(r1 - r0);
+            double mu = A.su / nt, xss = A.suu - A.su * mu;
+            // heavy cancellation: the task again, around the mean
+            const bool redo = good && isfinite(xss) && A.suu > SC_REDO * xss;
+            if (__any(redo)) {
+                if (redo) {
+                    A.K += mu;
+                    A.su = A.suu = 0.0;
+#pragma unroll
+                    for (int r = 0; r < NR; ++r) A.sur[r] = 0.0;
                 }
+                for (int64_t s0 = r0; s0 < r1; s0 += SC_TS) {
+                    const int cnt = (int)(r1 - s0 < SC_TS ? r1 - s0 : SC_TS);
+                    screen_load<OP>(X, ca, cb, s0, cnt, tile, lane);
+                    wave_lds_sync();
+                    screen_tile<OP, NR, false, true, false>(tile, lane, Rt + s0 * NR, cnt, A, redo, fin, amax,
+                                                            vmin, vmax);
+                    wave_lds_sync();
+                }
+                mu = A.su / nt;
+                xss = A.suu - A.su * mu;
             }
-            if constexpr (OP != OP_STORED) {
-                if (!__all(fin)) break;  // a non-finite value: no score
-            }
-            const double mean = wave_sum(sum) / (double)(r1 - r0);
-            double xss = 0.0, raw = 0.0;
-            double cr[SISSO_SIS_MAX_RES];
-#pragma unroll
-            for (int r = 0; r < SISSO_SIS_MAX_RES; ++r) cr[r] = 0.0;
-            for (int64_t i = r0 + lane; i < r1; i += WAVE) {
-                const double v = s.at(i);
-                const double d = v - mean;
-                xss += d * d;
-                raw += v * v;
-#pragma unroll
-                for (int r = 0; r < SISSO_SIS_MAX_RES; ++r)
-                    if (r < nres) cr[r] += d * Rc[(int64_t)r * n + i];
-            }
-            xss = wave_sum(xss);
-            raw = wave_sum(raw);
+            const double raw = A.suu + A.K * (2.0 * A.su + nt * A.K);  // sum of v^2
+            if (!(isfinite(A.su) && isfinite(A.suu) && isfinite(A.K))) nonfinite = true;
             if (xss <= RANK_EPS * raw) flat = true;  // constant on this task
+            const double inv = xss > 0.0 ? 1.0 / xss : 0.0;
 #pragma unroll
-            for (int r = 0; r < SISSO_SIS_MAX_RES; ++r) {
+            for (int r = 0; r < NR; ++r) {
+                const double c = A.sur[r] - mu * Rsum[t * NR + r];
+                num[r] = fma(c * c, inv, num[r]);
+            }
+        }
+        if (live) {
+            bool ok = fin && good;
+            if constexpr (RULES) ok = ok && amax >= lower && amax <= upper && vmin != vmax;
+            double best = -INFINITY;
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
                 if (r < nres) {
-                    const double c = wave_sum(cr[r]);
-                    if (xss > 0.0) num[r] += c * c / xss;
+                    const double c = Ctot[r];
+                    best = fmax(best, c > 0.0 ? num[r] / c : 0.0);
                 }
             }
-        }
-        bool ok = __all(fin);
-        if constexpr (OP != OP_STORED) {
-            amax = wave_max(amax);
-            vmin = wave_min(vmin);
-            vmax = wave_max(vmax);
-            ok = ok && amax >= lower && amax <= upper && vmin != vmax;
-        }
-        if (lane == 0) {
-            double best = -INFINITY;
-            for (int r = 0; r < nres; ++r) {
-                const double c = Ctot[r];
-                best = fmax(best, c > 0.0 ? num[r] / c : 0.0);
-            }
-            scores[f] = (ok && !flat) ? best + 0.0 : __builtin_nan("");
+            scores[f] = (ok && !flat && !nonfinite) ? best + 0.0 : __builtin_nan("");
             if (valid) valid[f] = ok ? 1 : 0;
         }
     }
@@ -222,10 +331,12 @@ __global__ void __launch_bounds__(256) score_kernel(const double *__restrict__ X
 
 // -------------------------------------------------- residual preparation
 // One wave per (residual, task): rho_c = rho - mean over the task's rows,
-// and c = |rho_c|^2 into ctask[r * T + t].
+// c = |rho_c|^2 into ctask[r * T + t] and the sum of rho_c (zero up to
+// rounding) into rsum[t * NR + r].
 __global__ void __launch_bounds__(256) centre_kernel(const double *__restrict__ R, int64_t n,
-                                                     const int64_t *__restrict__ off, int T, int nres,
-                                                     double *__restrict__ Rc, double *__restrict__ ctask) {
+                                                     const int64_t *__restrict__ off, int T, int nres, int NR,
+                                                     double *__restrict__ Rc, double *__restrict__ ctask,
+                                                     double *__restrict__ rsum) {
     const int lane = threadIdx.x & (WAVE - 1);
     const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
     if (w >= (int64_t)nres * T) return;
@@ -236,14 +347,32 @@ __global__ void __launch_bounds__(256) centre_kernel(const double *__restrict__ 
     double sum = 0.0;
     for (int64_t i = r0 + lane; i < r1; i += WAVE) sum += x[i];
     const double mean = wave_sum(sum) / (double)(r1 - r0);
-    double ss = 0.0;
+    double ss = 0.0, sc = 0.0;
     for (int64_t i = r0 + lane; i < r1; i += WAVE) {
         const double d = x[i] - mean;
         y[i] = d;
         ss += d * d;
+        sc += d;
     }
     ss = wave_sum(ss);
-    if (lane == 0) ctask[w] = ss;
+    sc = wave_sum(sc);
+    if (lane == 0) {
+        ctask[w] = ss;
+        rsum[t * NR + r] = sc;
+    }
+}
+
+// The sample-major copy Rt[i * NR + r] of the centred residuals (zero for
+// r >= nres) and the zero task sums of those padding residuals.
+__global__ void __launch_bounds__(256) transpose_kernel(const double *__restrict__ Rc, int64_t n, int T, int nres,
+                                                        int NR, double *__restrict__ Rt, double *__restrict__ rsum) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n * NR) {
+        const int64_t i = e / NR;
+        const int r = (int)(e % NR);
+        Rt[e] = r < nres ? Rc[(int64_t)r * n + i] : 0.0;
+    }
+    if (e < (int64_t)T * NR && (int)(e % NR) >= nres) rsum[e] = 0.0;
 }
 
 // Totals over tasks, in task order.
@@ -443,10 +572,24 @@ static unsigned grid_for(int64_t items, int per_block) {
     return (unsigned)(b < 1 ? 1 : (b > 8192 ? 8192 : b));
 }
 
+template <int OP, int NR>
+static void launch_screen_nr(const ScoreArgs &a, hipStream_t st) {
+    const int64_t groups = (a.P + WAVE - 1) / WAVE;
+    hipLaunchKernelGGL((screen_kernel<OP, NR>), dim3(grid_for(groups, SC_WPB)), dim3(SC_WPB * WAVE), 0, st, a.X, a.n,
+                       a.Mc, a.pairs, a.P, a.off, a.T, a.Rt, a.Rsum, a.Ctot, a.nres, a.lower, a.upper, a.scores,
+                       a.valid);
+}
+
 template <int OP>
 static void launch_score_op(const ScoreArgs &a, hipStream_t st) {
-    hipLaunchKernelGGL((score_kernel<OP>), dim3(grid_for(a.P, 4)), dim3(256), 0, st, a.X, a.n, a.Mc, a.pairs, a.P,
-                       a.off, a.T, a.Rc, a.Ctot, a.nres, a.lower, a.upper, a.scores, a.valid);
+    switch (nr_pad(a.nres)) {
+        case 1: launch_screen_nr<OP, 1>(a, st); break;
+        case 2: launch_screen_nr<OP, 2>(a, st); break;
+        case 4: launch_screen_nr<OP, 4>(a, st); break;
+        case 8: launch_screen_nr<OP, 8>(a, st); break;
+        case 10: launch_screen_nr<OP, 10>(a, st); break;
+        default: launch_screen_nr<OP, 16>(a, st); break;
+    }
 }
 
 template <int OP>
@@ -493,13 +636,19 @@ int launch_fc(int op, const FcArgs &a, hipStream_t st) {
 }
 
 int launch_centre(const double *R, int64_t n, const int64_t *off, int T, int nres, double *Rc, double *ctask,
-                  double *ctot, hipStream_t st) {
+                  double *ctot, double *Rt, double *rsum, hipStream_t st) {
+    const int NR = nr_pad(nres);
     const int64_t waves = (int64_t)nres * T;
-    hipLaunchKernelGGL(centre_kernel, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, R, n, off, T, nres, Rc,
-                       ctask);
+    hipLaunchKernelGGL(centre_kernel, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, R, n, off, T, nres, NR, Rc,
+                       ctask, rsum);
     hipLaunchKernelGGL(ctot_kernel, dim3(1), dim3(64), 0, st, ctask, T, nres, ctot);
+    const int64_t e = std::max<int64_t>(n * NR, (int64_t)T * NR);
+    hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)((e + 255) / 256)), dim3(256), 0, st, Rc, n, T, nres, NR, Rt,
+                       rsum);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
+
+int residual_width(int nres) { return nr_pad(nres); }
 
 int launch_residuals(const double *F, const double *y, int64_t n, const int64_t *off, int T, const int32_t *idx,
                      const double *coef, int r, int D, double *R, hipStream_t st) {

@@ -17,3 +17,10 @@ from .problems import (  # noqa: F401
     integer_problem,
     input_digest,
 )
+from .screening import (  # noqa: F401
+    SCREEN_CONFIGS,
+    ScreenWorkload,
+    all_pairs,
+    make_screen_workload,
+    screen_digest,
+)

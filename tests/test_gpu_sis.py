@@ -26,7 +26,7 @@ def _problem(seed, S, n, T):
     return tiny_problem(seed, S=S, n=n, T=T, D=2, sigma=0.5, task_sizes=sizes)
 
 
-@pytest.mark.parametrize("T,nres", [(1, 1), (1, 4), (3, 1), (3, 3)])
+@pytest.mark.parametrize("T,nres", [(1, 1), (1, 4), (3, 1), (3, 3), (1, 5), (2, 10), (1, 16)])
 def test_sis_scores_match_oracle(T, nres):
     import torch
     from paper_2502_20072_amd import _binding as B
@@ -43,6 +43,44 @@ def test_sis_scores_match_oracle(T, nres):
     h.close()
     ref = R.sis_scores(F, res, p.task_offsets)
     assert np.array_equal(np.isnan(got), np.isnan(ref)) and np.isnan(got[3])
+    live = ~np.isnan(ref)
+    np.testing.assert_allclose(got[live], ref[live], rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("T", [1, 2])
+def test_sis_scores_shift_and_cancellation_edges(T):
+    """Features whose shifted sums cancel heavily (a spike on the first
+    sample of a task with n_t > 1024, a large offset), constant and
+    non-finite stored features, and a partial last group of candidates."""
+    import torch
+    from paper_2502_20072_amd import _binding as B
+    n = 3000
+    offs = np.array([0, n], dtype=np.int64) if T == 1 else np.array([0, 1300, n], dtype=np.int64)
+    rng = np.random.default_rng(40 + T)
+    F = rng.normal(size=(70, n))
+    for t in range(T):
+        a, b = offs[t], offs[t + 1]
+        F[0, a:b] = 0.0
+        F[0, a] = 1.0                                   # one-hot spike on the task's first sample
+        F[1, a:b] = rng.normal(0, 1e-3, b - a)
+        F[1, a] = 5.0                                   # spike over small noise
+    F[2] = 1e6 + rng.normal(size=n)                     # large offset, unit spread
+    F[3] = 1e6 * rng.normal(size=n) + 3e9               # large values, large offset
+    F[4] = -2.5                                         # constant everywhere
+    F[5, offs[-2]:] = 0.125                             # constant on the last task
+    F[6, 11] = np.inf                                   # non-finite values
+    F[7, n - 1] = np.nan
+    F[8] = rng.normal(size=n) * 1e-150                  # tiny but not constant
+    res = [rng.normal(size=n) + F[9] * 0.5, F[10] - 0.3 * F[0], rng.normal(size=n)]
+    _say(f"shift/cancellation edges T={T} n={n} M={F.shape[0]}")
+    h = B.SisScreen(_d(np.array(res)), offs)
+    out = torch.empty(F.shape[0], dtype=torch.float64, device="cuda:0")
+    h.score(_d(F), out)
+    got = out.cpu().numpy()
+    h.close()
+    ref = R.sis_scores(F, res, offs)
+    assert np.array_equal(np.isnan(got), np.isnan(ref)), (np.flatnonzero(np.isnan(got)), np.flatnonzero(np.isnan(ref)))
+    assert all(np.isnan(got[[4, 5, 6, 7]]))
     live = ~np.isnan(ref)
     np.testing.assert_allclose(got[live], ref[live], rtol=0, atol=1e-12)
 

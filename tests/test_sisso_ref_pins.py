@@ -226,3 +226,14 @@ def test_planted_mistake_is_caught(monkeypatch, name, attr, fn):
     monkeypatch.setitem(R.__dict__, "_orig_sis_score", R.sis_score)
     monkeypatch.setattr(R, attr, fn)
     assert not _pins_pass(), f"planted mistake {name} passes every pin"
+
+
+def test_sis_score_non_finite_feature_has_no_score():
+    """Eq. (1) is undefined for a feature with a non-finite value: no score,
+    whatever the residuals."""
+    rng = np.random.default_rng(3)
+    y = rng.normal(size=40)
+    for bad in (np.inf, -np.inf, np.nan):
+        x = rng.normal(size=40)
+        x[17] = bad
+        assert math.isnan(R.sis_score(x, [y, y * 2.0 + 1.0]))
