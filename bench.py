@@ -644,14 +644,17 @@ def bench_screen(args) -> int:
                    "ops": list(w.ops), "candidates": M, "nres": nres, "m": m},
         "valid_candidates": n_valid, "topm_matches_oracle": ok, "oracle_check": note,
         "kernel_ms": {op: float(t) for op, t in zip(w.ops, kern_ms)},
-        "roofline": {"bound": "alu", "kernel": "score_kernel (created)", "achieved": achieved / 1e12,
-                     "peak": FP64_PEAK / 1e12, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK, "traffic": None,
+        "roofline": {"bound": "alu", "kernel": "screen_kernel (created features, 5 launches)",
+                     "achieved": achieved / 1e12, "peak": FP64_PEAK / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_PEAK,
+                     "traffic": measured_traffic("screen_kernel_created", w.meta["name"]),
                      "flop_per_sample": screen_flop_per_sample(nres), "kernel_ms": fused_kern},
         "stored": {"ms_per_step": stored_ms, "candidates_per_s": Mv / (stored_ms * 1e-3), "features": Mv,
                    "same_selection_as_fused": same,
-                   "roofline": {"bound": "hbm", "kernel": "score_kernel (stored)",
+                   "roofline": {"bound": "hbm", "kernel": "screen_kernel (stored features)",
                                 "achieved": sbytes / (skern * 1e-3) / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                                "frac": sbytes / (skern * 1e-3) / HBM_PEAK, "traffic": None,
+                                "frac": sbytes / (skern * 1e-3) / HBM_PEAK,
+                                "traffic": measured_traffic("screen_kernel_stored", w.meta["name"]),
                                 "bytes_per_feature": w.n * 8 + 8, "kernel_ms": skern}},
     }
     if not args.no_cpu:

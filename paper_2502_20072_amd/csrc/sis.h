@@ -14,8 +14,9 @@ struct ScoreArgs {
     int64_t P;             // features or candidates to score
     const int64_t *off;    // device task offsets [T+1]
     int T;
-    const double *Rt;      // centred residuals, sample-major n x residual_width(nres), zero-padded
-    const double *Rsum;    // [T][residual_width(nres)] task sums of the centred residuals
+    const double *Rc;      // centred residuals, residual_width(nres) rows of stride ldr (zero-padded)
+    int64_t ldr;
+    const double *Rsum;    // [T][residual_width(nres)] task sums of the centred residuals (zero-padded)
     const double *Ctot;    // [nres] total sum of squares of each residual
     int nres;
     double lower, upper;   // value rules (created features)
@@ -38,12 +39,14 @@ constexpr int OP_STORED_FEATURES = -1;
 bool op_known(int op);
 int launch_score(int op, const ScoreArgs &a, hipStream_t st);  // op = OP_STORED_FEATURES for stored columns
 int launch_fc(int op, const FcArgs &a, hipStream_t st);
-// Residuals nres x n are centred per task into Rc (and copied sample-major
-// into Rt, n x residual_width(nres)); ctask[r * T + t] their per-task sums of
-// squares, ctot[r] the totals, rsum[t * width + r] the task sums of Rc.
+// Residuals nres x n are centred per task into Rc (residual_width(nres) rows
+// of stride residual_stride(n), padding zero); ctask[r * T + t] gets their
+// per-task sums of squares, ctot[r] the totals, rsum[t * width + r] the task
+// sums of Rc (zero for r >= nres).
 int launch_centre(const double *R, int64_t n, const int64_t *off, int T, int nres, double *Rc, double *ctask,
-                  double *ctot, double *Rt, double *rsum, hipStream_t st);
-int residual_width(int nres);  // residuals in Rt per sample: nres rounded up to 1, 2, 4, 8, 10 or 16
+                  double *ctot, double *rsum, hipStream_t st);
+int residual_width(int nres);        // nres rounded up to 1, 2, 4, 8, 10 or 16
+int64_t residual_stride(int64_t n);  // row stride of the centred residuals
 int launch_residuals(const double *F, const double *y, int64_t n, const int64_t *off, int T, const int32_t *idx,
                      const double *coef, int r, int D, double *R, hipStream_t st);
 size_t topm_ws_bytes(int64_t M, int m);

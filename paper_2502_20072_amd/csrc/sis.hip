@@ -9,7 +9,6 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
-#include <algorithm>
 #include <stdint.h>
 
 #include "../../include/sisso_l0.h"
@@ -135,11 +134,13 @@ __global__ void __launch_bounds__(256) fc_eval_kernel(const double *__restrict__
 // One lane per candidate feature, 64 candidates (a group) per wave.  The
 // wave walks the samples of each task in tiles of SC_TS: its lanes load the
 // group's 64 columns cooperatively (16 consecutive lanes read 16 consecutive
-// samples of one column, a 128-byte segment), create the values (the
-// operator, for created features) and write them transposed into a
-// wave-private LDS tile; each lane then reads its own feature's samples back
-// from the tile.  The residuals come from a sample-major copy whose address
-// is uniform across the wave, so they are scalar operands.  No cross-lane
+// samples of one column, a 128-byte segment; a group whose candidates share
+// their first child reads that child's segment once), create the values
+// (the operator, for created features) and write them transposed into a
+// wave-private LDS tile; each lane then reads its own feature's 16 values
+// back into registers.  The residuals are then taken residual by residual,
+// 16 consecutive samples at a time, from addresses uniform across the wave:
+// scalar operands, never waited for together with LDS reads.  No cross-lane
 // reduction is needed: every sum is one lane's own.
 //
 // Per task, a feature's sums are shifted by its first sample K (u = v - K):
@@ -148,33 +149,41 @@ __global__ void __launch_bounds__(256) fc_eval_kernel(const double *__restrict__
 // and since every residual is centred over the task, the centred cross
 // product is sur_r - (su / n_t) sum rho_r (the last sum is zero up to
 // rounding).  The shift keeps the cancellation in xss to the ratio suu / xss
-// = 1 + (mean - K)^2 / variance; where that ratio exceeds SC_REDO the task's
-// sums are taken again around the mean (a second pass over the task, which
-// every lane of the wave runs and only the lanes that need it keep).
+// = 1 + n_t (mean - K)^2 / xss <= 1 + n_t; where that ratio exceeds SC_REDO
+// for some lane, the wave takes the task's sums again with those lanes
+// shifted by their mean (the other lanes repeat the same arithmetic and get
+// the same sums).
 constexpr int SC_TS = 16;     // samples per tile
 constexpr int SC_LD = 66;     // LDS row stride of a tile (doubles): conflict-free writes and reads
 constexpr int SC_WPB = 4;     // waves per workgroup
 constexpr double SC_REDO = 1024.0;
 
-// The residual count of a kernel instantiation: nres rounded up to one of
-// these (the extra residuals are zero).
+// The residual count of a kernel instantiation: nres rounded up to 1, 2, 4,
+// 8, 10 or 16 (the padding residuals are zero).
 __host__ __device__ constexpr int nr_pad(int nres) {
     return nres <= 1 ? 1 : nres <= 2 ? 2 : nres <= 4 ? 4 : nres <= 8 ? 8 : nres <= 10 ? 10 : 16;
 }
 
-template <int OP, int NR>
-struct ScreenAcc {
-    double K, su, suu;
-    double sur[NR];
-};
-
 // Load one tile: samples [s0, s0 + cnt) of the group's 64 columns.  Lane l
-// fills sample s0 + (l & 15) of slot (l >> 4) + 4 q, q = 0..15.
+// fills sample s0 + (l & 15) of slot (l >> 4) + 4 q, q = 0..15.  ua >= 0:
+// every slot's first child is column ua (read once per lane).
 template <int OP>
 __device__ inline void screen_load(const double *__restrict__ X, const int64_t *__restrict__ ca,
-                                   const int64_t *__restrict__ cb, int64_t s0, int cnt, double *tile, int lane) {
+                                   const int64_t *__restrict__ cb, int64_t ua, int64_t s0, int cnt, double *tile,
+                                   int lane) {
     const int s = lane & (SC_TS - 1);
     if (s >= cnt) return;
+    if constexpr (is_binary(OP)) {
+        if (ua >= 0) {
+            const double a = X[ua + s0 + s];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int slot = (lane >> 4) + 4 * q;
+                tile[s * SC_LD + slot] = apply<OP>(a, X[cb[slot] + s0 + s]);
+            }
+            return;
+        }
+    }
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
         const int slot = (lane >> 4) + 4 * q;
@@ -193,29 +202,64 @@ __device__ inline void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// One task's shifted sums over the tile samples [0, cnt) (REDO: only the
-// lanes with `keep` accumulate).  The value rules are tracked on the first
-// pass of created features.
-template <int OP, int NR, bool RULES, bool REDO, bool FULL>
-__device__ inline void screen_tile(const double *tile, int lane, const double *__restrict__ rt, int cnt,
-                                   ScreenAcc<OP, NR> &A, bool keep, bool &fin, double &amax, double &vmin,
-                                   double &vmax) {
+template <int NR>
+struct ScreenSums {
+    double su, suu;
+    double sur[NR];
+};
+
+// The sums over the tile samples [0, cnt) (all SC_TS when FULL).  rc:
+// residual 0 at the tile's first sample, residual r at rc + r ldr; 16
+// samples from there are always readable (rows are padded), and u = 0 past
+// cnt adds nothing.  RULES: track the value rules.
+template <int NR, bool RULES, bool FULL>
+__device__ inline void screen_tile(const double *tile, int lane, const double *__restrict__ rc, int64_t ldr,
+                                   int cnt, double K, ScreenSums<NR> &A, bool &fin, double &vmin, double &vmax) {
+    double u[SC_TS];
 #pragma unroll
     for (int j = 0; j < SC_TS; ++j) {
+        u[j] = 0.0;
         if (FULL || j < cnt) {
             const double v = tile[j * SC_LD + lane];
-            const double u = REDO ? (keep ? v - A.K : 0.0) : v - A.K;
-            A.su += u;
-            A.suu = fma(u, u, A.suu);
-#pragma unroll
-            for (int r = 0; r < NR; ++r) A.sur[r] = fma(u, rt[j * NR + r], A.sur[r]);
+            u[j] = v - K;
+            A.su += u[j];
+            A.suu = fma(u[j], u[j], A.suu);
             if constexpr (RULES) {
                 fin = fin && isfinite(v);
-                amax = fmax(amax, fabs(v));
                 vmin = fmin(vmin, v);
                 vmax = fmax(vmax, v);
             }
         }
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const double *rr = rc + (int64_t)r * ldr;
+#pragma unroll
+        for (int j = 0; j < SC_TS; ++j) A.sur[r] = fma(u[j], rr[j], A.sur[r]);
+    }
+}
+
+// One pass over the rows [r0, r1) of a task.  FIRST: K is set to the
+// lane's first value and the value rules are tracked.
+template <int OP, int NR, bool FIRST>
+__device__ inline void screen_pass(const double *__restrict__ X, const int64_t *__restrict__ ca,
+                                   const int64_t *__restrict__ cb, int64_t ua, int64_t r0, int64_t r1,
+                                   const double *__restrict__ Rc, int64_t ldr, double *tile, int lane, double &K,
+                                   ScreenSums<NR> &A, bool &fin, double &vmin, double &vmax) {
+    constexpr bool RULES = FIRST && OP != OP_STORED;
+    A.su = A.suu = 0.0;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) A.sur[r] = 0.0;
+    for (int64_t s0 = r0; s0 < r1; s0 += SC_TS) {
+        const int cnt = (int)(r1 - s0 < SC_TS ? r1 - s0 : SC_TS);
+        screen_load<OP>(X, ca, cb, ua, s0, cnt, tile, lane);
+        wave_lds_sync();
+        if (FIRST && s0 == r0) K = tile[lane];
+        if (cnt == SC_TS)
+            screen_tile<NR, RULES, true>(tile, lane, Rc + s0, ldr, cnt, K, A, fin, vmin, vmax);
+        else
+            screen_tile<NR, RULES, false>(tile, lane, Rc + s0, ldr, cnt, K, A, fin, vmin, vmax);
+        wave_lds_sync();
     }
 }
 
@@ -223,11 +267,11 @@ template <int OP, int NR>
 __global__ void __launch_bounds__(256) screen_kernel(const double *__restrict__ X, int64_t n, int64_t Mc,
                                                      const int32_t *__restrict__ pairs, int64_t P,
                                                      const int64_t *__restrict__ off, int T,
-                                                     const double *__restrict__ Rt, const double *__restrict__ Rsum,
+                                                     const double *__restrict__ Rc, int64_t ldr,
+                                                     const double *__restrict__ Rsum,
                                                      const double *__restrict__ Ctot, int nres, double lower,
                                                      double upper, double *__restrict__ scores,
                                                      uint8_t *__restrict__ valid) {
-    constexpr bool RULES = OP != OP_STORED;
     __shared__ double tiles[SC_WPB][SC_TS * SC_LD];
     __shared__ int64_t cols[SC_WPB][2][WAVE];
     const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
@@ -255,55 +299,33 @@ __global__ void __launch_bounds__(256) screen_kernel(const double *__restrict__ 
         }
         ca[lane] = oa;
         cb[lane] = ob;
+        // one first child for the whole group (the usual case of pair lists
+        // in lexicographic order)
+        const int64_t oa0 = __shfl(oa, 0, WAVE);
+        const int64_t ua = (is_binary(OP) && __all(good && oa == oa0)) ? oa0 : -1;
         wave_lds_sync();
         double num[NR];
 #pragma unroll
         for (int r = 0; r < NR; ++r) num[r] = 0.0;
         bool fin = true, flat = false, nonfinite = false;
-        double amax = 0.0, vmin = INFINITY, vmax = -INFINITY;
+        double vmin = INFINITY, vmax = -INFINITY;
         for (int t = 0; t < T; ++t) {
             const int64_t r0 = off[t], r1 = off[t + 1];
-            ScreenAcc<OP, NR> A;
-            A.su = A.suu = 0.0;
-#pragma unroll
-            for (int r = 0; r < NR; ++r) A.sur[r] = 0.0;
-            for (int64_t s0 = r0; s0 < r1; s0 += SC_TS) {
-                const int cnt = (int)(r1 - s0 < SC_TS ? r1 - s0 : SC_TS);
-                screen_load<OP>(X, ca, cb, s0, cnt, tile, lane);
-                wave_lds_sync();
-                if (s0 == r0) A.K = tile[lane];
-                if (cnt == SC_TS)
-                    screen_tile<OP, NR, RULES, false, true>(tile, lane, Rt + s0 * NR, cnt, A, true, fin, amax, vmin,
-                                                            vmax);
-                else
-                    screen_tile<OP, NR, RULES, false, false>(tile, lane, Rt + s0 * NR, cnt, A, true, fin, amax,
-                                                             vmin, vmax);
-                wave_lds_sync();
-            }
             const double nt = (double)(r1 - r0);
+            ScreenSums<NR> A;
+            double K = 0.0;
+            screen_pass<OP, NR, true>(X, ca, cb, ua, r0, r1, Rc, ldr, tile, lane, K, A, fin, vmin, vmax);
             double mu = A.su / nt, xss = A.suu - A.su * mu;
             // heavy cancellation: the task again, around the mean
             const bool redo = good && isfinite(xss) && A.suu > SC_REDO * xss;
             if (__any(redo)) {
-                if (redo) {
-                    A.K += mu;
-                    A.su = A.suu = 0.0;
-#pragma unroll
-                    for (int r = 0; r < NR; ++r) A.sur[r] = 0.0;
-                }
-                for (int64_t s0 = r0; s0 < r1; s0 += SC_TS) {
-                    const int cnt = (int)(r1 - s0 < SC_TS ? r1 - s0 : SC_TS);
-                    screen_load<OP>(X, ca, cb, s0, cnt, tile, lane);
-                    wave_lds_sync();
-                    screen_tile<OP, NR, false, true, false>(tile, lane, Rt + s0 * NR, cnt, A, redo, fin, amax,
-                                                            vmin, vmax);
-                    wave_lds_sync();
-                }
+                if (redo) K += mu;
+                screen_pass<OP, NR, false>(X, ca, cb, ua, r0, r1, Rc, ldr, tile, lane, K, A, fin, vmin, vmax);
                 mu = A.su / nt;
                 xss = A.suu - A.su * mu;
             }
-            const double raw = A.suu + A.K * (2.0 * A.su + nt * A.K);  // sum of v^2
-            if (!(isfinite(A.su) && isfinite(A.suu) && isfinite(A.K))) nonfinite = true;
+            const double raw = A.suu + K * (2.0 * A.su + nt * K);  // sum of v^2
+            if (!(isfinite(A.su) && isfinite(A.suu) && isfinite(K))) nonfinite = true;
             if (xss <= RANK_EPS * raw) flat = true;  // constant on this task
             const double inv = xss > 0.0 ? 1.0 / xss : 0.0;
 #pragma unroll
@@ -314,7 +336,10 @@ __global__ void __launch_bounds__(256) screen_kernel(const double *__restrict__ 
         }
         if (live) {
             bool ok = fin && good;
-            if constexpr (RULES) ok = ok && amax >= lower && amax <= upper && vmin != vmax;
+            if constexpr (OP != OP_STORED) {
+                const double amax = fmax(fabs(vmin), fabs(vmax));  // the largest |v|
+                ok = ok && amax >= lower && amax <= upper && vmin != vmax;
+            }
             double best = -INFINITY;
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
@@ -335,15 +360,15 @@ __global__ void __launch_bounds__(256) screen_kernel(const double *__restrict__ 
 // rounding) into rsum[t * NR + r].
 __global__ void __launch_bounds__(256) centre_kernel(const double *__restrict__ R, int64_t n,
                                                      const int64_t *__restrict__ off, int T, int nres, int NR,
-                                                     double *__restrict__ Rc, double *__restrict__ ctask,
-                                                     double *__restrict__ rsum) {
+                                                     double *__restrict__ Rc, int64_t ldr,
+                                                     double *__restrict__ ctask, double *__restrict__ rsum) {
     const int lane = threadIdx.x & (WAVE - 1);
     const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
     if (w >= (int64_t)nres * T) return;
     const int r = (int)(w / T), t = (int)(w % T);
     const int64_t r0 = off[t], r1 = off[t + 1];
     const double *x = R + (int64_t)r * n;
-    double *y = Rc + (int64_t)r * n;
+    double *y = Rc + (int64_t)r * ldr;
     double sum = 0.0;
     for (int64_t i = r0 + lane; i < r1; i += WAVE) sum += x[i];
     const double mean = wave_sum(sum) / (double)(r1 - r0);
@@ -362,16 +387,12 @@ __global__ void __launch_bounds__(256) centre_kernel(const double *__restrict__ 
     }
 }
 
-// The sample-major copy Rt[i * NR + r] of the centred residuals (zero for
-// r >= nres) and the zero task sums of those padding residuals.
-__global__ void __launch_bounds__(256) transpose_kernel(const double *__restrict__ Rc, int64_t n, int T, int nres,
-                                                        int NR, double *__restrict__ Rt, double *__restrict__ rsum) {
+// The padding of the centred residuals: rows nres..NR-1, the SC_TS columns
+// past n of every row, and the task sums of the padding rows, all zero.
+__global__ void __launch_bounds__(256) pad_kernel(int64_t n, int64_t ldr, int T, int nres, int NR,
+                                                  double *__restrict__ Rc, double *__restrict__ rsum) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < n * NR) {
-        const int64_t i = e / NR;
-        const int r = (int)(e % NR);
-        Rt[e] = r < nres ? Rc[(int64_t)r * n + i] : 0.0;
-    }
+    if (e < NR * ldr && (e / ldr >= nres || e % ldr >= n)) Rc[e] = 0.0;
     if (e < (int64_t)T * NR && (int)(e % NR) >= nres) rsum[e] = 0.0;
 }
 
@@ -452,25 +473,52 @@ __global__ void __launch_bounds__(1024) topm_hist_kernel(const double *__restric
         if (h[b]) atomicAdd(&hist[b], h[b]);
 }
 
-// One workgroup: clear the state (level 0) or pick the level's digit.
-__global__ void topm_digit_kernel(unsigned int *__restrict__ hist, int L, int64_t m, TopmState *__restrict__ st) {
-    if (threadIdx.x != 0) return;
-    if (L == 0) {
-        int64_t tot = 0;
-        for (int b = 0; b < TM_BINS; ++b) tot += hist[b];
-        st->finite = tot;
-        st->need = m < tot ? m : tot;
+// One workgroup of TM_THREADS: the level's digit is the bin b with
+// I[b] >= need > I[b + 1], I[b] = sum of hist[b'] over b' >= b (inclusive
+// suffix count; I[TM_BINS] = 0): the bin that holds the need-th largest
+// matching key.  Level 0 first sets need = min(m, number of finite scores).
+// Each thread sums 4 consecutive bins; the suffix sums of those partial
+// sums are a Hillis-Steele scan in LDS.
+constexpr int TM_THREADS = TM_BINS / 4;
+__global__ void __launch_bounds__(TM_THREADS) topm_digit_kernel(const unsigned int *__restrict__ hist, int L,
+                                                                int64_t m, TopmState *__restrict__ st) {
+    __shared__ int64_t part[2][TM_THREADS];
+    const int t = threadIdx.x;
+    int64_t h[4], own = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        h[q] = hist[4 * t + q];
+        own += h[q];
     }
-    int64_t need = st->need, acc = 0;
-    int b = TM_BINS - 1;
-    if (need > 0) {
-        for (; b > 0; --b) {
-            if (acc + (int64_t)hist[b] >= need) break;
-            acc += hist[b];
+    // suffix scan: part[.][t] = sum of own over threads >= t
+    int cur = 0;
+    part[0][t] = own;
+    __syncthreads();
+    for (int d = 1; d < TM_THREADS; d <<= 1) {
+        const int64_t v = part[cur][t] + (t + d < TM_THREADS ? part[cur][t + d] : 0);
+        part[cur ^ 1][t] = v;
+        cur ^= 1;
+        __syncthreads();
+    }
+    const int64_t total = part[cur][0];
+    const int64_t above = part[cur][t] - own;  // I[4 t + 4]
+    const int64_t need = L == 0 ? (m < total ? m : total) : st->need;
+    __syncthreads();
+    int64_t I = above;
+#pragma unroll
+    for (int q = 3; q >= 0; --q) {
+        const int64_t below = I;  // I[4 t + q + 1]
+        I += h[q];                // I[4 t + q]
+        const int b = 4 * t + q;
+        // need <= 0 (nothing left to place) keeps the top bin, as in a
+        // serial scan from the top that stops at once
+        const bool pick = need > 0 ? (I >= need && below < need) || (b == 0 && I < need) : b == TM_BINS - 1;
+        if (pick) {
+            st->digit[L] = (uint32_t)b;
+            st->need = need - (need > 0 ? below : 0);
+            if (L == 0) st->finite = total;
         }
     }
-    st->digit[L] = (uint32_t)b;
-    st->need = need - acc;
 }
 
 __global__ void topm_init_kernel(TopmState *__restrict__ st, unsigned int *__restrict__ hist) {
@@ -516,29 +564,26 @@ __global__ void __launch_bounds__(1024) topm_compact_kernel(const double *__rest
     }
 }
 
-// Rank of each candidate = candidates with a larger (score, -index) key.
+// Rank of each candidate = candidates with a larger (score, -index) key;
+// one wave per candidate, its lanes striding over the others.
 __global__ void __launch_bounds__(256) topm_rank_kernel(const double *__restrict__ csc,
                                                         const int64_t *__restrict__ cidx,
                                                         const TopmState *__restrict__ st, int64_t cap,
                                                         int64_t *__restrict__ out_idx, double *__restrict__ out_sc) {
-    __shared__ double ts[256];
-    __shared__ int64_t ti[256];
+    const int lane = threadIdx.x & (WAVE - 1);
     const int64_t cnt = (int64_t)st->count < cap ? (int64_t)st->count : cap;
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const double s = e < cnt ? csc[e] : 0.0;
-    const int64_t ix = e < cnt ? cidx[e] : 0;
+    const int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    if (e >= cnt) return;
+    const double s = csc[e];
+    const int64_t ix = cidx[e];
     int64_t rank = 0;
-    for (int64_t b0 = 0; b0 < cnt; b0 += 256) {
-        __syncthreads();
-        if (b0 + threadIdx.x < cnt) {
-            ts[threadIdx.x] = csc[b0 + threadIdx.x];
-            ti[threadIdx.x] = cidx[b0 + threadIdx.x];
-        }
-        __syncthreads();
-        const int lim = cnt - b0 < 256 ? (int)(cnt - b0) : 256;
-        for (int j = 0; j < lim; ++j) rank += (ts[j] > s || (ts[j] == s && ti[j] < ix)) ? 1 : 0;
+    for (int64_t j = lane; j < cnt; j += WAVE) {
+        const double sj = csc[j];
+        rank += (sj > s || (sj == s && cidx[j] < ix)) ? 1 : 0;
     }
-    if (e < cnt) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) rank += __shfl_xor(rank, o, WAVE);
+    if (lane == 0) {
         out_idx[rank] = ix;
         if (out_sc) out_sc[rank] = s;
     }
@@ -576,8 +621,8 @@ template <int OP, int NR>
 static void launch_screen_nr(const ScoreArgs &a, hipStream_t st) {
     const int64_t groups = (a.P + WAVE - 1) / WAVE;
     hipLaunchKernelGGL((screen_kernel<OP, NR>), dim3(grid_for(groups, SC_WPB)), dim3(SC_WPB * WAVE), 0, st, a.X, a.n,
-                       a.Mc, a.pairs, a.P, a.off, a.T, a.Rt, a.Rsum, a.Ctot, a.nres, a.lower, a.upper, a.scores,
-                       a.valid);
+                       a.Mc, a.pairs, a.P, a.off, a.T, a.Rc, a.ldr, a.Rsum, a.Ctot, a.nres, a.lower, a.upper,
+                       a.scores, a.valid);
 }
 
 template <int OP>
@@ -636,17 +681,19 @@ int launch_fc(int op, const FcArgs &a, hipStream_t st) {
 }
 
 int launch_centre(const double *R, int64_t n, const int64_t *off, int T, int nres, double *Rc, double *ctask,
-                  double *ctot, double *Rt, double *rsum, hipStream_t st) {
+                  double *ctot, double *rsum, hipStream_t st) {
     const int NR = nr_pad(nres);
+    const int64_t ldr = residual_stride(n);
     const int64_t waves = (int64_t)nres * T;
     hipLaunchKernelGGL(centre_kernel, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, R, n, off, T, nres, NR, Rc,
-                       ctask, rsum);
+                       ldr, ctask, rsum);
     hipLaunchKernelGGL(ctot_kernel, dim3(1), dim3(64), 0, st, ctask, T, nres, ctot);
-    const int64_t e = std::max<int64_t>(n * NR, (int64_t)T * NR);
-    hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)((e + 255) / 256)), dim3(256), 0, st, Rc, n, T, nres, NR, Rt,
-                       rsum);
+    const int64_t e = NR * ldr > (int64_t)T * NR ? NR * ldr : (int64_t)T * NR;
+    hipLaunchKernelGGL(pad_kernel, dim3((unsigned)((e + 255) / 256)), dim3(256), 0, st, n, ldr, T, nres, NR, Rc, rsum);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
+
+int64_t residual_stride(int64_t n) { return n + SC_TS; }
 
 int residual_width(int nres) { return nr_pad(nres); }
 
@@ -676,10 +723,10 @@ int launch_topm(const double *sc, int64_t M, int m, int64_t *out_idx, double *ou
     for (int L = 0; L < TM_LEVELS; ++L) {
         if (L > 0) hipLaunchKernelGGL(topm_clear_kernel, dim3(1), dim3(1024), 0, st, hist);
         hipLaunchKernelGGL(topm_hist_kernel, dim3(grid), dim3(1024), 0, st, sc, M, L, state, hist);
-        hipLaunchKernelGGL(topm_digit_kernel, dim3(1), dim3(64), 0, st, hist, L, (int64_t)m, state);
+        hipLaunchKernelGGL(topm_digit_kernel, dim3(1), dim3(TM_THREADS), 0, st, hist, L, (int64_t)m, state);
     }
     hipLaunchKernelGGL(topm_compact_kernel, dim3(grid), dim3(1024), 0, st, sc, M, state, csc, cidx, (int64_t)m);
-    hipLaunchKernelGGL(topm_rank_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, csc, cidx, state,
+    hipLaunchKernelGGL(topm_rank_kernel, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, st, csc, cidx, state,
                        (int64_t)m, out_idx, out_sc);
     *count_dev = &state->count;
     return hipGetLastError() == hipSuccess ? 0 : -1;

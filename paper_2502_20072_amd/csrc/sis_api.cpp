@@ -26,7 +26,7 @@ bool offsets_ok(const int64_t *o, int T, int64_t n, int64_t min_rows) {
 }
 
 struct SisLayout {
-    size_t off, Rc, ctask, ctot, Rt, rsum, total;
+    size_t off, Rc, ctask, ctot, rsum, total;
 };
 
 SisLayout sis_layout(int64_t n, int T, int nres) {
@@ -38,11 +38,10 @@ SisLayout sis_layout(int64_t n, int T, int nres) {
         return at;
     };
     L.off = take((size_t)(T + 1) * sizeof(int64_t));
-    L.Rc = take((size_t)n * nres * sizeof(double));
+    L.Rc = take((size_t)sis::residual_stride(n) * sis::residual_width(nres) * sizeof(double));
     L.ctask = take((size_t)nres * T * sizeof(double));
     L.ctot = take((size_t)nres * sizeof(double));
     const int w = sis::residual_width(nres);
-    L.Rt = take((size_t)n * w * sizeof(double));
     L.rsum = take((size_t)T * w * sizeof(double));
     L.total = o;
     return L;
@@ -58,7 +57,7 @@ struct sisso_sis {
     int T, nres;
     hipStream_t stream;
     int64_t *off;
-    double *Rc, *ctask, *ctot, *Rt, *rsum;
+    double *Rc, *ctask, *ctot, *rsum;
     std::string err;
 };
 
@@ -98,11 +97,10 @@ extern "C" int32_t sisso_sis_create(const sisso_sis_desc *d, sisso_sis **out) {
     h->Rc = (double *)(b + L.Rc);
     h->ctask = (double *)(b + L.ctask);
     h->ctot = (double *)(b + L.ctot);
-    h->Rt = (double *)(b + L.Rt);
     h->rsum = (double *)(b + L.rsum);
     if (hipMemcpyAsync(h->off, d->task_offsets, (size_t)(d->T + 1) * sizeof(int64_t), hipMemcpyHostToDevice,
                        h->stream) != hipSuccess ||
-        sis::launch_centre(d->R, h->n, h->off, h->T, h->nres, h->Rc, h->ctask, h->ctot, h->Rt, h->rsum,
+        sis::launch_centre(d->R, h->n, h->off, h->T, h->nres, h->Rc, h->ctask, h->ctot, h->rsum,
                            h->stream) != 0 ||
         hipStreamSynchronize(h->stream) != hipSuccess) {
         delete h;
@@ -126,7 +124,8 @@ static sis::ScoreArgs score_args(sisso_sis *h, const double *X, int64_t Mc, cons
     a.P = P;
     a.off = h->off;
     a.T = h->T;
-    a.Rt = h->Rt;
+    a.Rc = h->Rc;
+    a.ldr = sis::residual_stride(h->n);
     a.Rsum = h->rsum;
     a.Ctot = h->ctot;
     a.nres = h->nres;
