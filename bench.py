@@ -266,17 +266,22 @@ def bench_exhaustive(args, p, name: str, prec: int, steps: int, warmup: int, sea
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms_step = dt / steps * 1e3
-    # correctness of the last timed step's output against the stored oracle result
-    if p.T == 1:
+    # correctness of the last timed step's output against the stored oracle
+    # result: over every tuple where one exists, else over the tuples whose
+    # first index is below a (that rank range searched again and compared)
+    if p.T == 1 and os.path.exists(os.path.join(ROOT, "tests", "golden", f"oracle_topk_{name}.json")):
         matches, note = golden_check(p, name, out[0], out[1])
     else:
-        # several tasks: the stored oracle result covers the tuples whose first
-        # index is 0 or 1; search that rank range and compare
-        r1 = ntup - math.comb(p.S - 2, D)
+        a = 2
+        for cand in (100, 2, 1):
+            if os.path.exists(os.path.join(ROOT, "tests", "golden", f"oracle_topk_{name}_i1_0_{cand}.json")):
+                a = cand
+                break
+        r1 = ntup - math.comb(p.S - a, D)
         s.search_range(D, k, 0, r1)
         ri, rs, _ = s.topk(k)
-        matches, note = golden_check(p, name, ri, rs, (0, 2))
-        note += f" (rank range [0, {r1}) = first index in [0, 2))"
+        matches, note = golden_check(p, name, ri, rs, (0, a))
+        note += f" (rank range [0, {r1}) = first index in [0, {a}))"
 
     # per-phase times with HIP events on the library's stream (separate pass,
     # same launches), averaged over the same number of steps

@@ -110,7 +110,8 @@ typedef struct {
  * shape (pure function of n_total, S, T, D_max, k_max and precision; reads
  * no pointer).  With several tasks and D_max >= 3 it includes the filter
  * task's matrix (S^2 doubles) and the D = 3 step queue (24 bytes per sweep
- * step, at most 1 GiB).  Returns 0 if the shape is invalid. */
+ * step, at most 8 GiB: about 2 GB at S = 5000).  Returns 0 if the shape is
+ * invalid. */
 size_t sisso_l0_workspace_bytes(const sisso_l0_desc *desc);
 
 /* Validate the descriptor and create a handle in *out.  Errors: EINVAL for

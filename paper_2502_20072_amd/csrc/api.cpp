@@ -154,13 +154,14 @@ static Layout compute_layout(int64_t n_total, int64_t S, int T, int D_max, int k
     L.G1_bytes = (D_max >= 3 && S >= 3 && T > 1) ? Sp * Sp * d : 0;
     L.G1 = take(L.G1_bytes);
     // several tasks, D = 3: a pool with a record for every step of the sweep
-    // plus one partly filled chunk per wave, so that it cannot run out; above
-    // 1 GiB of records the several-task search keeps its general kernel
+    // plus one partly filled chunk per wave, so that it cannot run out (the
+    // pool grows as S^3: 2 GB at S = 5000); above MTQ_POOL_MAX bytes of
+    // records the several-task search keeps its general kernel
     L.mtq_chunks = 0;
     if (L.G1_bytes) {
         const uint64_t steps = s3_tiles_host(S) * (uint64_t)s3_rows_per_tile();
         const uint64_t chunks = (steps + MTQ_CHUNK - 1) / MTQ_CHUNK + (uint64_t)nlists;
-        if (chunks * MTQ_CHUNK * 3 * sizeof(uint64_t) <= (1ull << 30)) L.mtq_chunks = (int)chunks;
+        if (chunks * MTQ_CHUNK * 3 * sizeof(uint64_t) <= MTQ_POOL_MAX) L.mtq_chunks = (int)chunks;
     }
     const size_t nch = (size_t)L.mtq_chunks;
     L.mtq = take(nch * MTQ_CHUNK * 3 * sizeof(uint64_t));

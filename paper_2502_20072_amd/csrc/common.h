@@ -163,6 +163,7 @@ __host__ __device__ inline void unpack_tuple(uint64_t k, int D, int32_t *t) {
 // 64 steps stays inside 32 KB of contiguous memory.
 constexpr int GT = 64;
 constexpr int MTQ_CHUNK = 256;  // queued sweep steps per pool chunk (several tasks, D = 3)
+constexpr unsigned long long MTQ_POOL_MAX = 8ull << 30;  // largest pool of queued steps (bytes)
 __host__ __device__ inline int64_t gidx(int64_t i, int64_t k, int64_t nt, int TP, int t) {
     return ((((i >> 6) * nt + (k >> 6)) << 12) + ((i & 63) << 6) + (k & 63)) * TP + t;
 }

@@ -2818,7 +2818,7 @@ __global__ __launch_bounds__(MERGE_THREADS) void merge_compact_kernel(Ctx c, int
 
 // merge_select: one workgroup selects the KP smallest (SSE, key) pairs of
 // the candidates with bitonic sorts in LDS, carrying a running top-KP across
-// chunks when there are many.
+// fills of the buffer when there are many.
 // Marks the later copy of every adjacent equal (SSE, key) pair as empty and
 // re-sorts (a prefix-list search can offer one tuple from several prefixes,
 // always with bitwise the same SSE, so copies are adjacent after a sort).
@@ -2838,9 +2838,11 @@ __device__ void drop_adjacent_duplicates(double *ks, uint64_t *kr, int N) {
     if (__syncthreads_or(nd)) bitonic_sort_lds(ks, kr, N);
 }
 
-__global__ __launch_bounds__(MERGE_THREADS) void merge_select_kernel(Ctx c, int KP, int L, int use_pre, int dedupe) {
+__global__ __launch_bounds__(MERGE_THREADS) void merge_select_kernel(Ctx c, int KP, int L, int use_pre, int dedupe,
+                                                                     int nlists, const uint32_t *nl_dev) {
     __shared__ double ks[MERGE_CAP];
     __shared__ uint64_t kr[MERGE_CAP];
+    __shared__ int fill;
     const int tid = threadIdx.x;
     const int64_t total = *c.merge_count;
     if (tid == 0) {
@@ -2849,31 +2851,72 @@ __global__ __launch_bounds__(MERGE_THREADS) void merge_select_kernel(Ctx c, int 
         c.stats[2] = (uint64_t)__double_as_longlong(th0);
         c.stats[3] = (uint64_t)__double_as_longlong(theta_load(c.theta_bits));
     }
-    for (int i = tid; i < MERGE_CAP; i += MERGE_THREADS) {
-        ks[i] = INF;
-        kr[i] = ~0ull;
+    auto clear_from = [&](int at) {
+        for (int i = at + tid; i < MERGE_CAP; i += MERGE_THREADS) {
+            ks[i] = INF;
+            kr[i] = ~0ull;
+        }
+    };
+    auto pow2_at_least = [&](int64_t need) {
+        int N = 2 * KP;
+        while (N < need) N <<= 1;
+        return N;
+    };
+    clear_from(0);
+    __syncthreads();
+    const int chunk = MERGE_CAP - KP;
+    // Many candidates: every list is sorted, so the KP-th smallest of the
+    // lists' first entries bounds the KP-th smallest candidate (those KP
+    // lists each hold an entry at or below it); only candidates at or below
+    // that cut can be selected.  Not with dedupe: there one tuple can head
+    // several lists, and KP first entries need not be KP tuples.
+    double cut = INF;
+    const int64_t nl = nl_dev ? (int64_t)min(*nl_dev, (uint32_t)nlists) : (int64_t)nlists;
+    if (!dedupe && total > chunk && nl >= KP) {
+        for (int64_t base = 0; base < nl; base += chunk) {
+            const int64_t here = nl - base < chunk ? nl - base : chunk;
+            const int N = pow2_at_least(KP + here);
+            for (int i = tid; i < N - KP; i += MERGE_THREADS) {
+                ks[KP + i] = i < here ? c.list_sse[(base + i) * KP] : INF;
+                kr[KP + i] = 0;
+            }
+            __syncthreads();
+            bitonic_sort_lds(ks, kr, N);
+        }
+        cut = ks[KP - 1];
+        __syncthreads();
+        clear_from(0);
+        if (tid == 0) fill = 0;
+        __syncthreads();
+    } else if (tid == 0) {
+        fill = 0;
     }
     __syncthreads();
-    const int64_t chunk = MERGE_CAP - KP;
-    for (int64_t base = 0; base < total || base == 0; base += chunk) {
-        const int64_t here = total - base < chunk ? (total - base > 0 ? total - base : 0) : chunk;
-        int N = 2 * KP;  // sort only as many slots as hold keys: the carried KP plus this chunk
-        while (N < KP + here) N <<= 1;
-        for (int i = tid; i < N - KP; i += MERGE_THREADS) {
-            const int64_t e = base + i;
-            if (i < here) {
-                ks[KP + i] = c.cand_sse[e];
-                kr[KP + i] = c.cand_rank[e];
-            } else {
-                ks[KP + i] = INF;
-                kr[KP + i] = ~0ull;
+    // the candidates at or below the cut are appended behind the KP kept in
+    // front; the buffer is sorted (the KP smallest kept) before it could
+    // overflow.  Append order does not matter: the sort is by (SSE, key).
+    auto sort_keep = [&]() {
+        const int N = pow2_at_least(KP + fill);
+        bitonic_sort_lds(ks, kr, N);
+        if (dedupe) drop_adjacent_duplicates(ks, kr, N);
+        clear_from(KP);
+        if (tid == 0) fill = 0;
+        __syncthreads();
+    };
+    for (int64_t e = 0; e < total; e += MERGE_THREADS) {
+        if (fill > chunk - MERGE_THREADS) sort_keep();
+        const int64_t i = e + tid;
+        if (i < total) {
+            const double v = c.cand_sse[i];
+            if (v <= cut) {
+                const int at = atomicAdd(&fill, 1);
+                ks[KP + at] = v;
+                kr[KP + at] = c.cand_rank[i];
             }
         }
         __syncthreads();
-        bitonic_sort_lds(ks, kr, N);
-        if (dedupe) drop_adjacent_duplicates(ks, kr, N);
-        if (base + chunk >= total) break;
     }
+    sort_keep();
     for (int i = tid; i < KP; i += MERGE_THREADS) {
         c.merged_sse[i] = ks[i];
         c.merged_rank[i] = kr[i];
@@ -3230,7 +3273,8 @@ static void launch_merge(const Ctx &c, int nlists, int L, int use_pre, hipStream
     const int per = MERGE_THREADS / 64;
     hipLaunchKernelGGL(merge_compact_kernel, dim3((nlists + per - 1) / per), dim3(MERGE_THREADS), 0, st, c, nlists,
                        c.KP, L, use_pre, nl_dev);
-    hipLaunchKernelGGL(merge_select_kernel, dim3(1), dim3(MERGE_THREADS), 0, st, c, c.KP, L, use_pre, dedupe);
+    hipLaunchKernelGGL(merge_select_kernel, dim3(1), dim3(MERGE_THREADS), 0, st, c, c.KP, L, use_pre, dedupe, nlists,
+                       nl_dev);
 }
 
 // The one-task D = 3 record-table path applies (it also needs the table in

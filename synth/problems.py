@@ -224,6 +224,17 @@ CONFIGS: Dict[str, Dict] = {
                                    tasks=dict(T=16, lo=50, hi=5000)),
     "learned_s600_d4": dict(n=2000, S=600, D=4, k=100, seed=505,
                             beta=(1.5, -0.8, 0.6, -0.4), sigma=0.05, tasks=None),
+    # the shapes of the paper's two test cases (section "Test Cases"), with
+    # synthetic values: the thermal-conductivity case (two tasks of 78 rows,
+    # a 5000-feature subspace, D = 3) and the Kaggle band-gap subset (2400
+    # samples, a 50,000-feature subspace, D = 2; latent-factor columns, see
+    # make_factor_problem)
+    "paper_thermal_t2_s5000_d3": dict(n=None, S=5000, D=3, k=100, seed=909,
+                                      beta=(1.5, -0.8, 0.6), sigma=0.05,
+                                      tasks=dict(T=2, lo=78, hi=79)),
+    "paper_kaggle_s50000_d2": dict(n=2400, S=50000, D=2, k=100, seed=910,
+                                   beta=(1.5, -0.8), sigma=0.05, tasks=None,
+                                   generator="factor"),
 }
 
 
@@ -267,7 +278,40 @@ def make_config(name: str, seed: Optional[int] = None, **override) -> Problem:
     if seed is not None:
         cfg["seed"] = seed
     cfg.update(override)
+    if cfg.pop("generator", "trees") == "factor":
+        return make_factor_problem(name=name, **cfg)
     return make_problem(name=name, **cfg)
+
+
+def make_factor_problem(n: int, S: int, D: int, k: int, seed: int, beta: Sequence[float],
+                        sigma: float, tasks: Optional[Dict] = None, n_factors: int = 20,
+                        name: str = "custom") -> Problem:
+    """A large subspace of mutually correlated features, as a screening step
+    leaves it: column j = z a_j + e_j with z (n x n_factors) latent factors
+    ~ N(0, 1), loadings a_j ~ N(0, 1) and own noise e_j ~ N(0, 1), then
+    standardised.  The tree generator's duplicate filter compares every
+    candidate with every kept column (S^2 n operations), which is minutes at
+    S = 50,000; here no two columns are near-duplicates by construction (each
+    has its own unit-variance noise).  The target is planted on D columns
+    drawn without replacement, plus N(0, sigma^2) noise; one task."""
+    assert tasks is None
+    rng = np.random.Generator(np.random.PCG64(seed))
+    z = rng.standard_normal((n, n_factors))
+    F = np.empty((S, n), dtype=np.float64)
+    step = 4096
+    for j0 in range(0, S, step):
+        j1 = min(S, j0 + step)
+        a = rng.standard_normal((n_factors, j1 - j0))
+        F[j0:j1] = (z @ a + rng.standard_normal((n, j1 - j0))).T
+    F -= F.mean(axis=1, keepdims=True)
+    F /= F.std(axis=1, keepdims=True)
+    planted = sorted(int(i) for i in rng.choice(S, size=len(beta), replace=False))
+    y = np.asarray(beta, dtype=np.float64) @ F[planted] + sigma * rng.standard_normal(n)
+    offs = np.array([0, n], dtype=np.int64)
+    meta = dict(name=name, seed=seed, n=n, S=S, D=D, k=k, sigma=sigma, planted=planted,
+                coefs=[(0.0, list(beta))], draws=S, T=1, generator="factor", n_factors=n_factors)
+    return Problem(F=np.ascontiguousarray(F), y=y, task_offsets=offs, planted=planted, D=D, k=k,
+                   exprs=[f"f{j}" for j in range(S)], meta=meta)
 
 
 def make_batch_problem(i: int, seed0: int = 4100, D: int = 3, k: int = 100,

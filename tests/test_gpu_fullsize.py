@@ -74,6 +74,8 @@ def _check(name, rng=None, precision=None, tie_rel=1e-9):
 @pytest.mark.parametrize("name,rng", [
     ("multitask_t16_s1500_d3", (0, 2)),
     ("learned_s600_d4", (0, 1)),
+    ("paper_thermal_t2_s5000_d3", (0, 2)),
+    ("paper_kaggle_s50000_d2", (0, 100)),
     ("batch64_d3.63", None), ("batch64_d3.33", None), ("batch64_d3.18", None), ("batch64_d3.27", None),
     ("batch64_d3.14", (0, 2)), ("batch64_d3.57", (0, 2)), ("batch64_d3.60", (0, 2)), ("batch64_d3.9", (0, 2)),
 ])
@@ -99,6 +101,8 @@ def test_precision_workload_sliced_gram_full(form):
 @pytest.mark.parametrize("name,rng", [
     ("multitask_t16_s1500_d3", (0, 2)),
     ("learned_s600_d4", (0, 1)),
+    ("paper_thermal_t2_s5000_d3", (0, 2)),
+    ("paper_kaggle_s50000_d2", (0, 100)),
     ("batch64_d3.63", None), ("batch64_d3.14", (0, 2)),
 ])
 def test_fp32_solve_form_against_stored_oracle(name, rng):

@@ -50,3 +50,20 @@ def test_batch_problem_ranges():
 def test_tiny_problem():
     p = tiny_problem(3, S=6, n=17, T=3)
     assert p.F.shape == (6, 17) and p.T == 3 and p.task_offsets[-1] == 17
+
+
+def test_factor_generator_small():
+    """The latent-factor generator of the large-subspace shape: deterministic,
+    standardised, correlated but never duplicated columns, planted target."""
+    from synth.problems import make_factor_problem
+    kw = dict(n=300, S=700, D=2, k=10, seed=3, beta=(1.5, -0.8), sigma=0.0)
+    a, b = make_factor_problem(**kw), make_factor_problem(**kw)
+    assert np.array_equal(a.F, b.F) and np.array_equal(a.y, b.y) and a.planted == b.planted
+    assert a.F.shape == (700, 300) and a.F.flags.c_contiguous
+    assert np.allclose(a.F.mean(axis=1), 0.0, atol=1e-12)
+    assert np.allclose(a.F.std(axis=1), 1.0, atol=1e-12)
+    C = (a.F @ a.F.T) / a.n
+    np.fill_diagonal(C, 0.0)
+    assert 0.05 < np.median(np.abs(C)) and np.max(np.abs(C)) <= CORR_DUP
+    np.testing.assert_allclose(a.y, 1.5 * a.F[a.planted[0]] - 0.8 * a.F[a.planted[1]], atol=1e-12)
+    assert make_config("paper_kaggle_s50000_d2", S=700, n=300).F.shape == (700, 300)
