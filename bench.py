@@ -97,6 +97,30 @@ def measured_traffic(kernel: str, workload: str):
     return float(fields["bytes per launch"])
 
 
+# MFMA products per Gram K-step: FP64 one, the BF16 form's three slices six
+# (s + u <= 2), the FP16 form's two slices three
+GRAM_PRODUCTS = {"fp64": 1, "bf16": 6, "fp16": 3, "fp32": 1}
+MFMA_PEAK = {"fp64": 78.6e12, "bf16": 2.5e15, "fp16": 2.5e15, "fp32": 78.6e12}
+
+
+def gram_roofline(p, name: str, prec: int, gram_ms: float) -> dict:
+    """Roofline of the Gram phase: algorithmic FLOP n (S (S + 1) + 2 S) (the
+    correlation matrix and F^T y, every task's rows once) times the MFMA
+    products the form issues, over the phase time (the Gram launch and its
+    finishing pass), against the MFMA peak of the type it runs in."""
+    from paper_2502_20072_amd import _binding as B
+    form = {B.SISSO_PREC_FP64: "fp64", B.SISSO_PREC_BF16_COMP: "bf16", B.SISSO_PREC_FP16_COMP: "fp16",
+            B.SISSO_PREC_FP32_SOLVE: "fp32"}[prec]
+    alg = float(p.n) * (p.S * (p.S + 1) + 2 * p.S)
+    kern = "gram_lp_kernel" if form in ("bf16", "fp16") else "gram_kernel"
+    achieved = alg * GRAM_PRODUCTS[form] / (gram_ms * 1e-3)
+    return dict(bound="mfma", kernel=kern, achieved=achieved / 1e12, peak=MFMA_PEAK[form] / 1e12, unit="TFLOP/s",
+                frac=achieved / MFMA_PEAK[form], traffic=measured_traffic(kern, name), algorithmic_flop=alg,
+                mfma_products=GRAM_PRODUCTS[form], gram_ms=gram_ms,
+                note="phase time: the Gram launch and its finishing pass (the partial sums summed, "
+                     "scaled and tiled)")
+
+
 def cpu_baseline(p, D: int, k: int, target_s: float = 15.0):
     """The oracle on a bounded sample: all tuples whose first index is < a.
 
@@ -313,6 +337,11 @@ def bench_exhaustive(args, p, name: str, prec: int, steps: int, warmup: int, sea
         roofline["pruned"] = ("several tasks at D=3: the sweep solves every tuple in the task of largest "
                               "|y_t - mean|^2 only (an exact lower bound of the sum); the survivors' "
                               "all-task solves are not counted")
+    search_roofline = None
+    if acc["gram"] > acc["search"]:
+        # the Gram dominates the step: its roofline is the line's, the
+        # search's is kept beside it
+        search_roofline, roofline = roofline, gram_roofline(p, name, prec, acc["gram"])
     res = {
         "value": ntup * steps / dt,
         "unit": "tuples/s",
@@ -339,6 +368,8 @@ def bench_exhaustive(args, p, name: str, prec: int, steps: int, warmup: int, sea
         "phase_ms": acc,
         "roofline": roofline,
     }
+    if search_roofline is not None:
+        res["search_roofline"] = search_roofline
     if p.T > 1:
         res["tuple_task_solves_per_s"] = ntup * p.T * steps / dt
     if prec != B.SISSO_PREC_FP64:
