@@ -309,12 +309,36 @@ __global__ __launch_bounds__(256) void gram_finish_kernel(const double *__restri
     const int64_t pb = blockIdx.x / (GT / FIN_ROWS);
     const int t = (int)(pb / npair);
     int64_t pr = pb % npair;
-    int64_t ti = 0;
-    while (pr >= nt - ti) {
-        pr -= nt - ti;
-        ++ti;
+    int64_t ti = 0, tk = 0;
+    // tile pairs in groups of 8 tile rows, column by column: consecutive
+    // workgroups write tile (ti, tk) in 8 streams and its mirror (tk, ti)
+    // in one, instead of a mirror nt tiles further for every pair (at
+    // S = 50,000 the finishing pass took 28.7 ms in row-by-row order, 13 ms
+    // in this one)
+    {
+        int64_t r0 = 0;
+        for (;;) {
+            const int64_t g = nt - r0 < 8 ? nt - r0 : 8;
+            const int64_t cnt = g * (g + 1) / 2 + g * (nt - r0 - g);
+            if (pr < cnt) {
+                const int64_t tri = g * (g + 1) / 2;
+                if (pr < tri) {
+                    int64_t k = 0;
+                    while ((k + 1) * (k + 2) / 2 <= pr) ++k;
+                    tk = r0 + k;
+                    ti = r0 + (pr - k * (k + 1) / 2);
+                } else {
+                    const int64_t q = pr - tri;
+                    tk = r0 + g + q / g;
+                    ti = r0 + q % g;
+                }
+                break;
+            }
+            pr -= cnt;
+            r0 += g;
+        }
     }
-    const int64_t tk = ti + pr;
+
     const double *ist = inv_s + (int64_t)t * S;
     const bool one = G1 != nullptr && t == *tstar;  // also write the one-task copy
     // each thread owns PER elements of rows [FIN_ROWS qr, FIN_ROWS (qr + 1));
