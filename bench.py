@@ -492,6 +492,7 @@ def bench_learned(args, p) -> int:
     propose_two_stage(s, D, k, r2_scorer, budget_frac=args.budget)
     rec_two_r2 = recall(s.topk()[0], ei)
     s.close()
+    decoy = decoy_comparison(args.budget) if D == 4 else None
     ntup = math.comb(p.S, D)
     res = {
         "metric": f"l0 tuples/sec at D={D} (learned proposal, exact FP64 evaluation; recall@{k} vs exhaustive)",
@@ -507,6 +508,8 @@ def bench_learned(args, p) -> int:
         "train": {"prefixes": int(X.shape[0]), "seconds": train_s, "loss_first_epoch": hist[0],
                   "loss_last_epoch": hist[-1]},
     }
+    if decoy is not None:
+        res["decoy_subspaces"] = decoy
     print(json.dumps(res), flush=True)
     return 0
 
@@ -713,6 +716,38 @@ def bench_screen(args) -> int:
         res["cpu_baseline"] = screen_cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(res), flush=True)
     return 0
+
+
+def decoy_comparison(budget: float) -> dict:
+    """The network against the R^2 feature alone where they differ: eight
+    decoy subspaces (make_decoy_problem, n = 2000, S = 600, D = 4, k = 100,
+    seeds 7500-7507; the network trained on 60 + 20 smaller decoy problems),
+    two-stage proposal at the same budget, recall@100 against exhaustive."""
+    import numpy as np
+    import torch
+
+    from synth import make_decoy_problem
+    from paper_2502_20072_amd import L0Search
+    from paper_2502_20072_amd.learned import ProposalNet, training_set, propose_two_stage, r2_scorer, recall
+
+    X2, Y2 = training_set([make_decoy_problem(500, 200, 7000 + i) for i in range(60)], 2)
+    X3, Y3 = training_set([make_decoy_problem(500, 60, 7100 + i) for i in range(20)], 3)
+    net = ProposalNet(seed=0)
+    net.fit(torch.cat([X2, X3]), torch.cat([Y2, Y3]), epochs=6, batch=8192, lr=2e-3)
+    rec = {"net": [], "r2": []}
+    for seed in range(7500, 7508):
+        p = make_decoy_problem(2000, 600, seed)
+        s = L0Search(p.F, p.y, p.task_offsets, D_max=4, k_max=100, device="cuda:0")
+        s.gram().search(4, 100)
+        ei, _, _ = s.topk()
+        for name, sc in (("net", net.predict), ("r2", r2_scorer)):
+            propose_two_stage(s, 4, 100, sc, budget_frac=budget)
+            rec[name].append(recall(s.topk()[0], ei))
+        s.close()
+    return {"instances": 8, "budget": budget, "two_stage": True,
+            "recall_at_100_net": {"mean": float(np.mean(rec["net"])), "min": float(np.min(rec["net"]))},
+            "recall_at_100_r2_only": {"mean": float(np.mean(rec["r2"])), "min": float(np.min(rec["r2"]))},
+            "per_instance": rec}
 
 
 if __name__ == "__main__":

@@ -12,6 +12,7 @@ from .problems import (  # noqa: F401
     make_problem,
     make_config,
     make_batch_problem,
+    make_decoy_problem,
     make_batch_problems,
     tiny_problem,
     integer_problem,

@@ -314,6 +314,36 @@ def make_factor_problem(n: int, S: int, D: int, k: int, seed: int, beta: Sequenc
                    exprs=[f"f{j}" for j in range(S)], meta=meta)
 
 
+def make_decoy_problem(n: int, S: int, seed: int, D: int = 4, k: int = 100, r_decoy: float = 0.7,
+                       frac_decoy: float = 1 / 6, sigma: float = 0.05) -> Problem:
+    """A subspace in which many features are noisy proxies of the target.
+
+    The target is the sum of D mutually independent N(0, 1) features plus
+    N(0, sigma^2) noise, so each of them correlates with it at about
+    1 / sqrt(D); a fraction frac_decoy of the other features are decoys, the
+    standardised target plus independent noise scaled so that each
+    correlates with it at r_decoy (and, through the target, with each
+    other); the rest are independent N(0, 1).  A screening step that ranks
+    features one by one keeps such decoys, and pairs of decoys fit the
+    target better than pairs of the D features, although the D features
+    together fit it almost exactly.  Columns standardised; one task."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    X = rng.standard_normal((S, n))
+    planted = sorted(int(i) for i in rng.choice(S, size=D, replace=False))
+    y = X[planted].sum(axis=0) + sigma * rng.standard_normal(n)
+    ys = (y - y.mean()) / y.std()
+    rest = np.array([j for j in range(S) if j not in planted])
+    decoys = rng.choice(rest, size=int(S * frac_decoy), replace=False)
+    eta = math.sqrt(1.0 / (r_decoy * r_decoy) - 1.0)
+    for j in decoys:
+        X[j] = ys + eta * rng.standard_normal(n)
+    X = (X - X.mean(axis=1, keepdims=True)) / X.std(axis=1, keepdims=True)
+    meta = dict(name="decoy", seed=seed, n=n, S=S, D=D, k=k, sigma=sigma, planted=planted, r_decoy=r_decoy,
+                frac_decoy=frac_decoy, decoys=sorted(int(j) for j in decoys), T=1)
+    return Problem(F=np.ascontiguousarray(X), y=y, task_offsets=np.array([0, n], dtype=np.int64),
+                   planted=planted, D=D, k=k, exprs=[f"d{j}" for j in range(S)], meta=meta)
+
+
 def make_batch_problem(i: int, seed0: int = 4100, D: int = 3, k: int = 100,
                        S_range=(200, 2000), n_range=(100, 5000), sigma: float = 0.05) -> Problem:
     """Problem i of the batch of independent single-task searches (seed seed0 + i)."""

@@ -67,3 +67,20 @@ def test_factor_generator_small():
     assert 0.05 < np.median(np.abs(C)) and np.max(np.abs(C)) <= CORR_DUP
     np.testing.assert_allclose(a.y, 1.5 * a.F[a.planted[0]] - 0.8 * a.F[a.planted[1]], atol=1e-12)
     assert make_config("paper_kaggle_s50000_d2", S=700, n=300).F.shape == (700, 300)
+
+
+def test_decoy_generator():
+    """Decoy subspaces: deterministic, standardised, the planted features
+    correlate with the target at about 1/sqrt(D), the decoys at r_decoy,
+    and the planted tuple fits the target almost exactly."""
+    from synth import make_decoy_problem
+    a, b = make_decoy_problem(800, 120, 5), make_decoy_problem(800, 120, 5)
+    assert np.array_equal(a.F, b.F) and np.array_equal(a.y, b.y) and a.planted == b.planted
+    assert np.allclose(a.F.mean(axis=1), 0.0, atol=1e-12) and np.allclose(a.F.std(axis=1), 1.0, atol=1e-12)
+    yc = (a.y - a.y.mean()) / a.y.std()
+    r = a.F @ yc / a.n
+    assert np.all(np.abs(r[a.planted] - 0.5) < 0.1)
+    assert len(a.meta["decoys"]) == 20 and abs(np.mean(r[a.meta["decoys"]]) - 0.7) < 0.05
+    A = np.column_stack([np.ones(a.n), a.F[a.planted].T])
+    res = a.y - A @ np.linalg.lstsq(A, a.y, rcond=None)[0]
+    assert res @ res < 1e-2 * ((a.y - a.y.mean()) @ (a.y - a.y.mean()))
