@@ -425,3 +425,33 @@ def test_d4_constant_and_collinear_columns_never_returned():
         assert 5 not in t and not (2 in t and 9 in t)
     oidx, osse, _ = oracle.topk(p.F, p.y, 4, 25, p.task_offsets)
     compare_topk(p, 4, 25, gidx, gsse, oidx, osse)
+
+
+@pytest.mark.parametrize("grid", [16, 1024])
+def test_full_lists_merge_vs_oracle(grid):
+    """A target of pure noise (no tuple stands out) searched over the tuples
+    whose first index is below 100 (a rank range, 6.1M tuples, S = 400,
+    D = 3, k = 100): the lists fill, so the merge receives more candidates
+    (about 3,600) than its selection buffer holds (1,920).  With
+    1024 workgroups (4096 lists) the selection first cuts at the KP-th
+    smallest of the lists' first entries; with 16 workgroups (64 lists,
+    fewer than KP) it sorts every candidate.  Both return the oracle's
+    top-k of the range."""
+    from paper_2502_20072_amd import L0Search
+    from paper_2502_20072_amd import _binding as B
+    from synth.problems import Problem
+    p = tiny_problem(91, S=400, n=40, T=1, D=3, sigma=0.3)
+    y = np.random.default_rng(92).standard_normal(p.n)
+    p = Problem(F=p.F, y=y, task_offsets=p.task_offsets, planted=[], D=3, k=100, exprs=p.exprs, meta={})
+    r1 = math.comb(p.S, 3) - math.comb(p.S - 100, 3)
+    _say(f"full lists S={p.S} n={p.n} ranks [0, {r1}) grid={grid}")
+    s = L0Search(p.F, p.y, p.task_offsets, D_max=3, k_max=100)
+    s.gram()
+    s.set_search_grid(grid)
+    s.search_range(3, 100, 0, r1)
+    gidx, gsse, gcoef = s.topk()
+    st = B.sisso_l0_search_stats(s.handle)
+    s.close()
+    _say(f"candidates offered {st['candidates']}")
+    oidx, osse, _ = oracle.topk(p.F, p.y, 3, 100, p.task_offsets, i1_range=(0, 100))
+    compare_topk(p, 3, 100, gidx, gsse, oidx, osse, gcoef=gcoef)
