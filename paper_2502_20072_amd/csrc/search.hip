@@ -1991,11 +1991,15 @@ __global__ void s4_init_kernel(Ctx c) {
 // zs = z_j / s_j = e / d_j and z_j^2 = e^2 / d_j with e = b_j - v0 z0 - v1 z1,
 // so a record takes one division and no root.
 __global__ __launch_bounds__(256) void rec4_kernel(Ctx c, double *__restrict__ rec, int64_t nrec) {
+    // the workgroup's records are staged in LDS and written out as
+    // consecutive doubles (full cache lines), not as S4_RECW strided stores
+    __shared__ double stage[256 * S4_RECW];
     const int64_t S = c.S;
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= nrec) return;
-    const int r = (int)(e & (S4_NR - 1));
-    const int64_t row = e / S4_NR;
+    const int64_t e0 = (int64_t)blockIdx.x * blockDim.x;
+    const int64_t e = e0 + threadIdx.x;
+    const int64_t ecl = e < nrec ? e : nrec - 1;  // a thread past the end computes the last record, unwritten
+    const int r = (int)(ecl & (S4_NR - 1));
+    const int64_t row = ecl / S4_NR;
     // i2: the largest index in [1, S - 3] whose rows start at or before row
     int64_t lo = 1, hi = S - 3;
     while (lo < hi) {
@@ -2032,12 +2036,16 @@ __global__ __launch_bounds__(256) void rec4_kernel(Ctx c, double *__restrict__ r
             }
         }
     }
-    double *o = rec + e * S4_RECW;
+    double *o = stage + threadIdx.x * S4_RECW;
     o[0] = v0;
     o[1] = v1;
     o[2] = al;
     o[3] = zs;
     o[4] = p;
+    __syncthreads();
+    const int64_t nvals = (nrec - e0 < 256 ? nrec - e0 : 256) * S4_RECW;
+    double *out = rec + e0 * S4_RECW;
+    for (int64_t q = threadIdx.x; q < nvals; q += 256) out[q] = stage[q];
 }
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S4_WPE))) void search4_kernel(
