@@ -209,6 +209,9 @@ static void carve(sisso_l0 *h) {
     c.T = h->desc.T;
     c.TP = L.TP;
     c.Gnt = (c.S + GT - 1) / GT;
+    c.rows_max = 0;
+    for (int t = 0; t < c.T; ++t)
+        c.rows_max = std::max(c.rows_max, h->offsets[t + 1] - h->offsets[t]);
     c.off_dev = (int64_t *)(base + L.off_dev);
     c.torder = (int32_t *)(base + L.torder);
     c.ybar = (double *)(base + L.ybar);

@@ -15,18 +15,29 @@ namespace sl0 {
 
 // ---------------------------------------------------------------- a0: stats
 // One wavefront per (feature j or the target, task t).  Sums run over the
-// task's rows with a fixed lane-strided order and a fixed butterfly, so the
-// result does not depend on scheduling.
+// task's rows with a fixed lane-strided order (lane l adds rows r0 + l + 64 u
+// in increasing u) and a fixed butterfly, so the result does not depend on
+// scheduling.  Both sums are two-pass: the mean first, then the centred
+// moments.  With VPT > 0 (every task at most 64 VPT rows; VPT is the
+// smallest power of two from 2 to SX_VPT that covers the largest task) a
+// lane loads its rows, and the target's, once into registers with all loads
+// in flight together, and both passes run on the registers: one memory round
+// trip per column instead of one per few rows.  With VPT = 0 both passes
+// stream the column.  The order of the additions is the same in every form,
+// so their results agree bit for bit.
 __device__ inline double wave_sum(double v) {
     for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
     return v;
 }
+
+constexpr int SX_VPT = 32;  // most rows per lane held in registers (tasks of up to 2048 rows)
 
 // One workgroup: clears the status words, then wave w handles tasks w,
 // w + 4, ... (so no other workgroup can set a status bit before the clear).
 // Last, it names the filter tasks: the tasks of largest and second largest
 // c_t (the first such; -1 for the second when T = 1), whose SSEs bound any
 // tuple's SSE summed over tasks from below.
+template <int VPT>
 __global__ __launch_bounds__(256) void stats_y_kernel(const double *__restrict__ y,
                                                       const int64_t *__restrict__ off, int T,
                                                       double *__restrict__ ybar,
@@ -37,29 +48,53 @@ __global__ __launch_bounds__(256) void stats_y_kernel(const double *__restrict__
     if (threadIdx.x < 64) flags[threadIdx.x] = 0u;
     __syncthreads();
     for (int t = threadIdx.x >> 6; t < T; t += 4) {
-    const int64_t r0 = off[t], r1 = off[t + 1];
-    double s = 0.0;
-    bool bad = false;
-#pragma unroll 4
-    for (int64_t i = r0 + lane; i < r1; i += 64) {
-        double v = y[i];
-        bad |= !isfinite(v);
-        s += v;
-    }
-    s = wave_sum(s);
-    const double m = s / (double)(r1 - r0);
-    double ss = 0.0;
-#pragma unroll 4
-    for (int64_t i = r0 + lane; i < r1; i += 64) {
-        double d = y[i] - m;
-        ss += d * d;
-    }
-    ss = wave_sum(ss);
-    if (__any(bad) && lane == 0) atomicOr(&flags[FLAG_NONFINITE], 1u);
-    if (lane == 0) {
-        ybar[t] = m;
-        cyy[t] = ss;
-    }
+        const int64_t r0 = off[t], r1 = off[t + 1];
+        double s = 0.0, ss = 0.0, m;
+        bool bad = false;
+        if constexpr (VPT > 0) {
+            double v[VPT];
+#pragma unroll
+            for (int u = 0; u < VPT; ++u) {
+                const int64_t i = r0 + lane + 64 * u;
+                v[u] = i < r1 ? y[i] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < VPT; ++u) {
+                if (r0 + lane + 64 * u < r1) {
+                    bad |= !isfinite(v[u]);
+                    s += v[u];
+                }
+            }
+            s = wave_sum(s);
+            m = s / (double)(r1 - r0);
+#pragma unroll
+            for (int u = 0; u < VPT; ++u) {
+                if (r0 + lane + 64 * u < r1) {
+                    const double d = v[u] - m;
+                    ss += d * d;
+                }
+            }
+        } else {
+#pragma unroll 8
+            for (int64_t i = r0 + lane; i < r1; i += 64) {
+                const double v = y[i];
+                bad |= !isfinite(v);
+                s += v;
+            }
+            s = wave_sum(s);
+            m = s / (double)(r1 - r0);
+#pragma unroll 8
+            for (int64_t i = r0 + lane; i < r1; i += 64) {
+                const double d = y[i] - m;
+                ss += d * d;
+            }
+        }
+        ss = wave_sum(ss);
+        if (__any(bad) && lane == 0) atomicOr(&flags[FLAG_NONFINITE], 1u);
+        if (lane == 0) {
+            ybar[t] = m;
+            cyy[t] = ss;
+        }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -77,6 +112,7 @@ __global__ __launch_bounds__(256) void stats_y_kernel(const double *__restrict__
     }
 }
 
+template <int VPT>
 __global__ __launch_bounds__(256) void stats_x_kernel(const double *__restrict__ F,
                                                       const double *__restrict__ y,
                                                       const int64_t *__restrict__ off,
@@ -93,25 +129,52 @@ __global__ __launch_bounds__(256) void stats_x_kernel(const double *__restrict__
     const int t = (int)(job % T);
     const int64_t r0 = off[t], r1 = off[t + 1];
     const double *col = F + j * n_total;
-    double s = 0.0;
-    bool bad = false;
-#pragma unroll 4
-    for (int64_t i = r0 + lane; i < r1; i += 64) {
-        double v = col[i];
-        bad |= !isfinite(v);
-        s += v;
-    }
-    s = wave_sum(s);
-    const double m = s / (double)(r1 - r0);
     const double ym = ybar[t];
-    double ss = 0.0, sy = 0.0, sr = 0.0;
-#pragma unroll 4
-    for (int64_t i = r0 + lane; i < r1; i += 64) {
-        const double v = col[i];
-        const double d = v - m;
-        ss += d * d;
-        sy += d * (y[i] - ym);
-        sr += v * v;
+    double s = 0.0, ss = 0.0, sy = 0.0, sr = 0.0, m;
+    bool bad = false;
+    if constexpr (VPT > 0) {
+        double v[VPT], w[VPT];
+#pragma unroll
+        for (int u = 0; u < VPT; ++u) {
+            const int64_t i = r0 + lane + 64 * u;
+            v[u] = i < r1 ? col[i] : 0.0;
+            w[u] = i < r1 ? y[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < VPT; ++u) {
+            if (r0 + lane + 64 * u < r1) {
+                bad |= !isfinite(v[u]);
+                s += v[u];
+            }
+        }
+        s = wave_sum(s);
+        m = s / (double)(r1 - r0);
+#pragma unroll
+        for (int u = 0; u < VPT; ++u) {
+            if (r0 + lane + 64 * u < r1) {
+                const double d = v[u] - m;
+                ss += d * d;
+                sy += d * (w[u] - ym);
+                sr += v[u] * v[u];
+            }
+        }
+    } else {
+#pragma unroll 8
+        for (int64_t i = r0 + lane; i < r1; i += 64) {
+            const double v = col[i];
+            bad |= !isfinite(v);
+            s += v;
+        }
+        s = wave_sum(s);
+        m = s / (double)(r1 - r0);
+#pragma unroll 8
+        for (int64_t i = r0 + lane; i < r1; i += 64) {
+            const double v = col[i];
+            const double d = v - m;
+            ss += d * d;
+            sy += d * (y[i] - ym);
+            sr += v * v;
+        }
     }
     ss = wave_sum(ss);
     sy = wave_sum(sy);
@@ -470,11 +533,24 @@ int launch_untile(const Ctx &c, int t, double *dst, hipStream_t st) {
 // ------------------------------------------------------------- launchers
 int launch_stats(const Ctx &c, hipStream_t st) {
     phase_begin(c, SISSO_PHASE_STATS, st);
-    hipLaunchKernelGGL(stats_y_kernel, dim3(1), dim3(256), 0, st, c.y, c.off_dev, c.T, c.ybar, c.cyy, c.flags,
-                       c.tstar);
-    const int64_t jobs = c.S * c.T;
-    hipLaunchKernelGGL(stats_x_kernel, dim3((unsigned)((jobs + 3) / 4)), dim3(256), 0, st, c.F, c.y,
-                       c.off_dev, c.n_total, c.S, c.T, c.TP, c.ybar, c.mu, c.inv_s, c.bhat, c.flags);
+    const dim3 xg((unsigned)((c.S * c.T + 3) / 4));
+    int vpt = 2;
+    while (vpt <= SX_VPT && 64 * vpt < c.rows_max) vpt *= 2;
+    switch (vpt) {
+#define SX_LAUNCH(V)                                                                                            \
+    hipLaunchKernelGGL(stats_y_kernel<V>, dim3(1), dim3(256), 0, st, c.y, c.off_dev, c.T, c.ybar, c.cyy, c.flags, \
+                       c.tstar);                                                                                \
+    hipLaunchKernelGGL(stats_x_kernel<V>, xg, dim3(256), 0, st, c.F, c.y, c.off_dev, c.n_total, c.S, c.T, c.TP,  \
+                       c.ybar, c.mu, c.inv_s, c.bhat, c.flags);                                                 \
+    break;
+    case 2: SX_LAUNCH(2)
+    case 4: SX_LAUNCH(4)
+    case 8: SX_LAUNCH(8)
+    case 16: SX_LAUNCH(16)
+    case 32: SX_LAUNCH(32)
+    default: SX_LAUNCH(0)  // longer tasks: streamed
+#undef SX_LAUNCH
+    }
     phase_end(c, SISSO_PHASE_STATS, st);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }

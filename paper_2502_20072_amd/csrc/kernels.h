@@ -12,6 +12,7 @@ struct Ctx {
     int64_t n_total, S;
     int T, TP;
     int64_t Gnt;  // 64-wide tiles per row of the tiled correlation matrices
+    int64_t rows_max;  // rows of the largest task (chooses the statistics kernels' form)
     // carved from the workspace
     int64_t *off_dev;
     int32_t *torder;                 // tasks by decreasing row count (the Gram's launch order)
