@@ -2859,6 +2859,47 @@ __global__ __launch_bounds__(MERGE_THREADS) void merge_select_kernel(Ctx c, int 
         c.stats[2] = (uint64_t)__double_as_longlong(th0);
         c.stats[3] = (uint64_t)__double_as_longlong(theta_load(c.theta_bits));
     }
+    // Few candidates (the usual case once the pre-pass bound is tight): the
+    // KP smallest by rank counting, with no sort.  Without dedupe the keys are
+    // distinct, so the ranks (candidates ordered before each one) are too,
+    // and writing candidate x at position rank(x) < KP gives the sorted
+    // prefix the sorting path below returns (the candidates are finite:
+    // merge_compact appends only entries below INF); positions past the
+    // candidates are empty (INF, ~0) as there.
+    if (!dedupe && total <= MERGE_THREADS) {
+        const int n = (int)total;
+        if (tid < n) {
+            ks[tid] = c.cand_sse[tid];
+            kr[tid] = c.cand_rank[tid];
+        }
+        __syncthreads();
+        if (tid < n) {
+            const double v = ks[tid];
+            const uint64_t r = kr[tid];
+            // (SSE, key) order written without short-circuit evaluation, so
+            // that the eight steps' LDS reads are all in flight together
+            auto before = [&](int i) {
+                const double a = ks[i];
+                const uint64_t b = kr[i];
+                return (int)((a < v) | ((a == v) & (b < r)));
+            };
+            int rank = 0, i = 0;
+            for (; i + 8 <= n; i += 8) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) rank += before(i + u);
+            }
+            for (; i < n; ++i) rank += before(i);
+            if (rank < KP) {
+                c.merged_sse[rank] = v;
+                c.merged_rank[rank] = r;
+            }
+        }
+        for (int i = n + tid; i < KP; i += MERGE_THREADS) {
+            c.merged_sse[i] = INF;
+            c.merged_rank[i] = ~0ull;
+        }
+        return;
+    }
     auto clear_from = [&](int at) {
         for (int i = at + tid; i < MERGE_CAP; i += MERGE_THREADS) {
             ks[i] = INF;
