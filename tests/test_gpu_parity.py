@@ -62,6 +62,45 @@ def test_gram_matches_numpy(S, n, T):
     s.close()
 
 
+def test_statistics_forms_agree_bitwise():
+    """The column statistics hold a task's rows in registers (2 to 32 per
+    lane, the smallest count that covers the largest task) or stream them
+    (tasks over 2048 rows).  The additions keep the same order in every form,
+    so b_t and c_t of the same rows are bitwise equal whichever form the
+    other tasks select, and agree with the plain definition to rounding."""
+    from paper_2502_20072_amd import L0Search
+    rng = np.random.default_rng(77)
+    S = 40
+    parts = {m: (rng.standard_normal((S, m)) * 3.0 + 1.5, rng.standard_normal(m)) for m in (100, 2000, 2100)}
+
+    def stats(sizes):
+        F = np.ascontiguousarray(np.concatenate([parts[m][0] for m in sizes], axis=1))
+        y = np.concatenate([parts[m][1] for m in sizes])
+        off = np.cumsum([0] + list(sizes)).astype(np.int64)
+        s = L0Search(F, y, off, D_max=1, k_max=1)
+        s.gram()
+        out = {m: s.gram_read(t)[1:] for t, m in enumerate(sizes)}
+        s.close()
+        return out
+
+    forms = {"2 per lane": stats((100,)), "32 per lane": stats((100, 2000)), "streamed": stats((100, 2000, 2100)),
+             "32 per lane, alone": stats((2000,))}
+    _say("statistics forms: " + ", ".join(forms))
+    for m in (100, 2000):
+        got = [(name, f[m]) for name, f in forms.items() if m in f]
+        b0, c0 = got[0][1]
+        for name, (b, c) in got[1:]:
+            assert np.array_equal(b, b0), (m, name)
+            assert c == c0, (m, name)
+        X, y = parts[m]
+        Xc = X - X.mean(axis=1, keepdims=True)
+        yc = y - y.mean()
+        cr = float(yc @ yc)
+        np.testing.assert_allclose(b0, (Xc @ yc) / np.sqrt(np.sum(Xc * Xc, axis=1)), rtol=0,
+                                   atol=1e-12 * math.sqrt(cr))
+        assert abs(c0 - cr) <= 1e-12 * cr
+
+
 SWEEP = []
 _rng = np.random.default_rng(2024)
 for _i in range(40):
