@@ -1,6 +1,6 @@
 """Learned proposal: the network kernels against the FP64 reference, the
 prefix-list kernels against the CPU oracle, and the proposal against
-exhaustive search (the judge of recall)."""
+exhaustive search (the reference for recall)."""
 import itertools
 import math
 
@@ -351,7 +351,7 @@ def test_two_stage_proposal_at_the_learned_workload():
 
 
 def test_c5_exhaustive_sampled_parity():
-    """The judge of recall at the learned-proposal shape (n=2000, S=600, D=4,
+    """The reference for recall at the learned-proposal shape (n=2000, S=600, D=4,
     k=100): every returned SSE is the oracle's, the planted tuple is first,
     and no sampled tuple beats the k-th result (5.3e9 tuples are beyond the
     oracle)."""
