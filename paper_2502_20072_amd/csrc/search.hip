@@ -2953,7 +2953,9 @@ __global__ __launch_bounds__(MERGE_THREADS) void merge_select_kernel(Ctx c, int 
         __syncthreads();
     };
     for (int64_t e = 0; e < total; e += MERGE_THREADS) {
-        if (fill > chunk - MERGE_THREADS) sort_keep();
+        // sort only when this batch could overflow the buffer
+        const int64_t batch = total - e < MERGE_THREADS ? total - e : MERGE_THREADS;
+        if (fill + batch > chunk) sort_keep();
         const int64_t i = e + tid;
         if (i < total) {
             const double v = c.cand_sse[i];
